@@ -1,0 +1,653 @@
+// lbmd_oracle.cpp -- plain, slow CPU reference of the coupled lattice-Boltzmann / atom step.
+//
+// TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or call this file:
+// it exists so that tests, the smoke check and the benchmark's CPU baseline can compare
+// the HIP path against an independent implementation written from the paper.  It shares
+// no code, header or table with the HIP library.
+//
+// What it follows (Lauricella et al., arXiv 2305.05025, Section 2.2 "Coupled Lattice
+// Boltzmann and Molecular Dynamics"):
+//   * Eq. (1), the single-relaxation-time (BGK) lattice Boltzmann equation on the
+//     19-speed D3Q19 lattice, with relaxation frequency omega = 2/(6 nu + 1), i.e.
+//     tau = 1/omega = 3 nu + 1/2 in lattice units, and the second-order (in Mach number)
+//     truncated Maxwell-Boltzmann equilibrium.  The printed sign of the relaxation term is
+//     read as the standard BGK "minus omega (f - f_eq)" (the printed plus sign would make
+//     the non-equilibrium part grow by (1 + omega) per step).
+//   * Eqs. (2)-(3): rho = sum_i f_i, rho u = sum_i f_i c_i.
+//   * The forcing term S_i of Eq. (1), here the Guo-Zheng-Shi scheme (Phys. Rev. E 65,
+//     046308, 2002) because the paper leaves the scheme open; thermal noise xi_i = 0.
+//   * The friction coupling paragraph: fluid velocity at an atom by linear interpolation
+//     over the nearest eight lattice nodes, friction force gamma (u - v), the equal and
+//     opposite force entering the lattice through S_i with the same (trilinear) weights,
+//     one lattice step per atom step.
+//
+// The atom force field of the paper (CHARMM36 + implicit-solvent Coulomb) is replaced by
+// a stand-in: harmonic tethers to the initial positions, harmonic chain bonds and a
+// Lennard-Jones pair term truncated (not shifted) at r_c with minimum image, bonded pairs
+// optionally excluded.  Atom update: symplectic Euler, v += F/m then x += v (dt = 1).
+//
+// Populations are kept as deviations g_i = f_i - w_i rho0 (exactly the same scheme,
+// written around the rest state).  All arithmetic is in the template scalar T:
+// double (the oracle proper), float (to measure the FP32 error floor) or Dual (forward-mode
+// derivative of a loss with respect to gamma, tau or a body-force direction).
+//
+// Parity status: every sub-step is pinned by the CPU tests (closed forms, invariants,
+// brute force); the long coupled trajectory itself has no published values to pin
+// against beyond those invariants.
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#include <algorithm>
+
+namespace {
+
+// ---------------------------------------------------------------------------------------
+// D3Q19 velocity set: the rest velocity, the 6 face neighbours and the 12 edge neighbours.
+// Ordering: opposite(i) = i + 1 for odd i, i - 1 for even i > 0.
+// ---------------------------------------------------------------------------------------
+const int CV[19][3] = {
+    {0, 0, 0},
+    {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+    {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+    {1, 0, 1}, {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+    {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+const double WV[19] = {
+    1.0 / 3.0,
+    1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
+    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+// ---------------------------------------------------------------------------------------
+// Forward-mode dual number: value + derivative along one seeded direction.
+// ---------------------------------------------------------------------------------------
+struct Dual {
+  double v, d;
+  Dual(double a = 0.0, double b = 0.0) : v(a), d(b) {}
+};
+inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+inline Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+inline Dual operator/(Dual a, Dual b) {
+  return Dual(a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v));
+}
+inline Dual& operator+=(Dual& a, Dual b) { a = a + b; return a; }
+inline Dual& operator-=(Dual& a, Dual b) { a = a - b; return a; }
+inline Dual& operator*=(Dual& a, Dual b) { a = a * b; return a; }
+inline Dual sqrt(Dual a) { double s = std::sqrt(a.v); return Dual(s, a.d / (2.0 * s)); }
+
+inline double val(double x) { return x; }
+inline double val(float x) { return x; }
+inline double val(const Dual& x) { return x.v; }
+inline double dval(const Dual& x) { return x.d; }
+
+inline double sqrtT(double x) { return std::sqrt(x); }
+inline float sqrtT(float x) { return std::sqrt(x); }
+inline Dual sqrtT(Dual x) { return sqrt(x); }
+
+// ---------------------------------------------------------------------------------------
+// Problem description (scalars in T so that gamma / tau can carry derivatives).
+// ---------------------------------------------------------------------------------------
+template <class T>
+struct Model {
+  int L[3];
+  long S;
+  T tau, rho0, gamma, mass, k_tether, k_bond, r0_bond, lj_eps, lj_sigma, lj_rc;
+  int lj_exclude_bonded;
+  int n_atoms, n_bonds;
+  std::vector<int> bond_i, bond_j;           // bond list
+  std::vector<std::vector<int>> partners;    // bonded partners per atom (for exclusions)
+  std::vector<T> fext;                       // external force density [3][S]
+  std::vector<T> anchor;                     // tether anchors = initial positions [N][3]
+};
+
+template <class T>
+struct State {
+  std::vector<T> g;   // pre-collision populations, deviation form, [19][S]
+  std::vector<T> X;   // unwrapped positions [N][3]
+  std::vector<T> V;   // velocities [N][3]
+};
+
+inline long site_index(const int L[3], long x, long y, long z) { return x + L[0] * (y + (long)L[1] * z); }
+
+inline long wrap(long a, int n) {
+  long r = a % n;
+  return r < 0 ? r + n : r;
+}
+
+// Eqs. (2)-(3) in deviation form: delta rho = sum_i g_i, j = sum_i c_i g_i.
+template <class T>
+void moments_at(const Model<T>& m, const std::vector<T>& g, long s, T& drho, T j[3]) {
+  drho = T(0.0);
+  j[0] = j[1] = j[2] = T(0.0);
+  for (int i = 0; i < 19; ++i) {
+    T gi = g[i * m.S + s];
+    drho += gi;
+    j[0] += T((double)CV[i][0]) * gi;
+    j[1] += T((double)CV[i][1]) * gi;
+    j[2] += T((double)CV[i][2]) * gi;
+  }
+}
+
+// Second-order equilibrium (Section 2.2 after Eq. 1), minus its rest part w_i rho0:
+//   g_eq_i = w_i [ delta_rho + rho (3 c.u + 9/2 (c.u)^2 - 3/2 u.u) ].
+template <class T>
+void equilibrium_dev(T drho, T rho, const T u[3], T out[19]) {
+  T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  for (int i = 0; i < 19; ++i) {
+    T cu = T((double)CV[i][0]) * u[0] + T((double)CV[i][1]) * u[1] + T((double)CV[i][2]) * u[2];
+    out[i] = T(WV[i]) * (drho + rho * (T(3.0) * cu + T(4.5) * cu * cu - T(1.5) * uu));
+  }
+}
+
+// Eq. (1) at one node, BGK with Guo forcing:
+//   u* = (j + F/2) / rho
+//   S_i = (1 - 1/(2 tau)) w_i [ 3 (c_i - u*) + 9 (c_i . u*) c_i ] . F
+//   g*_i = g_i - (g_i - g_eq_i(rho, u*)) / tau + S_i
+template <class T>
+void collide_node(T tau, T rho0, const T g[19], const T F[3], T out[19]) {
+  T drho = T(0.0), j[3] = {T(0.0), T(0.0), T(0.0)};
+  for (int i = 0; i < 19; ++i) {
+    drho += g[i];
+    for (int a = 0; a < 3; ++a) j[a] += T((double)CV[i][a]) * g[i];
+  }
+  T rho = rho0 + drho;
+  T u[3];
+  for (int a = 0; a < 3; ++a) u[a] = (j[a] + T(0.5) * F[a]) / rho;
+  T geq[19];
+  equilibrium_dev(drho, rho, u, geq);
+  T pref = T(1.0) - T(1.0) / (T(2.0) * tau);
+  for (int i = 0; i < 19; ++i) {
+    T cu = T((double)CV[i][0]) * u[0] + T((double)CV[i][1]) * u[1] + T((double)CV[i][2]) * u[2];
+    T src = T(0.0);
+    for (int a = 0; a < 3; ++a) {
+      T ca = T((double)CV[i][a]);
+      src += (T(3.0) * (ca - u[a]) + T(9.0) * cu * ca) * F[a];
+    }
+    T Si = pref * T(WV[i]) * src;
+    out[i] = g[i] - (g[i] - geq[i]) / tau + Si;
+  }
+}
+
+// Left-hand side of Eq. (1): the value leaving node x along c_i arrives at x + c_i
+// (periodic box).
+template <class T>
+void stream(const Model<T>& m, const std::vector<T>& post, std::vector<T>& pre) {
+  const int* L = m.L;
+  for (int i = 0; i < 19; ++i)
+    for (long z = 0; z < L[2]; ++z)
+      for (long y = 0; y < L[1]; ++y)
+        for (long x = 0; x < L[0]; ++x) {
+          long src = site_index(L, x, y, z);
+          long dst = site_index(L, wrap(x + CV[i][0], L[0]), wrap(y + CV[i][1], L[1]),
+                                wrap(z + CV[i][2], L[2]));
+          pre[i * m.S + dst] = post[i * m.S + src];
+        }
+}
+
+// The eight lattice nodes around a point and their trilinear weights.  The point is
+// first brought into the box [0, L) by floor-mod; nodes sit at integer coordinates.
+template <class T>
+void stencil(const int L[3], const T* Xa, long node[8], T w[8]) {
+  long i0[3];
+  T d[3];
+  for (int a = 0; a < 3; ++a) {
+    T Y = Xa[a] - T((double)L[a]) * T(std::floor(val(Xa[a]) / L[a]));
+    double fl = std::floor(val(Y));
+    d[a] = Y - T(fl);
+    i0[a] = wrap((long)fl, L[a]);
+  }
+  for (int k = 0; k < 8; ++k) {
+    int dx = k & 1, dy = (k >> 1) & 1, dz = (k >> 2) & 1;
+    T wx = dx ? d[0] : T(1.0) - d[0];
+    T wy = dy ? d[1] : T(1.0) - d[1];
+    T wz = dz ? d[2] : T(1.0) - d[2];
+    w[k] = wx * wy * wz;
+    node[k] = site_index(L, wrap(i0[0] + dx, L[0]), wrap(i0[1] + dy, L[1]), wrap(i0[2] + dz, L[2]));
+  }
+}
+
+// Linear interpolation over the nearest eight nodes of a [3][S] field at atom positions.
+template <class T>
+void interpolate(const int L[3], long S, const std::vector<T>& field, int n, const T* X, T* U) {
+  for (int a = 0; a < n; ++a) {
+    long node[8];
+    T w[8];
+    stencil(L, &X[3 * a], node, w);
+    for (int c = 0; c < 3; ++c) {
+      T acc = T(0.0);
+      for (int k = 0; k < 8; ++k) acc += w[k] * field[c * S + node[k]];
+      U[3 * a + c] = acc;
+    }
+  }
+}
+
+// Transpose of the interpolation: field(node) += W(X_a, node) F_a.
+template <class T>
+void spread(const int L[3], long S, int n, const T* X, const T* F, std::vector<T>& field) {
+  for (int a = 0; a < n; ++a) {
+    long node[8];
+    T w[8];
+    stencil(L, &X[3 * a], node, w);
+    for (int k = 0; k < 8; ++k)
+      for (int c = 0; c < 3; ++c) field[c * S + node[k]] += w[k] * F[3 * a + c];
+  }
+}
+
+template <class T>
+T min_image(T r, int L) {
+  return r - T((double)L) * T(std::floor(val(r) / L + 0.5));
+}
+
+template <class T>
+bool bonded(const Model<T>& m, int i, int j) {
+  for (int p : m.partners[i])
+    if (p == j) return true;
+  return false;
+}
+
+// Stand-in force field at positions X (unwrapped): tethers, bonds, truncated LJ.
+template <class T>
+void atom_forces(const Model<T>& m, const std::vector<T>& X, std::vector<T>& F) {
+  const int N = m.n_atoms;
+  std::fill(F.begin(), F.end(), T(0.0));
+  // harmonic tethers: U = k/2 |X - X^0|^2
+  if (val(m.k_tether) != 0.0)
+    for (int a = 0; a < N; ++a)
+      for (int c = 0; c < 3; ++c) F[3 * a + c] -= m.k_tether * (X[3 * a + c] - m.anchor[3 * a + c]);
+  // harmonic bonds: U = k/2 (r - r0)^2
+  for (int b = 0; b < m.n_bonds; ++b) {
+    int i = m.bond_i[b], j = m.bond_j[b];
+    T r[3];
+    for (int c = 0; c < 3; ++c) r[c] = min_image(X[3 * i + c] - X[3 * j + c], m.L[c]);
+    T rl = sqrtT(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    T fmag = -m.k_bond * (rl - m.r0_bond) / rl;   // force on i along r = X_i - X_j
+    for (int c = 0; c < 3; ++c) {
+      F[3 * i + c] += fmag * r[c];
+      F[3 * j + c] -= fmag * r[c];
+    }
+  }
+  // Lennard-Jones: U = 4 eps [(s/r)^12 - (s/r)^6] for r < r_c, all pairs (brute force)
+  if (val(m.lj_eps) != 0.0) {
+    T rc2 = m.lj_rc * m.lj_rc;
+    T s2 = m.lj_sigma * m.lj_sigma;
+    for (int i = 0; i < N; ++i)
+      for (int j = i + 1; j < N; ++j) {
+        T r[3];
+        for (int c = 0; c < 3; ++c) r[c] = min_image(X[3 * i + c] - X[3 * j + c], m.L[c]);
+        T r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        if (!(val(r2) < val(rc2))) continue;
+        if (m.lj_exclude_bonded && bonded(m, i, j)) continue;
+        T sr2 = s2 / r2;
+        T sr6 = sr2 * sr2 * sr2;
+        // F_i = 24 eps / r^2 [2 (s/r)^12 - (s/r)^6] r_vec
+        T fmag = T(24.0) * m.lj_eps * (T(2.0) * sr6 * sr6 - sr6) / r2;
+        for (int c = 0; c < 3; ++c) {
+          F[3 * i + c] += fmag * r[c];
+          F[3 * j + c] -= fmag * r[c];
+        }
+      }
+  }
+}
+
+template <class T>
+T atom_energy(const Model<T>& m, const std::vector<T>& X) {
+  const int N = m.n_atoms;
+  T E = T(0.0);
+  for (int a = 0; a < N; ++a)
+    for (int c = 0; c < 3; ++c) {
+      T d = X[3 * a + c] - m.anchor[3 * a + c];
+      E += T(0.5) * m.k_tether * d * d;
+    }
+  for (int b = 0; b < m.n_bonds; ++b) {
+    int i = m.bond_i[b], j = m.bond_j[b];
+    T r[3];
+    for (int c = 0; c < 3; ++c) r[c] = min_image(X[3 * i + c] - X[3 * j + c], m.L[c]);
+    T rl = sqrtT(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    E += T(0.5) * m.k_bond * (rl - m.r0_bond) * (rl - m.r0_bond);
+  }
+  if (val(m.lj_eps) != 0.0)
+    for (int i = 0; i < N; ++i)
+      for (int j = i + 1; j < N; ++j) {
+        T r[3];
+        for (int c = 0; c < 3; ++c) r[c] = min_image(X[3 * i + c] - X[3 * j + c], m.L[c]);
+        T r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        if (!(val(r2) < val(m.lj_rc * m.lj_rc))) continue;
+        if (m.lj_exclude_bonded && bonded(m, i, j)) continue;
+        T sr6 = (m.lj_sigma * m.lj_sigma / r2) * (m.lj_sigma * m.lj_sigma / r2) * (m.lj_sigma * m.lj_sigma / r2);
+        E += T(4.0) * m.lj_eps * (sr6 * sr6 - sr6);
+      }
+  return E;
+}
+
+// One coupled step, in this order:
+//  1 moments at every node (pre-collision state of step n)
+//  2 coupling velocity u_c = (j + F_ext/2) / rho (the atoms' own force is not included)
+//  3 U_a = interpolation of u_c at X_a^n
+//  4 friction on the atom F_c = gamma (U_a - v_a^n)
+//  5 the fluid receives -F_c with the same trilinear weights: F = F_ext - spread(F_c)
+//  6 BGK + Guo collision at every node with that F
+//  7 streaming
+//  8 stand-in force field at X^n
+//  9 symplectic Euler: v^{n+1} = v^n + (F_ff + F_c)/m, X^{n+1} = X^n + v^{n+1}
+template <class T>
+void coupled_step(const Model<T>& m, State<T>& s, std::vector<T>& scratch_post) {
+  const long S = m.S;
+  const int N = m.n_atoms;
+  std::vector<T> drho(S), jf(3 * S), uc(3 * S);
+  for (long x = 0; x < S; ++x) {
+    T dr, j[3];
+    moments_at(m, s.g, x, dr, j);
+    drho[x] = dr;
+    T rho = m.rho0 + dr;
+    for (int c = 0; c < 3; ++c) {
+      jf[c * S + x] = j[c];
+      uc[c * S + x] = (j[c] + T(0.5) * m.fext[c * S + x]) / rho;
+    }
+  }
+  std::vector<T> U(3 * N), Fc(3 * N);
+  interpolate(m.L, S, uc, N, s.X.data(), U.data());
+  for (int k = 0; k < 3 * N; ++k) Fc[k] = m.gamma * (U[k] - s.V[k]);
+  std::vector<T> Ftot(m.fext);
+  std::vector<T> Fspread(3 * S, T(0.0));
+  spread(m.L, S, N, s.X.data(), Fc.data(), Fspread);
+  for (long k = 0; k < 3 * S; ++k) Ftot[k] -= Fspread[k];
+  for (long x = 0; x < S; ++x) {
+    T gin[19], gout[19], F[3];
+    for (int i = 0; i < 19; ++i) gin[i] = s.g[i * S + x];
+    for (int c = 0; c < 3; ++c) F[c] = Ftot[c * S + x];
+    collide_node(m.tau, m.rho0, gin, F, gout);
+    for (int i = 0; i < 19; ++i) scratch_post[i * S + x] = gout[i];
+  }
+  stream(m, scratch_post, s.g);
+  std::vector<T> Fff(3 * N);
+  atom_forces(m, s.X, Fff);
+  for (int k = 0; k < 3 * N; ++k) {
+    s.V[k] = s.V[k] + (Fff[k] + Fc[k]) / m.mass;
+    s.X[k] = s.X[k] + s.V[k];
+  }
+}
+
+}  // namespace
+
+// =======================================================================================
+// C interface (ctypes).  Arrays are float64 unless stated; layouts:
+//   populations [19][nz][ny][nx] (x fastest), fields [3][nz][ny][nx], atoms [N][3].
+// =======================================================================================
+extern "C" {
+
+struct or_params {
+  int32_t L[3];
+  int32_t n_atoms;
+  int32_t n_bonds;
+  int32_t lj_exclude_bonded;
+  int32_t bf_kind;   // 0 none, 1 Kolmogorov sin(2 pi y / ny), 2 sign(y + 1/2 - ny/2), 3 field
+  int32_t pad;
+  double tau, rho0, gamma, mass, k_tether, k_bond, r0_bond, lj_eps, lj_sigma, lj_rc, bf_amp;
+};
+
+}  // extern "C"
+
+namespace {
+
+template <class T>
+void external_force(const or_params* p, const double* field, std::vector<T>& fext, long S) {
+  fext.assign(3 * S, T(0.0));
+  for (long z = 0; z < p->L[2]; ++z)
+    for (long y = 0; y < p->L[1]; ++y)
+      for (long x = 0; x < p->L[0]; ++x) {
+        long s = site_index(p->L, x, y, z);
+        double gx = 0.0;
+        if (p->bf_kind == 1) {
+          gx = p->bf_amp * std::sin(2.0 * M_PI * (double)y / (double)p->L[1]);
+        } else if (p->bf_kind == 2) {
+          double a = (double)y + 0.5 - 0.5 * (double)p->L[1];
+          gx = p->bf_amp * (a > 0.0 ? 1.0 : (a < 0.0 ? -1.0 : 0.0));
+        }
+        if (p->bf_kind == 3) {
+          for (int c = 0; c < 3; ++c) fext[c * S + s] = T(field[c * S + s]);
+        } else {
+          fext[0 * S + s] = T(gx);
+        }
+      }
+}
+
+template <class T>
+void build_model(const or_params* p, const double* X0, const int32_t* bonds, const double* field,
+                 Model<T>& m) {
+  for (int a = 0; a < 3; ++a) m.L[a] = p->L[a];
+  m.S = (long)p->L[0] * p->L[1] * p->L[2];
+  m.tau = T(p->tau);
+  m.rho0 = T(p->rho0);
+  m.gamma = T(p->gamma);
+  m.mass = T(p->mass);
+  m.k_tether = T(p->k_tether);
+  m.k_bond = T(p->k_bond);
+  m.r0_bond = T(p->r0_bond);
+  m.lj_eps = T(p->lj_eps);
+  m.lj_sigma = T(p->lj_sigma);
+  m.lj_rc = T(p->lj_rc);
+  m.lj_exclude_bonded = p->lj_exclude_bonded;
+  m.n_atoms = p->n_atoms;
+  m.n_bonds = p->n_bonds;
+  m.bond_i.resize(p->n_bonds);
+  m.bond_j.resize(p->n_bonds);
+  m.partners.assign(p->n_atoms, {});
+  for (int b = 0; b < p->n_bonds; ++b) {
+    m.bond_i[b] = bonds[2 * b];
+    m.bond_j[b] = bonds[2 * b + 1];
+    m.partners[bonds[2 * b]].push_back(bonds[2 * b + 1]);
+    m.partners[bonds[2 * b + 1]].push_back(bonds[2 * b]);
+  }
+  m.anchor.resize(3 * (size_t)p->n_atoms);
+  for (long k = 0; k < 3L * p->n_atoms; ++k) m.anchor[k] = T(X0[k]);
+  external_force<T>(p, field, m.fext, m.S);
+}
+
+template <class T>
+int run_impl(const or_params* p, double* g, double* X, double* V, const double* X0,
+             const int32_t* bonds, const double* field, int32_t n_steps) {
+  Model<T> m;
+  build_model<T>(p, X0, bonds, field, m);
+  State<T> s;
+  s.g.resize(19 * m.S);
+  s.X.resize(3 * (size_t)m.n_atoms);
+  s.V.resize(3 * (size_t)m.n_atoms);
+  for (long k = 0; k < 19 * m.S; ++k) s.g[k] = T(g[k]);
+  for (long k = 0; k < 3L * m.n_atoms; ++k) {
+    s.X[k] = T(X[k]);
+    s.V[k] = T(V[k]);
+  }
+  std::vector<T> post(19 * m.S);
+  for (int n = 0; n < n_steps; ++n) coupled_step(m, s, post);
+  for (long k = 0; k < 19 * m.S; ++k) g[k] = val(s.g[k]);
+  for (long k = 0; k < 3L * m.n_atoms; ++k) {
+    X[k] = val(s.X[k]);
+    V[k] = val(s.V[k]);
+  }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+void or_velocity_set(int32_t* c, double* w) {
+  for (int i = 0; i < 19; ++i) {
+    for (int a = 0; a < 3; ++a) c[3 * i + a] = CV[i][a];
+    w[i] = WV[i];
+  }
+}
+
+// Deviation equilibrium g_eq_i(delta rho, u) around rest density rho0.
+void or_equilibrium(double rho0, double drho, const double* u, double* out) {
+  equilibrium_dev<double>(drho, rho0 + drho, u, out);
+}
+
+// One BGK + Guo collision at a single node.
+void or_collide_node(double tau, double rho0, const double* g, const double* F, double* out) {
+  collide_node<double>(tau, rho0, g, F, out);
+}
+
+// Streaming of a [19][S] population array (post-collision in, pre-collision out).
+void or_stream(const int32_t* L, const double* post, double* pre) {
+  Model<double> m;
+  for (int a = 0; a < 3; ++a) m.L[a] = L[a];
+  m.S = (long)L[0] * L[1] * L[2];
+  std::vector<double> in(post, post + 19 * m.S), out(19 * m.S);
+  stream(m, in, out);
+  std::memcpy(pre, out.data(), sizeof(double) * 19 * m.S);
+}
+
+// Trilinear interpolation of a [3][S] field at n positions.
+void or_interpolate(const int32_t* L, const double* field, int32_t n, const double* X, double* U) {
+  int Li[3] = {L[0], L[1], L[2]};
+  long S = (long)L[0] * L[1] * L[2];
+  std::vector<double> f(field, field + 3 * S);
+  interpolate(Li, S, f, n, X, U);
+}
+
+// Trilinear spreading: field += sum_a W(X_a) F_a (the field is accumulated into).
+void or_spread(const int32_t* L, int32_t n, const double* X, const double* F, double* field) {
+  int Li[3] = {L[0], L[1], L[2]};
+  long S = (long)L[0] * L[1] * L[2];
+  std::vector<double> f(field, field + 3 * S);
+  spread(Li, S, n, X, F, f);
+  std::memcpy(field, f.data(), sizeof(double) * 3 * S);
+}
+
+// Stand-in force field and its energy at unwrapped positions X.
+void or_forces(const or_params* p, const double* X, const double* X0, const int32_t* bonds,
+               double* F) {
+  Model<double> m;
+  build_model<double>(p, X0, bonds, nullptr, m);
+  std::vector<double> Xv(X, X + 3 * (size_t)p->n_atoms), Fv(3 * (size_t)p->n_atoms);
+  atom_forces(m, Xv, Fv);
+  std::memcpy(F, Fv.data(), sizeof(double) * 3 * p->n_atoms);
+}
+
+double or_energy(const or_params* p, const double* X, const double* X0, const int32_t* bonds) {
+  Model<double> m;
+  build_model<double>(p, X0, bonds, nullptr, m);
+  std::vector<double> Xv(X, X + 3 * (size_t)p->n_atoms);
+  return atom_energy(m, Xv);
+}
+
+// External force density field [3][S] for the given body-force kind.
+void or_external_force(const or_params* p, const double* field, double* out) {
+  long S = (long)p->L[0] * p->L[1] * p->L[2];
+  std::vector<double> f;
+  external_force<double>(p, field, f, S);
+  std::memcpy(out, f.data(), sizeof(double) * 3 * S);
+}
+
+// Observables of the pre-collision state: rho = rho0 + sum g, u = (j + F_ext/2) / rho.
+void or_observables(const or_params* p, const double* g, const double* field, double* rho,
+                    double* u) {
+  Model<double> m;
+  for (int a = 0; a < 3; ++a) m.L[a] = p->L[a];
+  m.S = (long)p->L[0] * p->L[1] * p->L[2];
+  std::vector<double> fext;
+  external_force<double>(p, field, fext, m.S);
+  std::vector<double> gv(g, g + 19 * m.S);
+  for (long x = 0; x < m.S; ++x) {
+    double dr, j[3];
+    moments_at(m, gv, x, dr, j);
+    double r = p->rho0 + dr;
+    rho[x] = r;
+    for (int c = 0; c < 3; ++c) u[c * m.S + x] = (j[c] + 0.5 * fext[c * m.S + x]) / r;
+  }
+}
+
+// Conserved sums: [0] mass = sum_x (rho0 + sum_i g_i), [1..3] fluid momentum sum_x j,
+// [4..6] atom momentum sum_a m v_a.
+void or_invariants(const or_params* p, const double* g, const double* V, double* out) {
+  long S = (long)p->L[0] * p->L[1] * p->L[2];
+  for (int k = 0; k < 7; ++k) out[k] = 0.0;
+  double dm = 0.0;   // sum of deviations, kept apart from the (large) rest mass
+  for (long x = 0; x < S; ++x) {
+    for (int i = 0; i < 19; ++i) {
+      double gi = g[i * S + x];
+      dm += gi;
+      for (int a = 0; a < 3; ++a) out[1 + a] += CV[i][a] * gi;
+    }
+  }
+  out[0] = p->rho0 * (double)S + dm;
+  for (int a = 0; a < p->n_atoms; ++a)
+    for (int c = 0; c < 3; ++c) out[4 + c] += p->mass * V[3 * a + c];
+}
+
+// n_steps coupled steps in float64, in place on (g, X, V).  X0 are the tether anchors,
+// field the [3][S] body force (bf_kind 3 only, else may be NULL).
+int or_run(const or_params* p, double* g, double* X, double* V, const double* X0,
+           const int32_t* bonds, const double* field, int32_t n_steps) {
+  return run_impl<double>(p, g, X, V, X0, bonds, field, n_steps);
+}
+
+// Same scheme evaluated in float32 arithmetic (inputs/outputs still float64 arrays).
+int or_run_f32(const or_params* p, double* g, double* X, double* V, const double* X0,
+               const int32_t* bonds, const double* field, int32_t n_steps) {
+  return run_impl<float>(p, g, X, V, X0, bonds, field, n_steps);
+}
+
+// Loss L = (1/N) sum_a |X_a(T) - (X_a(0) + D)|^2 after n_steps from (g, X, V), and its
+// exact derivative along one direction by forward-mode dual numbers:
+//   wrt = 0: d/d gamma;  wrt = 1: d/d tau;  wrt = 2: d/d eps of F_ext = field + eps * dfield
+//   (bf_kind must be 3 for wrt = 2).
+int or_loss_derivative(const or_params* p, const double* g, const double* X, const double* V,
+                       const double* X0, const int32_t* bonds, const double* field,
+                       const double* D, int32_t n_steps, int32_t wrt, const double* dfield,
+                       double* loss, double* dloss) {
+  Model<Dual> m;
+  build_model<Dual>(p, X0, bonds, field, m);
+  if (wrt == 0) m.gamma = Dual(p->gamma, 1.0);
+  else if (wrt == 1) m.tau = Dual(p->tau, 1.0);
+  else if (wrt == 2) {
+    if (p->bf_kind != 3 || !dfield) return 1;
+    for (long k = 0; k < 3 * m.S; ++k) m.fext[k].d = dfield[k];
+  } else {
+    return 1;
+  }
+  State<Dual> s;
+  s.g.resize(19 * m.S);
+  s.X.resize(3 * (size_t)m.n_atoms);
+  s.V.resize(3 * (size_t)m.n_atoms);
+  for (long k = 0; k < 19 * m.S; ++k) s.g[k] = Dual(g[k]);
+  for (long k = 0; k < 3L * m.n_atoms; ++k) {
+    s.X[k] = Dual(X[k]);
+    s.V[k] = Dual(V[k]);
+  }
+  std::vector<Dual> post(19 * m.S);
+  for (int n = 0; n < n_steps; ++n) coupled_step(m, s, post);
+  Dual acc(0.0);
+  for (int a = 0; a < m.n_atoms; ++a)
+    for (int c = 0; c < 3; ++c) {
+      Dual e = s.X[3 * a + c] - Dual(X[3 * a + c] + D[c]);
+      acc += e * e;
+    }
+  acc = acc / Dual((double)m.n_atoms);
+  *loss = acc.v;
+  *dloss = acc.d;
+  return 0;
+}
+
+// Loss only, float64 (for central finite differences).
+int or_loss(const or_params* p, const double* g, const double* X, const double* V,
+            const double* X0, const int32_t* bonds, const double* field, const double* D,
+            int32_t n_steps, double* loss) {
+  std::vector<double> gv(g, g + 19 * (size_t)p->L[0] * p->L[1] * p->L[2]);
+  std::vector<double> Xv(X, X + 3 * (size_t)p->n_atoms), Vv(V, V + 3 * (size_t)p->n_atoms);
+  run_impl<double>(p, gv.data(), Xv.data(), Vv.data(), X0, bonds, field, n_steps);
+  double acc = 0.0;
+  for (int a = 0; a < p->n_atoms; ++a)
+    for (int c = 0; c < 3; ++c) {
+      double e = Xv[3 * a + c] - (X[3 * a + c] + D[c]);
+      acc += e * e;
+    }
+  *loss = acc / p->n_atoms;
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,260 @@
+"""ctypes front-end of the plain CPU oracle (``lbmd_oracle.cpp``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, the smoke check and the benchmark's CPU
+baseline leg, never by the product path.  It shares no code with the HIP library.
+
+Arrays crossing this interface are float64 (int32 for bonds), C-contiguous:
+populations [19, nz, ny, nx], fields [3, nz, ny, nx], atom arrays [N, 3].
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "lbmd_oracle.cpp")
+LIB = os.path.join(HERE, "liblbmd_oracle.so")
+
+# The oracle is compiled without target-specific flags so that the same binary runs on any
+# x86-64 host, and without floating-point contraction so that it evaluates exactly the
+# expressions as written.
+CXXFLAGS = ["-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math"]
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["g++", *CXXFLAGS, SRC, "-o", tmp])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class OrParams(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_int32 * 3),
+        ("n_atoms", ctypes.c_int32),
+        ("n_bonds", ctypes.c_int32),
+        ("lj_exclude_bonded", ctypes.c_int32),
+        ("bf_kind", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
+        ("tau", ctypes.c_double),
+        ("rho0", ctypes.c_double),
+        ("gamma", ctypes.c_double),
+        ("mass", ctypes.c_double),
+        ("k_tether", ctypes.c_double),
+        ("k_bond", ctypes.c_double),
+        ("r0_bond", ctypes.c_double),
+        ("lj_eps", ctypes.c_double),
+        ("lj_sigma", ctypes.c_double),
+        ("lj_rc", ctypes.c_double),
+        ("bf_amp", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build(force=True)
+        L = ctypes.CDLL(LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int32)
+        pp = ctypes.POINTER(OrParams)
+        L.or_velocity_set.argtypes = [ip, dp]
+        L.or_equilibrium.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp]
+        L.or_collide_node.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp, dp]
+        L.or_stream.argtypes = [ip, dp, dp]
+        L.or_interpolate.argtypes = [ip, dp, ctypes.c_int32, dp, dp]
+        L.or_spread.argtypes = [ip, ctypes.c_int32, dp, dp, dp]
+        L.or_forces.argtypes = [pp, dp, dp, ip, dp]
+        L.or_energy.argtypes = [pp, dp, dp, ip]
+        L.or_energy.restype = ctypes.c_double
+        L.or_external_force.argtypes = [pp, dp, dp]
+        L.or_observables.argtypes = [pp, dp, dp, dp, dp]
+        L.or_invariants.argtypes = [pp, dp, dp, dp]
+        for f in (L.or_run, L.or_run_f32):
+            f.argtypes = [pp, dp, dp, dp, dp, ip, dp, ctypes.c_int32]
+            f.restype = ctypes.c_int
+        L.or_loss_derivative.argtypes = [pp, dp, dp, dp, dp, ip, dp, dp, ctypes.c_int32,
+                                         ctypes.c_int32, dp, dp, dp]
+        L.or_loss_derivative.restype = ctypes.c_int
+        L.or_loss.argtypes = [pp, dp, dp, dp, dp, ip, dp, dp, ctypes.c_int32, dp]
+        L.or_loss.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _i(a):
+    if a is None:
+        return None
+    assert a.dtype == np.int32 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def i32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def make_params(L, tau, rho0=1.0, gamma=0.0, mass=1.0, k_tether=0.0, k_bond=0.0, r0_bond=1.0,
+                lj_eps=0.0, lj_sigma=1.0, lj_rc=2.5, lj_exclude_bonded=0, bf_kind=0, bf_amp=0.0,
+                n_atoms=0, n_bonds=0) -> OrParams:
+    p = OrParams()
+    Ls = (L, L, L) if np.isscalar(L) else tuple(L)
+    for a in range(3):
+        p.L[a] = int(Ls[a])
+    p.n_atoms, p.n_bonds = int(n_atoms), int(n_bonds)
+    p.lj_exclude_bonded, p.bf_kind = int(lj_exclude_bonded), int(bf_kind)
+    p.tau, p.rho0, p.gamma, p.mass = float(tau), float(rho0), float(gamma), float(mass)
+    p.k_tether, p.k_bond, p.r0_bond = float(k_tether), float(k_bond), float(r0_bond)
+    p.lj_eps, p.lj_sigma, p.lj_rc, p.bf_amp = float(lj_eps), float(lj_sigma), float(lj_rc), float(bf_amp)
+    return p
+
+
+def params_from_workload(w) -> OrParams:
+    return make_params(w.L, w.tau, w.rho0, w.gamma, w.mass, w.k_tether, w.k_bond, w.r0_bond,
+                       w.lj_eps, w.lj_sigma, w.lj_rc, w.lj_exclude_bonded, w.bf_kind, w.bf_amp,
+                       n_atoms=w.n_atoms, n_bonds=len(w.bonds))
+
+
+def n_sites(p: OrParams) -> int:
+    return int(p.L[0]) * int(p.L[1]) * int(p.L[2])
+
+
+def pop_shape(p: OrParams):
+    return (19, int(p.L[2]), int(p.L[1]), int(p.L[0]))
+
+
+def velocity_set():
+    c = np.zeros((19, 3), np.int32)
+    w = np.zeros(19, np.float64)
+    lib().or_velocity_set(_i(c), _d(w))
+    return c, w
+
+
+def equilibrium(rho0, drho, u):
+    out = np.zeros(19)
+    lib().or_equilibrium(float(rho0), float(drho), _d(f64(u)), _d(out))
+    return out
+
+
+def collide_node(tau, rho0, g, F):
+    out = np.zeros(19)
+    lib().or_collide_node(float(tau), float(rho0), _d(f64(g)), _d(f64(F)), _d(out))
+    return out
+
+
+def stream(L, post):
+    post = f64(post)
+    pre = np.zeros_like(post)
+    lib().or_stream(_i(i32(L)), _d(post), _d(pre))
+    return pre
+
+
+def interpolate(L, field, X):
+    X = f64(X)
+    U = np.zeros_like(X)
+    lib().or_interpolate(_i(i32(L)), _d(f64(field)), int(X.shape[0]), _d(X), _d(U))
+    return U
+
+
+def spread(L, X, F, field=None):
+    X = f64(X)
+    Ls = i32(L)
+    if field is None:
+        field = np.zeros((3, int(Ls[2]), int(Ls[1]), int(Ls[0])))
+    field = f64(field).copy()
+    lib().or_spread(_i(Ls), int(X.shape[0]), _d(X), _d(f64(F)), _d(field))
+    return field
+
+
+def forces(p: OrParams, X, X0, bonds):
+    X = f64(X)
+    F = np.zeros_like(X)
+    lib().or_forces(ctypes.byref(p), _d(X), _d(f64(X0)), _i(i32(bonds).reshape(-1, 2)), _d(F))
+    return F
+
+
+def energy(p: OrParams, X, X0, bonds):
+    return lib().or_energy(ctypes.byref(p), _d(f64(X)), _d(f64(X0)), _i(i32(bonds).reshape(-1, 2)))
+
+
+def external_force(p: OrParams, field=None):
+    out = np.zeros((3,) + pop_shape(p)[1:])
+    lib().or_external_force(ctypes.byref(p), _d(f64(field)) if field is not None else None, _d(out))
+    return out
+
+
+def observables(p: OrParams, g, field=None):
+    g = f64(g)
+    rho = np.zeros(pop_shape(p)[1:])
+    u = np.zeros((3,) + pop_shape(p)[1:])
+    lib().or_observables(ctypes.byref(p), _d(g), _d(f64(field)) if field is not None else None,
+                         _d(rho), _d(u))
+    return rho, u
+
+
+def invariants(p: OrParams, g, V):
+    out = np.zeros(7)
+    lib().or_invariants(ctypes.byref(p), _d(f64(g)), _d(f64(V).reshape(-1, 3)), _d(out))
+    return out
+
+
+def run(p: OrParams, g, X, V, X0, bonds, field=None, n_steps=1, precision="f64"):
+    """n_steps coupled steps; returns new (g, X, V) arrays (inputs are not modified)."""
+    g = f64(g).copy()
+    X = f64(X).copy()
+    V = f64(V).copy()
+    fn = lib().or_run if precision == "f64" else lib().or_run_f32
+    rc = fn(ctypes.byref(p), _d(g), _d(X), _d(V), _d(f64(X0)), _i(i32(bonds).reshape(-1, 2)),
+            _d(f64(field)) if field is not None else None, int(n_steps))
+    if rc != 0:
+        raise RuntimeError("oracle run failed (%d)" % rc)
+    return g, X, V
+
+
+def loss_derivative(p: OrParams, g, X, V, bonds, field, D, n_steps, wrt, dfield=None):
+    """(loss, d loss) along gamma (wrt=0), tau (wrt=1) or a body-force direction (wrt=2)."""
+    loss = ctypes.c_double()
+    dl = ctypes.c_double()
+    X = f64(X)
+    rc = lib().or_loss_derivative(
+        ctypes.byref(p), _d(f64(g)), _d(X), _d(f64(V)), _d(X), _i(i32(bonds).reshape(-1, 2)),
+        _d(f64(field)) if field is not None else None, _d(f64(D)), int(n_steps), int(wrt),
+        _d(f64(dfield)) if dfield is not None else None, ctypes.byref(loss), ctypes.byref(dl))
+    if rc != 0:
+        raise RuntimeError("oracle loss_derivative failed (%d)" % rc)
+    return loss.value, dl.value
+
+
+def loss(p: OrParams, g, X, V, bonds, field, D, n_steps):
+    out = ctypes.c_double()
+    X = f64(X)
+    rc = lib().or_loss(ctypes.byref(p), _d(f64(g)), _d(X), _d(f64(V)), _d(X),
+                       _i(i32(bonds).reshape(-1, 2)),
+                       _d(f64(field)) if field is not None else None, _d(f64(D)), int(n_steps),
+                       ctypes.byref(out))
+    if rc != 0:
+        raise RuntimeError("oracle loss failed (%d)" % rc)
+    return out.value
+
+
+def rest_state(p: OrParams):
+    """Pre-collision deviation populations of fluid at rest (all zero)."""
+    return np.zeros(pop_shape(p))
