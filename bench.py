@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Benchmark of the coupled lattice-Boltzmann / atom step on one MI355X.
+
+Default workload: the 256^3 periodic D3Q19 lattice (tau = 0.55) with 200,000 atoms in ten
+20,000-atom globules, FP32 deviation storage.  One timed "step" is one full coupled step
+(atom coupling + spreading, neighbour-list binning, the fused stream/collide sweep, atom
+forces and integration), all on the GPU with the inputs resident in HBM.
+
+Prints one JSON line: MLUPS (the value), the step's algorithmic HBM GB/s, the roofline of
+the dominant kernel (the sweep, timed live with HIP events on its own stream), and the CPU
+oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS and HBM GB/s (% roofline) of coupled LB step; adjoint/forward time ratio"
+HBM_PEAK_GBS = 8000.0
+SWEEP_SRC = os.path.join(ROOT, "paper_2305_05025_amd", "csrc", "lb_sweep.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_counters.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def sweep_bytes_per_site(storage: str, field: bool) -> int:
+    """Algorithmic bytes of one sweep per site: 19 populations read + 19 written."""
+    s = 4 if storage == "f32" else 2
+    return 2 * 19 * s + (12 if field else 0)
+
+
+def source_hash() -> str:
+    return hashlib.sha256(open(SWEEP_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(workload: str, storage: str):
+    """HBM bytes per sweep launch from committed rocprofv3 counter runs, if they were taken
+    on the current sweep source; else None."""
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    rec = d.get("%s/%s" % (workload, storage))
+    if not rec or rec.get("source_hash") != source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(k: int):
+    """The CPU oracle, single-threaded FP64, on a bounded sample of the workload: one coupled
+    step of the full lattice with the first globule's atoms."""
+    import numpy as np
+    from oracle import oracle as O
+    from workloads import make_workload
+    w = make_workload(k)
+    n = min(w.n_atoms, 20000)
+    p = O.params_from_workload(w)
+    p.n_atoms = n
+    nb = int(((w.bonds[:, 0] < n) & (w.bonds[:, 1] < n)).sum())
+    p.n_bonds = nb
+    g = np.zeros(O.pop_shape(p))
+    t0 = time.perf_counter()
+    O.run(p, g, w.x0[:n], w.v0[:n], w.x0[:n], w.bonds[:nb], w.body_force, 1)
+    dt = time.perf_counter() - t0
+    S = w.n_sites
+    return {"value": S / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": "1 coupled step of the %dx%dx%d lattice with %d of the %d atoms "
+                      "(FP64, single thread, %.1f s)" % (w.L[0], w.L[1], w.L[2], n, w.n_atoms, dt)}
+
+
+def run(args):
+    import torch
+    from paper_2305_05025_amd import _abi as A
+    from paper_2305_05025_amd.coupled import CoupledLB
+    from workloads import make_workload
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    w = make_workload(args.config)
+    log("workload %s: lattice %s, %d atoms, built in %.1f s" % (w.name, w.L, w.n_atoms, time.time() - t0))
+    sim = CoupledLB.from_workload(w, storage=args.storage, device=dev)
+    stream = sim.stream
+    sim.step(args.warmup)
+    sim.check()
+    torch.cuda.synchronize()
+    log("warmup done (%d steps)" % args.warmup)
+
+    A.lb_timing_begin(sim.ctx, args.steps)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    ev0.record(stream)
+    sim.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    sweep_ms, atom_ms, nsteps = A.lb_timing_end(sim.ctx)
+    sim.check()
+    step_ms = ev0.elapsed_time(ev1) / args.steps
+    log("timed %d steps: %.4f ms/step (events), wall %.3f s; sweep %.4f ms, atoms %.4f ms" %
+        (args.steps, step_ms, wall, sweep_ms / nsteps, atom_ms / nsteps))
+
+    S = w.n_sites
+    field = w.bf_kind == 3
+    bps = sweep_bytes_per_site(args.storage, field)
+    mlups = S / (step_ms * 1e-3) / 1e6
+    sweep_avg_s = sweep_ms / nsteps * 1e-3
+    achieved = bps * S / sweep_avg_s / 1e9
+    # whole-step algorithmic bytes: the sweep plus the atom side (positions, velocities,
+    # forces read/written, the coupling gather over each atom's 8 nodes counted once per
+    # atom-node pair)
+    atom_bytes = w.n_atoms * (4 * 3 * 4 * 2 + 8 * 19 * (4 if args.storage == "f32" else 2))
+    step_gbs = (bps * S + atom_bytes) / (step_ms * 1e-3) / 1e9
+    traffic = measured_traffic(w.name, args.storage)
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(step_ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.storage,
+        "data": "synthetic",
+        "config": {"workload": w.name, "lattice": list(w.L), "atoms": w.n_atoms,
+                   "storage": args.storage, "tau": w.tau, "steps_per_call": args.steps},
+        "hbm_gbs_step": round(step_gbs, 1),
+        "hbm_frac_step": round(step_gbs / HBM_PEAK_GBS, 4),
+        "coupling_share": round(atom_ms / (atom_ms + sweep_ms), 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "k_sweep<%s>" % args.storage,
+                     "bytes_per_site": bps, "sweep_ms": round(sweep_ms / nsteps, 5)},
+        "adjoint_forward_ratio": None,
+    }
+    sim.close()
+    if args.cpu_baseline:
+        log("timing the CPU oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(args.config)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+def calibrate_copy(args):
+    """A plain device copy of known size, for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    n = 256 * 1024 * 1024  # floats: 1 GiB each way
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(args.steps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each_way": 4 * n, "launches": args.steps}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--config", type=int, default=2, help="workload 0..4 (2 = 256^3, 200k atoms)")
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
+    ap.add_argument("--calibrate-copy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the multi-GPU (domain-decomposed) path is not "
+              "built; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy(args)
+    else:
+        run(args)
+
+
+if __name__ == "__main__":
+    main()

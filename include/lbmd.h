@@ -1,0 +1,185 @@
+/*
+ * lbmd.h -- C interface of the MI355X (gfx950) coupled lattice-Boltzmann / atom library.
+ *
+ * The operation (Lauricella et al., arXiv 2305.05025, Section 2.2):
+ *   a periodic D3Q19 lattice evolved by the single-relaxation-time (BGK) lattice Boltzmann
+ *   equation, Eq. (1), with relaxation time tau = 1/omega = 3 nu + 1/2, the second-order
+ *   equilibrium and the moments of Eqs. (2)-(3); atoms coupled to it by a friction force
+ *   gamma (u - v), u interpolated linearly over the eight nearest nodes, the opposite force
+ *   returned to the lattice through the forcing term S_i of Eq. (1) (Guo scheme) with the
+ *   same weights; lattice and atoms advanced in lock-step, one step each.
+ *   The atoms' own force field is a stand-in: harmonic tethers to the initial positions,
+ *   harmonic bonds, and Lennard-Jones truncated at r_c with minimum image.
+ *
+ * Units are lattice units: dx = dt = 1, rest density rho0.  Nodes sit at integer
+ * coordinates; positions are continuous.
+ *
+ * Layouts (all arrays C-contiguous):
+ *   site index s = x + nx * (y + ny * z), x fastest; S = nx * ny * nz
+ *   scalar field [S], vector field [3][S] (component-major), atom arrays [N][3] float32.
+ * Velocity ordering of the 19 populations: see lb_velocity_set().
+ *
+ * Ownership: the library never allocates device memory.  The caller provides one device
+ * workspace of lb_workspace_bytes() bytes (256-byte aligned) that must stay valid until
+ * lb_destroy().  All array arguments are device pointers unless stated; inputs are copied
+ * at lb_init, outputs are written into caller buffers.
+ *
+ * Asynchrony: every call enqueues on the HIP stream given at lb_init (NULL = default
+ * stream) and returns without waiting, except lb_init (copies the bond list to the host
+ * once), lb_invariants and lb_status_check, which synchronise the stream.
+ *
+ * Errors: every entry point returns an lb_status.  Arguments are validated before any
+ * device work is queued; on failure nothing is queued and lb_last_error() describes why.
+ * Device-side conditions (a cell of the neighbour list overflowing, non-finite values)
+ * are latched in device memory and reported by the next synchronising call.
+ *
+ * Threading: a context may be used by one host thread at a time.
+ */
+#ifndef LBMD_H
+#define LBMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lb_ctx lb_ctx;
+
+typedef enum {
+  LB_OK = 0,
+  LB_EINVAL = 1,      /* invalid argument (nothing was queued) */
+  LB_ENOMEM = 2,      /* workspace too small or misaligned */
+  LB_EDEVICE = 3,     /* a HIP runtime call failed */
+  LB_ESTATE = 4,      /* call not valid in the context's current state */
+  LB_ENONFINITE = 5,  /* a NaN/Inf appeared in the populations or atom velocities */
+  LB_EOVERFLOW = 6    /* a neighbour-list cell exceeded its capacity (atoms overlap) */
+} lb_status;
+
+/* Storage format of the populations.  All three store the deviation g_i = f_i - w_i rho0
+ * (the same scheme written about the rest state); the collision is computed in FP32.
+ * Narrow formats round to nearest even on every store. */
+typedef enum {
+  LB_STORE_F32 = 0,
+  LB_STORE_F16 = 1,
+  LB_STORE_BF16 = 2
+} lb_storage;
+
+/* External force density F_ext(x) entering the forcing term S_i of Eq. (1). */
+typedef enum {
+  LB_BF_NONE = 0,
+  LB_BF_KOLMOGOROV = 1,  /* F_x = amp * sin(2 pi y / ny)                        */
+  LB_BF_SIGN_SHEAR = 2,  /* F_x = amp * sign(y + 1/2 - ny/2)                    */
+  LB_BF_FIELD = 3        /* F = caller field [3][S] (FP32), copied at lb_init    */
+} lb_body_force;
+
+/* lb_params.flags */
+#define LB_FLAG_CHECK_FINITE 0x1u  /* lb_couple_step also checks for NaN/Inf every step */
+
+typedef struct {
+  int32_t L[3];              /* nx, ny, nz >= 2; periodic */
+  float tau;                 /* BGK relaxation time, > 0.5: nu = (tau - 1/2)/3 */
+  float rho0;                /* rest density, > 0 */
+  int32_t storage;           /* lb_storage */
+  int32_t n_atoms;           /* >= 0 */
+  float mass;                /* atom mass, > 0 when n_atoms > 0 */
+  float gamma;               /* friction coefficient (force per unit velocity), >= 0 */
+  float k_tether;            /* tether spring to the initial positions; 0 = off */
+  int32_t n_bonds;           /* >= 0 */
+  float k_bond, r0_bond;     /* harmonic bond U = k/2 (r - r0)^2 */
+  float lj_eps, lj_sigma;    /* Lennard-Jones; lj_eps = 0 turns it off */
+  float lj_rc;               /* cut-off (truncated, not shifted); box >= 3 rc per axis */
+  int32_t lj_exclude_bonded; /* 1: no LJ between bonded pairs */
+  int32_t bf_kind;           /* lb_body_force */
+  float bf_amp;
+  uint32_t flags;            /* LB_FLAG_* */
+} lb_params;
+
+/* The 19 lattice velocities c[i][0..2] and weights w[i] in the library's ordering:
+ * i = 0 rest; 1..6 = +x,-x,+y,-y,+z,-z; 7..18 = (1,1,0),(-1,-1,0),(1,-1,0),(-1,1,0),
+ * (1,0,1),(-1,0,-1),(1,0,-1),(-1,0,1),(0,1,1),(0,-1,-1),(0,1,-1),(0,-1,1);
+ * opposite(i) = i+1 for odd i.  Weights 1/3, 1/18, 1/36 (the D3Q19 set named after Eq. 1).
+ * Host pointers; either may be NULL. */
+void lb_velocity_set(int8_t c[19][3], double w[19]);
+
+/* Bytes of device workspace lb_init needs for these parameters (0 if they are invalid). */
+size_t lb_workspace_bytes(const lb_params* p);
+
+/* Create a context and set up the initial state on `hip_stream` (a hipStream_t, NULL for
+ * the default stream):
+ *   populations at rest equilibrium f_i = w_i rho0 (deviation 0);
+ *   atom positions x0 [N][3] (unwrapped lattice coordinates; also the tether anchors and
+ *   the origin of the displacement the library integrates), velocities v0 [N][3];
+ *   bonds [n_bonds][2] int32 atom index pairs (may be NULL when n_bonds = 0; read back to
+ *   the host once to build per-atom bond lists);
+ *   body_force [3][S] float32 when bf_kind = LB_BF_FIELD, else ignored.
+ * Device pointers.  Inputs are copied; the caller may free them after the call returns.
+ * On success *out receives the context. */
+lb_status lb_init(const lb_params* p, void* workspace, size_t workspace_bytes,
+                  const float* x0, const float* v0, const int32_t* bonds,
+                  const float* body_force, void* hip_stream, lb_ctx** out);
+
+/* Advance n_steps >= 0 coupled steps (Section 2.2; one lattice step per atom step).
+ * Each step, on the state (g^n pre-collision, X^n, v^n):
+ *   1. for every atom, u_c = (j + F_ext/2)/rho at its eight nodes (Eqs. 2-3) and
+ *      U = trilinear interpolation of u_c at X^n; friction F_c = gamma (U - v^n);
+ *   2. -F_c spread back to the same eight nodes with the same weights;
+ *   3. BGK collision with Guo forcing under F = F_ext + spread force, then streaming;
+ *   4. atom forces at X^n; v^{n+1} = v^n + (F_ff + F_c)/m, X^{n+1} = X^n + v^{n+1}.
+ * Asynchronous. */
+lb_status lb_couple_step(lb_ctx* c, int32_t n_steps);
+
+/* Observables of the current state (Eqs. 2-3): rho(x) = rho0 + sum_i g_i,
+ * u(x) = (j + F_ext/2)/rho (without the atoms' friction forces), the unwrapped atom
+ * positions and velocities.  Device pointers [S], [3][S], [N][3], [N][3]; any may be
+ * NULL.  Asynchronous. */
+lb_status lb_read_fields(lb_ctx* c, float* rho, float* u, float* x_unwrapped, float* v);
+
+/* Raw populations of the current pre-collision state as float32 deviations g_i
+ * [19][S] (device pointer), in the lb_velocity_set ordering.  Asynchronous. */
+lb_status lb_read_populations(lb_ctx* c, float* g);
+
+/* Replace the current pre-collision state by caller deviations g [19][S] (float32, device
+ * pointer, lb_velocity_set ordering), rounded to the storage format.  Atoms are unchanged.
+ * Lets a run start from any lattice state (restart from external data, tests).
+ * Asynchronous. */
+lb_status lb_set_populations(lb_ctx* c, const float* g);
+
+/* Conserved sums accumulated in FP64 on the device, written to host out7:
+ * [0] mass sum_x rho, [1..3] fluid momentum sum_x j, [4..6] atom momentum sum_a m v.
+ * Synchronises the stream; returns LB_ENONFINITE / LB_EOVERFLOW if latched. */
+lb_status lb_invariants(lb_ctx* c, double out7[7]);
+
+/* Synchronise the stream and report any latched device-side condition. */
+lb_status lb_status_check(lb_ctx* c);
+
+/* Number of completed steps since lb_init (or since the last lb_state_load). */
+int64_t lb_step_count(const lb_ctx* c);
+
+/* Snapshot of the full dynamic state (populations, atom displacements and velocities,
+ * step count): lb_state_bytes() bytes of caller device memory.  Asynchronous. */
+size_t lb_state_bytes(const lb_ctx* c);
+lb_status lb_state_save(lb_ctx* c, void* dst);
+lb_status lb_state_load(lb_ctx* c, const void* src);
+
+/* Kernel timing with HIP events recorded on the context's stream around each phase of
+ * the next max_steps steps (creates 4 * max_steps events).  lb_timing_end synchronises and
+ * writes out_ms[0] = summed duration of the lattice sweep kernels, out_ms[1] = summed
+ * duration of the atom kernels (binning, coupling, forces and integration), out_ms[2] =
+ * number of steps timed (milliseconds; host pointer). */
+lb_status lb_timing_begin(lb_ctx* c, int32_t max_steps);
+lb_status lb_timing_end(lb_ctx* c, double out_ms[3]);
+
+/* Release the context (host memory only; the workspace stays the caller's). */
+lb_status lb_destroy(lb_ctx* c);
+
+/* Message describing the last failure on this context (or of the last lb_init when c is
+ * NULL).  Valid until the next call on the same context. */
+const char* lb_last_error(const lb_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBMD_H */

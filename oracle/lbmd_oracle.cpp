@@ -292,6 +292,36 @@ void atom_forces(const Model<T>& m, const std::vector<T>& X, std::vector<T>& F) 
   }
 }
 
+// The same force field evaluated for one atom i only (all partners scanned).
+template <class T>
+void atom_force_one(const Model<T>& m, const std::vector<T>& X, int i, T F[3]) {
+  F[0] = F[1] = F[2] = T(0.0);
+  for (int c = 0; c < 3; ++c) F[c] -= m.k_tether * (X[3 * i + c] - m.anchor[3 * i + c]);
+  for (int b = 0; b < m.n_bonds; ++b) {
+    int p = m.bond_i[b], q = m.bond_j[b];
+    if (p != i && q != i) continue;
+    int j = p == i ? q : p;
+    T r[3];
+    for (int c = 0; c < 3; ++c) r[c] = min_image(X[3 * i + c] - X[3 * j + c], m.L[c]);
+    T rl = sqrtT(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    T fmag = -m.k_bond * (rl - m.r0_bond) / rl;
+    for (int c = 0; c < 3; ++c) F[c] += fmag * r[c];
+  }
+  if (val(m.lj_eps) != 0.0)
+    for (int j = 0; j < m.n_atoms; ++j) {
+      if (j == i) continue;
+      T r[3];
+      for (int c = 0; c < 3; ++c) r[c] = min_image(X[3 * i + c] - X[3 * j + c], m.L[c]);
+      T r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+      if (!(val(r2) < val(m.lj_rc * m.lj_rc))) continue;
+      if (m.lj_exclude_bonded && bonded(m, i, j)) continue;
+      T sr2 = m.lj_sigma * m.lj_sigma / r2;
+      T sr6 = sr2 * sr2 * sr2;
+      T fmag = T(24.0) * m.lj_eps * (T(2.0) * sr6 * sr6 - sr6) / r2;
+      for (int c = 0; c < 3; ++c) F[c] += fmag * r[c];
+    }
+}
+
 template <class T>
 T atom_energy(const Model<T>& m, const std::vector<T>& X) {
   const int N = m.n_atoms;
@@ -332,28 +362,34 @@ T atom_energy(const Model<T>& m, const std::vector<T>& X) {
 //  7 streaming
 //  8 stand-in force field at X^n
 //  9 symplectic Euler: v^{n+1} = v^n + (F_ff + F_c)/m, X^{n+1} = X^n + v^{n+1}
+// Steps 1-5: friction force on every atom (Fc) and total force density on every node (Ftot).
+template <class T>
+void coupling_forces(const Model<T>& m, const State<T>& s, std::vector<T>& Fc, std::vector<T>& Ftot) {
+  const long S = m.S;
+  const int N = m.n_atoms;
+  std::vector<T> uc(3 * S);
+  for (long x = 0; x < S; ++x) {
+    T dr, j[3];
+    moments_at(m, s.g, x, dr, j);
+    T rho = m.rho0 + dr;
+    for (int c = 0; c < 3; ++c) uc[c * S + x] = (j[c] + T(0.5) * m.fext[c * S + x]) / rho;
+  }
+  std::vector<T> U(3 * N);
+  Fc.assign(3 * N, T(0.0));
+  interpolate(m.L, S, uc, N, s.X.data(), U.data());
+  for (int k = 0; k < 3 * N; ++k) Fc[k] = m.gamma * (U[k] - s.V[k]);
+  Ftot = m.fext;
+  std::vector<T> Fspread(3 * S, T(0.0));
+  spread(m.L, S, N, s.X.data(), Fc.data(), Fspread);
+  for (long k = 0; k < 3 * S; ++k) Ftot[k] -= Fspread[k];
+}
+
 template <class T>
 void coupled_step(const Model<T>& m, State<T>& s, std::vector<T>& scratch_post) {
   const long S = m.S;
   const int N = m.n_atoms;
-  std::vector<T> drho(S), jf(3 * S), uc(3 * S);
-  for (long x = 0; x < S; ++x) {
-    T dr, j[3];
-    moments_at(m, s.g, x, dr, j);
-    drho[x] = dr;
-    T rho = m.rho0 + dr;
-    for (int c = 0; c < 3; ++c) {
-      jf[c * S + x] = j[c];
-      uc[c * S + x] = (j[c] + T(0.5) * m.fext[c * S + x]) / rho;
-    }
-  }
-  std::vector<T> U(3 * N), Fc(3 * N);
-  interpolate(m.L, S, uc, N, s.X.data(), U.data());
-  for (int k = 0; k < 3 * N; ++k) Fc[k] = m.gamma * (U[k] - s.V[k]);
-  std::vector<T> Ftot(m.fext);
-  std::vector<T> Fspread(3 * S, T(0.0));
-  spread(m.L, S, N, s.X.data(), Fc.data(), Fspread);
-  for (long k = 0; k < 3 * S; ++k) Ftot[k] -= Fspread[k];
+  std::vector<T> Fc, Ftot;
+  coupling_forces(m, s, Fc, Ftot);
   for (long x = 0; x < S; ++x) {
     T gin[19], gout[19], F[3];
     for (int i = 0; i < 19; ++i) gin[i] = s.g[i * S + x];
@@ -630,6 +666,48 @@ int or_loss_derivative(const or_params* p, const double* g, const double* X, con
   acc = acc / Dual((double)m.n_atoms);
   *loss = acc.v;
   *dloss = acc.d;
+  return 0;
+}
+
+// One coupled step from (g, X, V), with the outputs evaluated only where asked: the
+// post-step pre-collision populations g'[k][0..18] at sites site_idx[k], and X', V' of atoms
+// atom_idx[k].  Same algorithm as or_run; the collision is evaluated only at the 19
+// upstream nodes of each requested site, the force field only for requested atoms.
+int or_step_sampled(const or_params* p, const double* g, const double* X, const double* V,
+                    const double* X0, const int32_t* bonds, const double* field,
+                    int32_t n_sites, const int64_t* site_idx, double* g_out,
+                    int32_t n_idx, const int32_t* atom_idx, double* X_out, double* V_out) {
+  Model<double> m;
+  build_model<double>(p, X0, bonds, field, m);
+  State<double> s;
+  s.g.assign(g, g + 19 * m.S);
+  s.X.assign(X, X + 3 * (size_t)m.n_atoms);
+  s.V.assign(V, V + 3 * (size_t)m.n_atoms);
+  std::vector<double> Fc, Ftot;
+  coupling_forces(m, s, Fc, Ftot);
+  const int* L = m.L;
+  for (int k = 0; k < n_sites; ++k) {
+    long xs = site_idx[k];
+    long x = xs % L[0], y = (xs / L[0]) % L[1], z = xs / ((long)L[0] * L[1]);
+    for (int i = 0; i < 19; ++i) {
+      long src = site_index(L, wrap(x - CV[i][0], L[0]), wrap(y - CV[i][1], L[1]), wrap(z - CV[i][2], L[2]));
+      double gin[19], gout[19], F[3];
+      for (int q = 0; q < 19; ++q) gin[q] = s.g[q * m.S + src];
+      for (int c = 0; c < 3; ++c) F[c] = Ftot[c * m.S + src];
+      collide_node(m.tau, m.rho0, gin, F, gout);
+      g_out[19 * k + i] = gout[i];
+    }
+  }
+  for (int k = 0; k < n_idx; ++k) {
+    int a = atom_idx[k];
+    double F[3];
+    atom_force_one(m, s.X, a, F);
+    for (int c = 0; c < 3; ++c) {
+      double v = s.V[3 * a + c] + (F[c] + Fc[3 * a + c]) / m.mass;
+      V_out[3 * k + c] = v;
+      X_out[3 * k + c] = s.X[3 * a + c] + v;
+    }
+  }
   return 0;
 }
 

@@ -84,6 +84,9 @@ def lib():
         L.or_loss_derivative.argtypes = [pp, dp, dp, dp, dp, ip, dp, dp, ctypes.c_int32,
                                          ctypes.c_int32, dp, dp, dp]
         L.or_loss_derivative.restype = ctypes.c_int
+        L.or_step_sampled.argtypes = [pp, dp, dp, dp, dp, ip, dp, ctypes.c_int32,
+                                      ctypes.POINTER(ctypes.c_int64), dp, ctypes.c_int32, ip, dp, dp]
+        L.or_step_sampled.restype = ctypes.c_int
         L.or_loss.argtypes = [pp, dp, dp, dp, dp, ip, dp, dp, ctypes.c_int32, dp]
         L.or_loss.restype = ctypes.c_int
         _lib = L
@@ -227,6 +230,23 @@ def run(p: OrParams, g, X, V, X0, bonds, field=None, n_steps=1, precision="f64")
     if rc != 0:
         raise RuntimeError("oracle run failed (%d)" % rc)
     return g, X, V
+
+
+def step_sampled(p: OrParams, g, X, V, X0, bonds, field, site_idx, atom_idx):
+    """One step; returns (g' [n_sites, 19] at site_idx, X' [n, 3], V' [n, 3] of atom_idx)."""
+    site_idx = np.ascontiguousarray(site_idx, dtype=np.int64)
+    atom_idx = i32(atom_idx)
+    gout = np.zeros((len(site_idx), 19))
+    Xo = np.zeros((len(atom_idx), 3))
+    Vo = np.zeros((len(atom_idx), 3))
+    rc = lib().or_step_sampled(
+        ctypes.byref(p), _d(f64(g)), _d(f64(X)), _d(f64(V)), _d(f64(X0)),
+        _i(i32(bonds).reshape(-1, 2)), _d(f64(field)) if field is not None else None,
+        len(site_idx), site_idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _d(gout),
+        len(atom_idx), _i(atom_idx), _d(Xo), _d(Vo))
+    if rc != 0:
+        raise RuntimeError("oracle step_sampled failed (%d)" % rc)
+    return gout, Xo, Vo
 
 
 def loss_derivative(p: OrParams, g, X, V, bonds, field, D, n_steps, wrt, dfield=None):

@@ -1,0 +1,154 @@
+"""PyTorch front-end of the coupled lattice-Boltzmann / atom library.
+
+PyTorch supplies device memory (one uint8 workspace tensor, input/output tensors) and the
+HIP stream (torch's current stream); every step of the computation runs in the library's
+HIP kernels through the C interface.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import torch
+
+from . import _abi as A
+
+STORAGE = {"f32": A.LB_STORE_F32, "f16": A.LB_STORE_F16, "bf16": A.LB_STORE_BF16}
+
+
+def make_params(L, tau, rho0=1.0, storage="f32", n_atoms=0, mass=1.0, gamma=0.0, k_tether=0.0,
+                n_bonds=0, k_bond=0.0, r0_bond=1.0, lj_eps=0.0, lj_sigma=1.0, lj_rc=2.5,
+                lj_exclude_bonded=0, bf_kind=0, bf_amp=0.0, flags=0) -> A.lb_params:
+    p = A.lb_params()
+    Ls = (L, L, L) if isinstance(L, int) else tuple(L)
+    for k in range(3):
+        p.L[k] = int(Ls[k])
+    p.tau, p.rho0 = float(tau), float(rho0)
+    p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    p.n_atoms, p.mass, p.gamma, p.k_tether = int(n_atoms), float(mass), float(gamma), float(k_tether)
+    p.n_bonds, p.k_bond, p.r0_bond = int(n_bonds), float(k_bond), float(r0_bond)
+    p.lj_eps, p.lj_sigma, p.lj_rc = float(lj_eps), float(lj_sigma), float(lj_rc)
+    p.lj_exclude_bonded, p.bf_kind, p.bf_amp = int(lj_exclude_bonded), int(bf_kind), float(bf_amp)
+    p.flags = int(flags)
+    return p
+
+
+def params_from_workload(w, storage="f32", flags=0) -> A.lb_params:
+    return make_params(w.L, w.tau, w.rho0, storage, w.n_atoms, w.mass, w.gamma, w.k_tether,
+                       len(w.bonds), w.k_bond, w.r0_bond, w.lj_eps, w.lj_sigma, w.lj_rc,
+                       w.lj_exclude_bonded, w.bf_kind, w.bf_amp, flags)
+
+
+def _aligned_workspace(nbytes: int, device) -> tuple:
+    raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    base = raw.data_ptr()
+    off = (-base) % 256
+    return raw, base + off
+
+
+class CoupledLB:
+    """One coupled lattice + atom system living on one GPU.
+
+    x0, v0: [N, 3] float32 (unwrapped positions, velocities); bonds: [n_bonds, 2] int32;
+    body_force: [3, nz, ny, nx] float32 when bf_kind is LB_BF_FIELD.
+    """
+
+    def __init__(self, params: A.lb_params, x0=None, v0=None, bonds=None, body_force=None,
+                 device="cuda", stream: Optional[torch.cuda.Stream] = None):
+        self.device = torch.device(device)
+        self.params = params
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.L = tuple(int(params.L[k]) for k in range(3))
+        self.S = self.L[0] * self.L[1] * self.L[2]
+        self.N = int(params.n_atoms)
+        nbytes = A.lb_workspace_bytes(params)
+        if nbytes == 0:
+            # the validator's message comes from lb_init
+            A.lb_init(params, 0, 0, 0, 0, 0, 0, 0)
+        self._ws, ws_ptr = _aligned_workspace(nbytes, self.device)
+        dev = self.device
+
+        def t32(a, shape):
+            if a is None:
+                return None
+            return torch.as_tensor(a, dtype=torch.float32).reshape(shape).contiguous().to(dev)
+
+        x0t = t32(x0, (self.N, 3)) if self.N else None
+        v0t = t32(v0, (self.N, 3)) if self.N else None
+        bt = None
+        if params.n_bonds:
+            bt = torch.as_tensor(bonds, dtype=torch.int32).reshape(-1, 2).contiguous().to(dev)
+        bft = t32(body_force, (3, self.S)) if params.bf_kind == A.LB_BF_FIELD else None
+        ptr = lambda t: t.data_ptr() if t is not None else 0
+        torch.cuda.synchronize(self.device)   # inputs were staged on torch's current stream
+        with torch.cuda.stream(self.stream):
+            self.ctx = A.lb_init(params, ws_ptr, nbytes, ptr(x0t), ptr(v0t), ptr(bt), ptr(bft),
+                                 self.stream.cuda_stream)
+        self._inputs = (x0t, v0t, bt, bft)   # kept alive until set-up copies are done
+
+    @classmethod
+    def from_workload(cls, w, storage="f32", device="cuda", flags=0, stream=None):
+        return cls(params_from_workload(w, storage, flags), w.x0, w.v0, w.bonds, w.body_force,
+                   device=device, stream=stream)
+
+    # -- stepping / observables ------------------------------------------------------------
+    def step(self, n: int = 1):
+        A.lb_couple_step(self.ctx, n)
+
+    def read_fields(self):
+        """(rho [nz,ny,nx], u [3,nz,ny,nx], x_unwrapped [N,3], v [N,3]) as device tensors."""
+        nz, ny, nx = self.L[2], self.L[1], self.L[0]
+        rho = torch.empty((nz, ny, nx), dtype=torch.float32, device=self.device)
+        u = torch.empty((3, nz, ny, nx), dtype=torch.float32, device=self.device)
+        x = torch.empty((self.N, 3), dtype=torch.float32, device=self.device)
+        v = torch.empty((self.N, 3), dtype=torch.float32, device=self.device)
+        A.lb_read_fields(self.ctx, rho.data_ptr(), u.data_ptr(),
+                         x.data_ptr() if self.N else 0, v.data_ptr() if self.N else 0)
+        self.stream.synchronize()
+        return rho, u, x, v
+
+    def populations(self):
+        """Pre-collision deviations g [19, nz, ny, nx] (float32)."""
+        g = torch.empty((19, self.L[2], self.L[1], self.L[0]), dtype=torch.float32, device=self.device)
+        A.lb_read_populations(self.ctx, g.data_ptr())
+        self.stream.synchronize()
+        return g
+
+    def set_populations(self, g):
+        """Load pre-collision deviations g [19, nz, ny, nx] as the current lattice state."""
+        gt = torch.as_tensor(g, dtype=torch.float32).reshape(19, self.S).contiguous().to(self.device)
+        torch.cuda.synchronize(self.device)
+        A.lb_set_populations(self.ctx, gt.data_ptr())
+        self.stream.synchronize()
+
+    def invariants(self):
+        return A.lb_invariants(self.ctx)
+
+    def check(self):
+        A.lb_status_check(self.ctx)
+
+    @property
+    def step_count(self) -> int:
+        return A.lb_step_count(self.ctx)
+
+    # -- checkpoints -----------------------------------------------------------------------
+    def save_state(self) -> torch.Tensor:
+        n = A.lb_state_bytes(self.ctx)
+        raw, ptr = _aligned_workspace(n, self.device)
+        A.lb_state_save(self.ctx, ptr)
+        return raw, ptr
+
+    def load_state(self, snap):
+        A.lb_state_load(self.ctx, snap[1])
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.stream.synchronize()
+            A.lb_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,509 @@
+// Lattice kernels for gfx950: the fused pull-stream + BGK/Guo collision sweep, readback of
+// the moments, and the FP64 conservation sums.
+//
+// Eq. (1) of the paper (Section 2.2), written for deviations g_i = f_i - w_i rho0 and read
+// with the standard BGK sign (relaxation toward equilibrium):
+//   g_i(x + c_i, t + 1) = g_i - omega (g_i - g_i^eq) + S_i
+// with omega = 1/tau, the second-order equilibrium, the moments of Eqs. (2)-(3), and the
+// forcing term S_i in the Guo form (velocity shifted by F/2, prefactor 1 - omega/2).
+//
+// Layout: populations are 19 planes (structure of arrays) of `plane` elements, site index
+// s = x + nx (y + ny z).  The stored buffer holds post-collision values at the site that
+// produced them; a site's pre-collision values are pulled from its 19 upstream neighbours
+// (x - c_i), so every load of a wavefront is a contiguous (possibly 4-byte shifted) run and
+// every store is a full aligned run.  The sweep reads buffer A and writes buffer B.
+//
+// One thread per site, 256 sites per workgroup.  A workgroup is also the unit ("tile") of
+// the sparse atom force: tiles that atoms touched in this step carry a flag, and only their
+// sites read (and clear) the fixed-point coupling-force field.
+#include "lbmd_internal.h"
+
+namespace lbmd {
+namespace {
+
+// ---- storage formats --------------------------------------------------------------------
+template <int ST>
+struct Store;
+
+template <>
+struct Store<LB_STORE_F32> {
+  using T = float;
+  static __device__ __forceinline__ float ld(const T* p) { return *p; }
+  static __device__ __forceinline__ void st(T* p, float v) { __builtin_nontemporal_store(v, p); }
+};
+
+template <>
+struct Store<LB_STORE_F16> {
+  using T = _Float16;
+  static __device__ __forceinline__ float ld(const T* p) { return (float)*p; }
+  // conversion to binary16 rounds to nearest even; subnormals are kept
+  static __device__ __forceinline__ void st(T* p, float v) {
+    __builtin_nontemporal_store((_Float16)v, p);
+  }
+};
+
+template <>
+struct Store<LB_STORE_BF16> {
+  using T = uint16_t;
+  static __device__ __forceinline__ float ld(const T* p) {
+    return __uint_as_float((uint32_t)(*p) << 16);
+  }
+  static __device__ __forceinline__ void st(T* p, float v) {
+    uint32_t u = __float_as_uint(v);
+    uint16_t h;
+    if ((u & 0x7fffffffu) > 0x7f800000u) {
+      h = (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+    } else {
+      u += 0x7fffu + ((u >> 16) & 1u);    // round to nearest, ties to even
+      h = (uint16_t)(u >> 16);
+    }
+    __builtin_nontemporal_store(h, p);
+  }
+};
+
+// ---- pull gather: pre-collision values at (x, y, z) -----------------------------------------
+template <int ST>
+__device__ __forceinline__ void gather(const typename Store<ST>::T* __restrict__ f, long plane,
+                                       int x, int y, int z, int nx, int ny, int nz,
+                                       float g[19]) {
+  const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+  const int nxy = nx * ny;
+  const int X3[3] = {xm, x, xp};
+  const int Y3[3] = {ym * nx, y * nx, yp * nx};
+  const int Z3[3] = {zm * nxy, z * nxy, zp * nxy};
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const int src = X3[1 - CX[i]] + Y3[1 - CY[i]] + Z3[1 - CZ[i]];
+    g[i] = Store<ST>::ld(f + (size_t)i * plane + src);
+  }
+}
+
+// ---- moments (Eqs. 2-3 in deviation form) --------------------------------------------------
+__device__ __forceinline__ void moments(const float g[19], float& drho, float& jx, float& jy,
+                                        float& jz) {
+  drho = 0.f;
+  jx = jy = jz = 0.f;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    drho += g[i];
+    if (CX[i] == 1) jx += g[i];
+    if (CX[i] == -1) jx -= g[i];
+    if (CY[i] == 1) jy += g[i];
+    if (CY[i] == -1) jy -= g[i];
+    if (CZ[i] == 1) jz += g[i];
+    if (CZ[i] == -1) jz -= g[i];
+  }
+}
+
+template <int C>
+__device__ __forceinline__ float cdot(float ax, float ay, float az, int cx, int cy, int cz) {
+  float r = 0.f;
+  if (cx == 1) r += ax;
+  if (cx == -1) r -= ax;
+  if (cy == 1) r += ay;
+  if (cy == -1) r -= ay;
+  if (cz == 1) r += az;
+  if (cz == -1) r -= az;
+  return r;
+}
+
+// ---- BGK + Guo collision in place; returns false on a non-finite moment ---------------------
+__device__ __forceinline__ bool collide(float g[19], float Fx, float Fy, float Fz, float rho0,
+                                        float omega, float pref) {
+  float drho, jx, jy, jz;
+  moments(g, drho, jx, jy, jz);
+  const float rho = rho0 + drho;
+  const float inv = 1.0f / rho;
+  const float ux = (jx + 0.5f * Fx) * inv;
+  const float uy = (jy + 0.5f * Fy) * inv;
+  const float uz = (jz + 0.5f * Fz) * inv;
+  const float uu = ux * ux + uy * uy + uz * uz;
+  const float uF = ux * Fx + uy * Fy + uz * Fz;
+  const float base = drho - 1.5f * rho * uu;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const float cu = cdot<0>(ux, uy, uz, CX[i], CY[i], CZ[i]);
+    const float cF = cdot<0>(Fx, Fy, Fz, CX[i], CY[i], CZ[i]);
+    const float geq = WQ[i] * (base + rho * (3.0f * cu + 4.5f * cu * cu));
+    const float src = pref * WQ[i] * (3.0f * (cF - uF) + 9.0f * cu * cF);
+    g[i] = g[i] - omega * (g[i] - geq) + src;
+  }
+  return __builtin_isfinite(drho + jx + jy + jz);
+}
+
+struct SweepArgs {
+  const void* fin;
+  void* fout;
+  long plane;
+  int nx, ny, nz, S;
+  float rho0, omega, pref;
+  int bf_kind;
+  const float* fext_tab;
+  const float* fext_field;
+  const uint32_t* tile_flag;   // NULL when there are no atoms
+  long long* fcoup;
+  uint32_t* err;
+};
+
+__device__ __forceinline__ void external_force(int bf_kind, const float* tab, const float* field,
+                                               long plane, int s, int y, float& Fx, float& Fy,
+                                               float& Fz) {
+  Fx = Fy = Fz = 0.f;
+  if (bf_kind == LB_BF_KOLMOGOROV || bf_kind == LB_BF_SIGN_SHEAR) {
+    Fx = tab[y];
+  } else if (bf_kind == LB_BF_FIELD) {
+    Fx = field[s];
+    Fy = field[plane + s];
+    Fz = field[2 * plane + s];
+  }
+}
+
+template <int ST>
+__global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
+  using T = typename Store<ST>::T;
+  const int s = blockIdx.x * kSweepBlock + threadIdx.x;
+  const bool hot = a.tile_flag != nullptr && a.tile_flag[blockIdx.x] != 0u;
+  if (s >= a.S) return;
+  const int x = s % a.nx;
+  const int t = s / a.nx;
+  const int y = t % a.ny;
+  const int z = t / a.ny;
+  float g[19];
+  gather<ST>(reinterpret_cast<const T*>(a.fin), a.plane, x, y, z, a.nx, a.ny, a.nz, g);
+  float Fx, Fy, Fz;
+  external_force(a.bf_kind, a.fext_tab, a.fext_field, a.plane, s, y, Fx, Fy, Fz);
+  if (hot) {
+    long long* fc = a.fcoup;
+    const long long qx = fc[s], qy = fc[a.plane + s], qz = fc[2 * a.plane + s];
+    Fx += (float)qx * kFixInv;
+    Fy += (float)qy * kFixInv;
+    Fz += (float)qz * kFixInv;
+    fc[s] = 0;
+    fc[a.plane + s] = 0;
+    fc[2 * a.plane + s] = 0;
+  }
+  if (!collide(g, Fx, Fy, Fz, a.rho0, a.omega, a.pref)) atomicOr(a.err, kErrNonFinite);
+  T* out = reinterpret_cast<T*>(a.fout);
+#pragma unroll
+  for (int i = 0; i < 19; ++i) Store<ST>::st(out + (size_t)i * a.plane + s, g[i]);
+}
+
+// ---- readback -------------------------------------------------------------------------------
+struct ReadArgs {
+  const void* f;
+  long plane;
+  int nx, ny, nz, S;
+  float rho0;
+  int bf_kind;
+  const float* fext_tab;
+  const float* fext_field;
+  float* rho;   // [S] or NULL
+  float* u;     // [3][S] or NULL
+  float* pops;  // [19][S] or NULL
+};
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_read(ReadArgs a) {
+  using T = typename Store<ST>::T;
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= a.S) return;
+  const int x = s % a.nx;
+  const int t = s / a.nx;
+  const int y = t % a.ny;
+  const int z = t / a.ny;
+  float g[19];
+  gather<ST>(reinterpret_cast<const T*>(a.f), a.plane, x, y, z, a.nx, a.ny, a.nz, g);
+  if (a.pops) {
+#pragma unroll
+    for (int i = 0; i < 19; ++i) a.pops[(size_t)i * a.S + s] = g[i];
+  }
+  if (a.rho || a.u) {
+    float drho, jx, jy, jz, Fx, Fy, Fz;
+    moments(g, drho, jx, jy, jz);
+    external_force(a.bf_kind, a.fext_tab, a.fext_field, a.plane, s, y, Fx, Fy, Fz);
+    const float rho = a.rho0 + drho;
+    if (a.rho) a.rho[s] = rho;
+    if (a.u) {
+      const float inv = 1.0f / rho;
+      a.u[s] = (jx + 0.5f * Fx) * inv;
+      a.u[(size_t)a.S + s] = (jy + 0.5f * Fy) * inv;
+      a.u[2 * (size_t)a.S + s] = (jz + 0.5f * Fz) * inv;
+    }
+  }
+}
+
+// ---- state upload: pre-collision g at x is stored where the pull will find it, x + c_i ----
+struct WriteArgs {
+  void* f;
+  long plane;
+  int nx, ny, nz, S;
+  const float* pops;  // [19][S]
+};
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_write(WriteArgs a) {
+  using T = typename Store<ST>::T;
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= a.S) return;
+  const int x = s % a.nx;
+  const int t = s / a.nx;
+  const int y = t % a.ny;
+  const int z = t / a.ny;
+  const int xm = x == 0 ? a.nx - 1 : x - 1, xp = x == a.nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? a.ny - 1 : y - 1, yp = y == a.ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? a.nz - 1 : z - 1, zp = z == a.nz - 1 ? 0 : z + 1;
+  const int nxy = a.nx * a.ny;
+  const int X3[3] = {xm, x, xp};
+  const int Y3[3] = {ym * a.nx, y * a.nx, yp * a.nx};
+  const int Z3[3] = {zm * nxy, z * nxy, zp * nxy};
+  T* f = reinterpret_cast<T*>(a.f);
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const int dst = X3[1 + CX[i]] + Y3[1 + CY[i]] + Z3[1 + CZ[i]];
+    Store<ST>::st(f + (size_t)i * a.plane + dst, a.pops[(size_t)i * a.S + s]);
+  }
+}
+
+// ---- FP64 conservation sums -------------------------------------------------------------------
+// Streaming permutes values between sites, so the lattice totals of the stored buffer equal
+// those of the pre-collision state; no gather is needed.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+struct RedArgs {
+  const void* f;
+  long plane;
+  int S;
+  double* partial;  // [kRedBlocks][4]
+  uint32_t* err;
+};
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_reduce_pops(RedArgs a) {
+  using T = typename Store<ST>::T;
+  const T* f = reinterpret_cast<const T*>(a.f);
+  double m = 0.0, px = 0.0, py = 0.0, pz = 0.0;
+  bool finite = true;
+  for (int s = blockIdx.x * 256 + threadIdx.x; s < a.S; s += gridDim.x * 256) {
+    float g[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) g[i] = Store<ST>::ld(f + (size_t)i * a.plane + s);
+    double dm = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      const double gi = (double)g[i];
+      dm += gi;
+      if (CX[i] == 1) jx += gi;
+      if (CX[i] == -1) jx -= gi;
+      if (CY[i] == 1) jy += gi;
+      if (CY[i] == -1) jy -= gi;
+      if (CZ[i] == 1) jz += gi;
+      if (CZ[i] == -1) jz -= gi;
+    }
+    finite = finite && __builtin_isfinite(dm + jx + jy + jz);
+    m += dm;
+    px += jx;
+    py += jy;
+    pz += jz;
+  }
+  if (!finite) atomicOr(a.err, kErrNonFinite);
+  __shared__ double sh[4][4];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  m = wave_sum(m);
+  px = wave_sum(px);
+  py = wave_sum(py);
+  pz = wave_sum(pz);
+  if (lane == 0) {
+    sh[wid][0] = m;
+    sh[wid][1] = px;
+    sh[wid][2] = py;
+    sh[wid][3] = pz;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int k = threadIdx.x;
+    a.partial[blockIdx.x * 4 + k] = ((sh[0][k] + sh[1][k]) + sh[2][k]) + sh[3][k];
+  }
+}
+
+struct FinalArgs {
+  const double* partial;
+  int nblocks;
+  const float* vel;   // [N][3]
+  int N;
+  float mass;
+  double rest_mass;   // rho0 * S
+  double* out;        // [8]
+  uint32_t* err;
+};
+
+__global__ __launch_bounds__(1024) void k_reduce_final(FinalArgs a) {
+  __shared__ double sh[16][7];
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < a.nblocks; b += 1024)
+    for (int k = 0; k < 4; ++k) acc[k] += a.partial[b * 4 + k];
+  bool finite = true;
+  for (int i = threadIdx.x; i < a.N; i += 1024) {
+    const float vx = a.vel[3 * i], vy = a.vel[3 * i + 1], vz = a.vel[3 * i + 2];
+    finite = finite && __builtin_isfinite(vx + vy + vz);
+    acc[4] += (double)a.mass * vx;
+    acc[5] += (double)a.mass * vy;
+    acc[6] += (double)a.mass * vz;
+  }
+  if (!finite) atomicOr(a.err, kErrNonFinite);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int k = 0; k < 7; ++k) {
+    const double v = wave_sum(acc[k]);
+    if (lane == 0) sh[wid][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 7) {
+    const int k = threadIdx.x;
+    double v = 0.0;
+    for (int w = 0; w < 16; ++w) v += sh[w][k];
+    if (k == 0) v += a.rest_mass;
+    a.out[k] = v;
+  }
+}
+
+__global__ void k_zero(uint32_t* p, size_t n_words) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n_words;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+__global__ void k_store_i64(int64_t* dst, int64_t v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v;
+}
+
+int blocks_for(long n, int per) { return (int)((n + per - 1) / per); }
+
+}  // namespace
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+  // every workspace region is a multiple of 4 bytes and 256-byte aligned
+  const size_t words = bytes / 4;
+  if (words == 0) return hipSuccess;
+  int blocks = (int)((words + 255) / 256);
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, (uint32_t*)p, words);
+  return hipGetLastError();
+}
+
+hipError_t launch_store_i64(void* dst, int64_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_store_i64, dim3(1), dim3(64), 0, s, (int64_t*)dst, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep(lb_ctx* c, const void* fin, void* fout) {
+  const Geometry& g = c->geo;
+  SweepArgs a;
+  a.fin = fin;
+  a.fout = fout;
+  a.plane = g.plane;
+  a.nx = g.nx;
+  a.ny = g.ny;
+  a.nz = g.nz;
+  a.S = (int)g.S;
+  a.rho0 = c->p.rho0;
+  a.omega = c->omega;
+  a.pref = 1.0f - 0.5f * c->omega;
+  a.bf_kind = c->p.bf_kind;
+  a.fext_tab = (const float*)(c->ws + c->lay.fext_tab);
+  a.fext_field = (const float*)(c->ws + c->lay.fext_field);
+  a.tile_flag = c->p.n_atoms > 0 ? (const uint32_t*)(c->ws + c->lay.tile_flag) : nullptr;
+  a.fcoup = (long long*)(c->ws + c->lay.fcoup);
+  a.err = (uint32_t*)(c->ws + c->lay.err);
+  const dim3 grid(g.ntiles), block(kSweepBlock);
+  switch (c->p.storage) {
+    case LB_STORE_F32: hipLaunchKernelGGL(k_sweep<LB_STORE_F32>, grid, block, 0, c->stream, a); break;
+    case LB_STORE_F16: hipLaunchKernelGGL(k_sweep<LB_STORE_F16>, grid, block, 0, c->stream, a); break;
+    default: hipLaunchKernelGGL(k_sweep<LB_STORE_BF16>, grid, block, 0, c->stream, a); break;
+  }
+  return hipGetLastError();
+}
+
+static hipError_t launch_read(lb_ctx* c, float* rho, float* u, float* pops) {
+  const Geometry& g = c->geo;
+  ReadArgs a;
+  a.f = c->ws + c->lay.pop[c->cur];
+  a.plane = g.plane;
+  a.nx = g.nx;
+  a.ny = g.ny;
+  a.nz = g.nz;
+  a.S = (int)g.S;
+  a.rho0 = c->p.rho0;
+  a.bf_kind = c->p.bf_kind;
+  a.fext_tab = (const float*)(c->ws + c->lay.fext_tab);
+  a.fext_field = (const float*)(c->ws + c->lay.fext_field);
+  a.rho = rho;
+  a.u = u;
+  a.pops = pops;
+  const dim3 grid(blocks_for(g.S, 256)), block(256);
+  switch (c->p.storage) {
+    case LB_STORE_F32: hipLaunchKernelGGL(k_read<LB_STORE_F32>, grid, block, 0, c->stream, a); break;
+    case LB_STORE_F16: hipLaunchKernelGGL(k_read<LB_STORE_F16>, grid, block, 0, c->stream, a); break;
+    default: hipLaunchKernelGGL(k_read<LB_STORE_BF16>, grid, block, 0, c->stream, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_read_fields(lb_ctx* c, float* rho, float* u) { return launch_read(c, rho, u, nullptr); }
+
+hipError_t launch_read_populations(lb_ctx* c, float* g) { return launch_read(c, nullptr, nullptr, g); }
+
+hipError_t launch_write_populations(lb_ctx* c, const float* g) {
+  const Geometry& geo = c->geo;
+  WriteArgs a;
+  a.f = c->ws + c->lay.pop[c->cur];
+  a.plane = geo.plane;
+  a.nx = geo.nx;
+  a.ny = geo.ny;
+  a.nz = geo.nz;
+  a.S = (int)geo.S;
+  a.pops = g;
+  const dim3 grid(blocks_for(geo.S, 256)), block(256);
+  switch (c->p.storage) {
+    case LB_STORE_F32: hipLaunchKernelGGL(k_write<LB_STORE_F32>, grid, block, 0, c->stream, a); break;
+    case LB_STORE_F16: hipLaunchKernelGGL(k_write<LB_STORE_F16>, grid, block, 0, c->stream, a); break;
+    default: hipLaunchKernelGGL(k_write<LB_STORE_BF16>, grid, block, 0, c->stream, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_invariants(lb_ctx* c) {
+  const Geometry& g = c->geo;
+  RedArgs a;
+  a.f = c->ws + c->lay.pop[c->cur];
+  a.plane = g.plane;
+  a.S = (int)g.S;
+  a.partial = (double*)(c->ws + c->lay.red_partial);
+  a.err = (uint32_t*)(c->ws + c->lay.err);
+  int nb = blocks_for(g.S, 256);
+  if (nb > kRedBlocks) nb = kRedBlocks;
+  switch (c->p.storage) {
+    case LB_STORE_F32: hipLaunchKernelGGL(k_reduce_pops<LB_STORE_F32>, dim3(nb), dim3(256), 0, c->stream, a); break;
+    case LB_STORE_F16: hipLaunchKernelGGL(k_reduce_pops<LB_STORE_F16>, dim3(nb), dim3(256), 0, c->stream, a); break;
+    default: hipLaunchKernelGGL(k_reduce_pops<LB_STORE_BF16>, dim3(nb), dim3(256), 0, c->stream, a); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  FinalArgs f;
+  f.partial = a.partial;
+  f.nblocks = nb;
+  f.vel = (const float*)(c->ws + c->lay.vel);
+  f.N = c->p.n_atoms;
+  f.mass = c->p.mass;
+  f.rest_mass = (double)c->p.rho0 * (double)g.S;
+  f.out = (double*)(c->ws + c->lay.red_out);
+  f.err = a.err;
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1024), 0, c->stream, f);
+  return hipGetLastError();
+}
+
+}  // namespace lbmd

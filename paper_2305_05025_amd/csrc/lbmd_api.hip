@@ -1,0 +1,475 @@
+// Host side of the C interface declared in include/lbmd.h: argument validation, the
+// workspace plan, initial state, the per-step launch sequence and the synchronising calls.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbmd_internal.h"
+
+namespace lbmd {
+
+static size_t round_up(size_t n, size_t a) { return (n + a - 1) / a * a; }
+
+static size_t elem_bytes(int storage) { return storage == LB_STORE_F32 ? 4 : 2; }
+
+bool geometry(const lb_params* p, Geometry* g) {
+  g->nx = p->L[0];
+  g->ny = p->L[1];
+  g->nz = p->L[2];
+  g->S = (long)p->L[0] * p->L[1] * p->L[2];
+  g->plane = (long)round_up((size_t)g->S, 64);
+  g->ntiles = (int)((g->S + kSweepBlock - 1) / kSweepBlock);
+  g->elem = elem_bytes(p->storage);
+  g->ncell = 0;
+  for (int k = 0; k < 3; ++k) {
+    g->nc[k] = 0;
+    g->inv_cw[k] = 0.f;
+  }
+  if (p->n_atoms > 0 && p->lj_eps != 0.0f) {
+    g->ncell = 1;
+    for (int k = 0; k < 3; ++k) {
+      // cells at least r_c (plus a 0.1% margin against rounding of wrapped positions) wide
+      g->nc[k] = (int)std::floor((double)p->L[k] / ((double)p->lj_rc * 1.001));
+      if (g->nc[k] < 3) return false;
+      g->inv_cw[k] = (float)((double)g->nc[k] / (double)p->L[k]);
+      g->ncell *= g->nc[k];
+    }
+  }
+  return true;
+}
+
+Layout plan(const lb_params* p, const Geometry& g) {
+  Layout l;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += round_up(bytes, 256);
+    return o;
+  };
+  const size_t N = (size_t)p->n_atoms;
+  const size_t popb = 19 * (size_t)g.plane * g.elem;
+  l.pop[0] = take(popb);
+  l.pop[1] = take(popb);
+  l.fcoup = take(N ? 3 * (size_t)g.plane * 8 : 0);
+  l.tile_flag = take(N ? (size_t)g.ntiles * 4 : 0);
+  l.fext_tab = take((size_t)g.ny * 4);
+  l.fext_field = take(p->bf_kind == LB_BF_FIELD ? 3 * (size_t)g.plane * 4 : 0);
+  l.x0 = take(3 * N * 4);
+  l.disp[0] = take(3 * N * 4);
+  l.disp[1] = take(3 * N * 4);
+  l.vel = take(3 * N * 4);
+  l.fc = take(3 * N * 4);
+  l.bond_off = take((N + 1) * 4);
+  l.bond_nbr = take(2 * (size_t)p->n_bonds * 4);
+  l.cell_count = take((size_t)g.ncell * 4);
+  l.cell_atoms = take((size_t)g.ncell * kCellCap * 4);
+  l.red_partial = take((size_t)kRedBlocks * 4 * 8);
+  l.red_out = take(8 * 8);
+  l.err = take(4 * 4);
+  l.total = off;
+  return l;
+}
+
+static bool finite(float x) { return std::isfinite(x); }
+
+// Returns an empty string when the parameters are valid.
+static std::string validate(const lb_params* p) {
+  char buf[256];
+  if (!p) return "params is NULL";
+  for (int k = 0; k < 3; ++k)
+    if (p->L[k] < 2) {
+      std::snprintf(buf, sizeof buf, "L[%d] = %d: every lattice extent must be >= 2", k, p->L[k]);
+      return buf;
+    }
+  const double S = (double)p->L[0] * p->L[1] * p->L[2];
+  if (S > 2147483647.0) return "lattice has more than 2^31 - 1 sites";
+  if (!finite(p->tau) || !(p->tau > 0.5f)) return "tau must be finite and > 0.5 (nu = (tau - 1/2)/3 > 0)";
+  if (!finite(p->rho0) || !(p->rho0 > 0.0f)) return "rho0 must be finite and > 0";
+  if (p->storage < LB_STORE_F32 || p->storage > LB_STORE_BF16) return "unknown storage format";
+  if (p->bf_kind < LB_BF_NONE || p->bf_kind > LB_BF_FIELD) return "unknown body-force kind";
+  if (!finite(p->bf_amp)) return "bf_amp must be finite";
+  if (p->n_atoms < 0 || p->n_atoms > (1 << 27)) return "n_atoms must be in [0, 2^27]";
+  if (p->n_bonds < 0) return "n_bonds must be >= 0";
+  if (p->n_atoms > 0) {
+    if (!finite(p->mass) || !(p->mass > 0.0f)) return "mass must be finite and > 0";
+    if (!finite(p->gamma) || p->gamma < 0.0f) return "gamma must be finite and >= 0";
+    if (!finite(p->k_tether)) return "k_tether must be finite";
+    if (!finite(p->k_bond) || !finite(p->r0_bond)) return "bond parameters must be finite";
+    if (!finite(p->lj_eps) || p->lj_eps < 0.0f) return "lj_eps must be finite and >= 0";
+    if (p->lj_eps != 0.0f) {
+      if (!finite(p->lj_sigma) || !(p->lj_sigma > 0.0f)) return "lj_sigma must be > 0";
+      if (!finite(p->lj_rc) || !(p->lj_rc > 0.0f)) return "lj_rc must be > 0";
+      for (int k = 0; k < 3; ++k)
+        if (std::floor((double)p->L[k] / ((double)p->lj_rc * 1.001)) < 3) {
+          std::snprintf(buf, sizeof buf,
+                        "L[%d] = %d is shorter than 3 Lennard-Jones cut-offs (%g): the cell list "
+                        "needs 3 cells per axis",
+                        k, p->L[k], (double)p->lj_rc);
+          return buf;
+        }
+    }
+  } else if (p->n_bonds > 0) {
+    return "bonds given without atoms";
+  }
+  return "";
+}
+
+}  // namespace lbmd
+
+using namespace lbmd;
+
+static thread_local std::string g_init_error;
+
+static lb_status fail(lb_ctx* c, lb_status s, const std::string& msg) {
+  if (c)
+    c->err = msg;
+  else
+    g_init_error = msg;
+  return s;
+}
+
+static lb_status hip_fail(lb_ctx* c, hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(c, LB_EDEVICE, m);
+}
+
+extern "C" {
+
+void lb_velocity_set(int8_t c[19][3], double w[19]) {
+  static const double wq[3] = {1.0 / 3.0, 1.0 / 18.0, 1.0 / 36.0};
+  for (int i = 0; i < 19; ++i) {
+    if (c) {
+      c[i][0] = (int8_t)CX[i];
+      c[i][1] = (int8_t)CY[i];
+      c[i][2] = (int8_t)CZ[i];
+    }
+    if (w) w[i] = wq[CX[i] * CX[i] + CY[i] * CY[i] + CZ[i] * CZ[i]];
+  }
+}
+
+size_t lb_workspace_bytes(const lb_params* p) {
+  if (!validate(p).empty()) return 0;
+  Geometry g;
+  if (!geometry(p, &g)) return 0;
+  return plan(p, g).total;
+}
+
+lb_status lb_init(const lb_params* p, void* workspace, size_t workspace_bytes, const float* x0,
+                  const float* v0, const int32_t* bonds, const float* body_force,
+                  void* hip_stream, lb_ctx** out) {
+  if (!out) return fail(nullptr, LB_EINVAL, "out is NULL");
+  *out = nullptr;
+  const std::string why = validate(p);
+  if (!why.empty()) return fail(nullptr, LB_EINVAL, why);
+  Geometry g;
+  if (!geometry(p, &g)) return fail(nullptr, LB_EINVAL, "cell-list geometry is invalid");
+  const Layout lay = plan(p, g);
+  if (!workspace) return fail(nullptr, LB_EINVAL, "workspace is NULL");
+  if ((uintptr_t)workspace % 256 != 0) return fail(nullptr, LB_ENOMEM, "workspace must be 256-byte aligned");
+  if (workspace_bytes < lay.total) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "workspace holds %zu bytes, %zu needed", workspace_bytes, lay.total);
+    return fail(nullptr, LB_ENOMEM, buf);
+  }
+  const int N = p->n_atoms;
+  if (N > 0 && (!x0 || !v0)) return fail(nullptr, LB_EINVAL, "x0 and v0 are required when n_atoms > 0");
+  if (p->n_bonds > 0 && !bonds) return fail(nullptr, LB_EINVAL, "bonds is NULL but n_bonds > 0");
+  if (p->bf_kind == LB_BF_FIELD && !body_force) return fail(nullptr, LB_EINVAL, "body_force field is NULL");
+  hipStream_t st = (hipStream_t)hip_stream;
+
+  // inputs read back once for validation and for the per-atom bond lists
+  std::vector<float> hx(3 * (size_t)N), hv(3 * (size_t)N);
+  std::vector<int32_t> hb(2 * (size_t)p->n_bonds);
+  hipError_t e;
+  if (N > 0) {
+    if ((e = hipMemcpyAsync(hx.data(), x0, hx.size() * 4, hipMemcpyDeviceToHost, st)) != hipSuccess)
+      return hip_fail(nullptr, e, "reading x0");
+    if ((e = hipMemcpyAsync(hv.data(), v0, hv.size() * 4, hipMemcpyDeviceToHost, st)) != hipSuccess)
+      return hip_fail(nullptr, e, "reading v0");
+  }
+  if (p->n_bonds > 0 &&
+      (e = hipMemcpyAsync(hb.data(), bonds, hb.size() * 4, hipMemcpyDeviceToHost, st)) != hipSuccess)
+    return hip_fail(nullptr, e, "reading bonds");
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(nullptr, e, "synchronising");
+  for (size_t k = 0; k < hx.size(); ++k) {
+    if (!std::isfinite(hx[k]) || std::fabs(hx[k]) > 1.0e6f)
+      return fail(nullptr, LB_EINVAL, "x0 holds a non-finite or out-of-range (|x| > 1e6) coordinate");
+    if (!std::isfinite(hv[k])) return fail(nullptr, LB_EINVAL, "v0 holds a non-finite value");
+  }
+  std::vector<int32_t> off(N + 1, 0), nbr(2 * (size_t)p->n_bonds);
+  for (int b = 0; b < p->n_bonds; ++b) {
+    const int i = hb[2 * b], j = hb[2 * b + 1];
+    if (i < 0 || i >= N || j < 0 || j >= N || i == j) {
+      char buf[128];
+      std::snprintf(buf, sizeof buf, "bond %d = (%d, %d) is not a pair of distinct atoms", b, i, j);
+      return fail(nullptr, LB_EINVAL, buf);
+    }
+    off[i + 1]++;
+    off[j + 1]++;
+  }
+  for (int i = 0; i < N; ++i) off[i + 1] += off[i];
+  {
+    std::vector<int32_t> fill(off.begin(), off.end() - 1);
+    for (int b = 0; b < p->n_bonds; ++b) {
+      const int i = hb[2 * b], j = hb[2 * b + 1];
+      nbr[fill[i]++] = j;
+      nbr[fill[j]++] = i;
+    }
+  }
+  std::vector<float> tab(g.ny, 0.0f);
+  for (int y = 0; y < g.ny; ++y) {
+    if (p->bf_kind == LB_BF_KOLMOGOROV) {
+      tab[y] = (float)((double)p->bf_amp * std::sin(2.0 * M_PI * (double)y / (double)g.ny));
+    } else if (p->bf_kind == LB_BF_SIGN_SHEAR) {
+      const double a = (double)y + 0.5 - 0.5 * (double)g.ny;
+      tab[y] = (float)((double)p->bf_amp * (a > 0 ? 1.0 : (a < 0 ? -1.0 : 0.0)));
+    }
+  }
+
+  lb_ctx* c = new (std::nothrow) lb_ctx();
+  if (!c) return fail(nullptr, LB_ENOMEM, "host allocation failed");
+  c->p = *p;
+  c->geo = g;
+  c->lay = lay;
+  c->stream = st;
+  c->ws = (char*)workspace;
+  c->cur = 0;
+  c->dcur = 0;
+  c->step = 0;
+  c->omega = 1.0f / p->tau;
+
+  char* ws = c->ws;
+  // zero everything the step relies on being zero
+  const size_t popb = 19 * (size_t)g.plane * g.elem;
+  struct Z { size_t off, bytes; } zs[] = {
+      {lay.pop[0], popb}, {lay.pop[1], popb},
+      {lay.fcoup, N ? 3 * (size_t)g.plane * 8 : 0}, {lay.tile_flag, N ? (size_t)g.ntiles * 4 : 0},
+      {lay.disp[0], 12 * (size_t)N}, {lay.disp[1], 12 * (size_t)N}, {lay.fc, 12 * (size_t)N},
+      {lay.cell_count, (size_t)g.ncell * 4}, {lay.err, 16},
+      {lay.fext_field, p->bf_kind == LB_BF_FIELD ? 3 * (size_t)g.plane * 4 : 0}};
+  for (const Z& z : zs)
+    if (z.bytes && (e = launch_zero(ws + z.off, round_up(z.bytes, 4), st)) != hipSuccess) {
+      delete c;
+      return hip_fail(nullptr, e, "clearing the workspace");
+    }
+  auto h2d = [&](size_t o, const void* src, size_t bytes) {
+    return bytes ? hipMemcpyAsync(ws + o, src, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
+  };
+  auto d2d = [&](size_t o, const void* src, size_t bytes) {
+    return bytes ? hipMemcpyAsync(ws + o, src, bytes, hipMemcpyDeviceToDevice, st) : hipSuccess;
+  };
+  if ((e = d2d(lay.x0, x0, 12 * (size_t)N)) != hipSuccess ||
+      (e = d2d(lay.vel, v0, 12 * (size_t)N)) != hipSuccess ||
+      (e = h2d(lay.fext_tab, tab.data(), 4 * (size_t)g.ny)) != hipSuccess ||
+      (e = h2d(lay.bond_off, off.data(), 4 * off.size())) != hipSuccess ||
+      (e = h2d(lay.bond_nbr, nbr.data(), 4 * nbr.size())) != hipSuccess) {
+    delete c;
+    return hip_fail(nullptr, e, "copying inputs");
+  }
+  if (p->bf_kind == LB_BF_FIELD)
+    for (int k = 0; k < 3; ++k)
+      if ((e = d2d(lay.fext_field + 4 * (size_t)k * g.plane, body_force + (size_t)k * g.S,
+                   4 * (size_t)g.S)) != hipSuccess) {
+        delete c;
+        return hip_fail(nullptr, e, "copying the body-force field");
+      }
+  // the host vectors must outlive the copies
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) {
+    delete c;
+    return hip_fail(nullptr, e, "synchronising after set-up");
+  }
+  *out = c;
+  return LB_OK;
+}
+
+lb_status lb_couple_step(lb_ctx* c, int32_t n_steps) {
+  if (!c) return fail(nullptr, LB_EINVAL, "context is NULL");
+  if (n_steps < 0) return fail(c, LB_EINVAL, "n_steps must be >= 0");
+  const bool atoms = c->p.n_atoms > 0;
+  const bool lj = c->geo.ncell > 0;
+  hipError_t e;
+  for (int n = 0; n < n_steps; ++n) {
+    hipEvent_t* ev = c->timed < c->timed_cap ? &c->ev[4 * (size_t)c->timed] : nullptr;
+    if (ev) c->timed++;
+    if (ev) (void)hipEventRecord(ev[0], c->stream);
+    if (atoms) {
+      if ((e = launch_prep(c)) != hipSuccess) return hip_fail(c, e, "prep launch");
+      if ((e = launch_couple(c)) != hipSuccess) return hip_fail(c, e, "coupling launch");
+      if (lj && (e = launch_cell_sort(c)) != hipSuccess) return hip_fail(c, e, "cell sort launch");
+    }
+    if (ev) (void)hipEventRecord(ev[1], c->stream);
+    if ((e = launch_sweep(c, c->ws + c->lay.pop[c->cur], c->ws + c->lay.pop[c->cur ^ 1])) != hipSuccess)
+      return hip_fail(c, e, "sweep launch");
+    if (ev) (void)hipEventRecord(ev[2], c->stream);
+    if (atoms && (e = launch_forces_integrate(c)) != hipSuccess)
+      return hip_fail(c, e, "force/integrate launch");
+    if (ev) (void)hipEventRecord(ev[3], c->stream);
+    c->cur ^= 1;
+    if (atoms) c->dcur ^= 1;
+    c->step++;
+    if (c->p.flags & LB_FLAG_CHECK_FINITE) {
+      lb_status s = lb_status_check(c);
+      if (s != LB_OK) return s;
+    }
+  }
+  return LB_OK;
+}
+
+lb_status lb_read_fields(lb_ctx* c, float* rho, float* u, float* x_unwrapped, float* v) {
+  if (!c) return fail(nullptr, LB_EINVAL, "context is NULL");
+  hipError_t e;
+  if ((rho || u) && (e = launch_read_fields(c, rho, u)) != hipSuccess) return hip_fail(c, e, "readback launch");
+  if (c->p.n_atoms > 0 && (x_unwrapped || v) && (e = launch_read_atoms(c, x_unwrapped, v)) != hipSuccess)
+    return hip_fail(c, e, "atom readback launch");
+  return LB_OK;
+}
+
+lb_status lb_read_populations(lb_ctx* c, float* g) {
+  if (!c) return fail(nullptr, LB_EINVAL, "context is NULL");
+  if (!g) return fail(c, LB_EINVAL, "output is NULL");
+  hipError_t e = launch_read_populations(c, g);
+  return e == hipSuccess ? LB_OK : hip_fail(c, e, "population readback launch");
+}
+
+lb_status lb_set_populations(lb_ctx* c, const float* g) {
+  if (!c) return fail(nullptr, LB_EINVAL, "context is NULL");
+  if (!g) return fail(c, LB_EINVAL, "input is NULL");
+  hipError_t e = launch_write_populations(c, g);
+  return e == hipSuccess ? LB_OK : hip_fail(c, e, "population upload launch");
+}
+
+lb_status lb_status_check(lb_ctx* c) {
+  if (!c) return fail(nullptr, LB_EINVAL, "context is NULL");
+  uint32_t err[4] = {0, 0, 0, 0};
+  hipError_t e = hipMemcpyAsync(err, c->ws + c->lay.err, sizeof err, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "status read");
+  if (err[0] & kErrOverflow)
+    return fail(c, LB_EOVERFLOW, "a neighbour-list cell overflowed (atoms packed beyond any physical density)");
+  if (err[0] & kErrNonFinite) return fail(c, LB_ENONFINITE, "a NaN or Inf appeared in the state");
+  return LB_OK;
+}
+
+lb_status lb_invariants(lb_ctx* c, double out7[7]) {
+  if (!c) return fail(nullptr, LB_EINVAL, "context is NULL");
+  if (!out7) return fail(c, LB_EINVAL, "out7 is NULL");
+  hipError_t e = launch_invariants(c);
+  if (e != hipSuccess) return hip_fail(c, e, "invariants launch");
+  double h[8];
+  e = hipMemcpyAsync(h, c->ws + c->lay.red_out, sizeof h, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "invariants read");
+  for (int k = 0; k < 7; ++k) out7[k] = h[k];
+  return lb_status_check(c);
+}
+
+int64_t lb_step_count(const lb_ctx* c) { return c ? c->step : -1; }
+
+// snapshot layout: [256-byte header: int64 step][populations][displacement][velocity]
+static size_t state_pop_bytes(const lb_ctx* c) { return 19 * (size_t)c->geo.plane * c->geo.elem; }
+
+size_t lb_state_bytes(const lb_ctx* c) {
+  if (!c) return 0;
+  return 256 + round_up(state_pop_bytes(c), 256) + 2 * round_up(12 * (size_t)c->p.n_atoms, 256);
+}
+
+lb_status lb_state_save(lb_ctx* c, void* dst) {
+  if (!c) return fail(nullptr, LB_EINVAL, "context is NULL");
+  if (!dst || (uintptr_t)dst % 256) return fail(c, LB_EINVAL, "dst must be a 256-byte aligned device buffer");
+  char* d = (char*)dst;
+  const size_t pb = round_up(state_pop_bytes(c), 256), ab = round_up(12 * (size_t)c->p.n_atoms, 256);
+  hipError_t e = launch_store_i64(d, c->step, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d + 256, c->ws + c->lay.pop[c->cur], state_pop_bytes(c), hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess && c->p.n_atoms > 0) {
+    e = hipMemcpyAsync(d + 256 + pb, c->ws + c->lay.disp[c->dcur], 12 * (size_t)c->p.n_atoms,
+                       hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d + 256 + pb + ab, c->ws + c->lay.vel, 12 * (size_t)c->p.n_atoms,
+                         hipMemcpyDeviceToDevice, c->stream);
+  }
+  return e == hipSuccess ? LB_OK : hip_fail(c, e, "state save");
+}
+
+lb_status lb_state_load(lb_ctx* c, const void* src) {
+  if (!c) return fail(nullptr, LB_EINVAL, "context is NULL");
+  if (!src || (uintptr_t)src % 256) return fail(c, LB_EINVAL, "src must be a 256-byte aligned device buffer");
+  const char* s = (const char*)src;
+  const size_t pb = round_up(state_pop_bytes(c), 256), ab = round_up(12 * (size_t)c->p.n_atoms, 256);
+  int64_t step = 0;
+  hipError_t e = hipMemcpyAsync(&step, s, 8, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->ws + c->lay.pop[c->cur], s + 256, state_pop_bytes(c), hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess && c->p.n_atoms > 0) {
+    e = hipMemcpyAsync(c->ws + c->lay.disp[c->dcur], s + 256 + pb, 12 * (size_t)c->p.n_atoms,
+                       hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->ws + c->lay.vel, s + 256 + pb + ab, 12 * (size_t)c->p.n_atoms,
+                         hipMemcpyDeviceToDevice, c->stream);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "state load");
+  c->step = step;
+  return LB_OK;
+}
+
+static void free_events(lb_ctx* c) {
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  c->ev.clear();
+  c->timed_cap = c->timed = 0;
+}
+
+lb_status lb_timing_begin(lb_ctx* c, int32_t max_steps) {
+  if (!c) return fail(nullptr, LB_EINVAL, "context is NULL");
+  if (max_steps < 0 || max_steps > (1 << 20)) return fail(c, LB_EINVAL, "max_steps must be in [0, 2^20]");
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "synchronising");
+  free_events(c);
+  c->ev.resize(4 * (size_t)max_steps);
+  for (size_t k = 0; k < c->ev.size(); ++k)
+    if ((e = hipEventCreate(&c->ev[k])) != hipSuccess) {
+      c->ev.resize(k);
+      free_events(c);
+      return hip_fail(c, e, "creating timing events");
+    }
+  c->timed_cap = max_steps;
+  c->timed = 0;
+  return LB_OK;
+}
+
+lb_status lb_timing_end(lb_ctx* c, double out_ms[3]) {
+  if (!c) return fail(nullptr, LB_EINVAL, "context is NULL");
+  if (!out_ms) return fail(c, LB_EINVAL, "out_ms is NULL");
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "synchronising");
+  double sweep = 0.0, atoms = 0.0;
+  for (int k = 0; k < c->timed; ++k) {
+    float a = 0.f, b = 0.f, d = 0.f;
+    hipEvent_t* ev = &c->ev[4 * (size_t)k];
+    if ((e = hipEventElapsedTime(&a, ev[0], ev[1])) != hipSuccess ||
+        (e = hipEventElapsedTime(&b, ev[1], ev[2])) != hipSuccess ||
+        (e = hipEventElapsedTime(&d, ev[2], ev[3])) != hipSuccess)
+      return hip_fail(c, e, "reading timing events");
+    sweep += b;
+    atoms += a + d;
+  }
+  out_ms[0] = sweep;
+  out_ms[1] = atoms;
+  out_ms[2] = c->timed;
+  free_events(c);
+  return LB_OK;
+}
+
+lb_status lb_destroy(lb_ctx* c) {
+  if (!c) return fail(nullptr, LB_EINVAL, "context is NULL");
+  free_events(c);
+  delete c;
+  return LB_OK;
+}
+
+const char* lb_last_error(const lb_ctx* c) { return c ? c->err.c_str() : g_init_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,61 @@
+"""Helpers shared by the GPU parity tests: run a workload through the HIP library (via the
+C interface) and through the CPU oracle, and compare."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+
+def say(*a):
+    """Print the case being run and flush, so a failing GPU step names itself."""
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def gpu_run(w, steps, storage="f32", g0=None, chunks=None):
+    """Run a workload on cuda:0; returns observables as float64 numpy arrays."""
+    import torch
+    from paper_2305_05025_amd.coupled import CoupledLB
+    say("gpu_run", w.name, w.L, "atoms", w.n_atoms, "steps", steps, storage)
+    sim = CoupledLB.from_workload(w, storage=storage, device="cuda:0")
+    if g0 is not None:
+        sim.set_populations(np.asarray(g0, np.float32))
+    for n in (chunks or [steps]):
+        sim.step(n)
+    rho, u, x, v = sim.read_fields()
+    g = sim.populations()
+    inv = sim.invariants()
+    torch.cuda.synchronize()
+    out = dict(rho=rho.double().cpu().numpy(), u=u.double().cpu().numpy(),
+               x=x.double().cpu().numpy(), v=v.double().cpu().numpy(),
+               g=g.double().cpu().numpy(), inv=np.array(inv), steps=sim.step_count)
+    sim.close()
+    return out
+
+
+def oracle_run(O, w, steps, g0=None, precision="f64"):
+    p = O.params_from_workload(w)
+    g = np.zeros(O.pop_shape(p)) if g0 is None else np.asarray(g0, np.float64)
+    field = w.body_force
+    g1, X1, V1 = O.run(p, g, w.x0, w.v0, w.x0, w.bonds, field, steps, precision=precision)
+    rho, u = O.observables(p, g1, field)
+    return dict(rho=rho, u=u, x=X1, v=V1, g=g1, inv=O.invariants(p, g1, V1))
+
+
+def compare(gp, orc, w):
+    x0 = w.x0.astype(np.float64)
+    r = dict(u=rel_l2(gp["u"], orc["u"]),
+             rho=rel_l2(gp["rho"] - w.rho0, orc["rho"] - w.rho0),
+             g=rel_l2(gp["g"], orc["g"]))
+    if w.n_atoms:
+        r["disp"] = rel_l2(gp["x"] - x0, orc["x"] - x0)
+        r["v"] = rel_l2(gp["v"], orc["v"])
+    return r

@@ -1,0 +1,100 @@
+"""The C interface on the CPU: the library loads, exports every entry point the header
+declares, and rejects invalid arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2305_05025_amd import _abi as A
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "lbmd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lb_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_symbols()
+    assert "lb_init" in names and "lb_couple_step" in names and "lb_read_fields" in names
+    lib = ctypes.CDLL(A.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    bound = {s[0] for s in A._SIGS}
+    assert set(names) <= bound, set(names) - bound
+
+
+def test_velocity_set_matches_oracle_ordering(O):
+    c, w = A.lb_velocity_set()
+    co, wo = O.velocity_set()
+    assert np.array_equal(np.array(c), co)
+    np.testing.assert_array_equal(np.array(w), wo)
+
+
+def _params(**kw):
+    from paper_2305_05025_amd.coupled import make_params
+    d = dict(L=16, tau=0.8, n_atoms=10, mass=8.0, gamma=0.1, lj_eps=0.01)
+    d.update(kw)
+    return make_params(**d)
+
+
+def test_workspace_bytes():
+    small = A.lb_workspace_bytes(_params(L=16))
+    big = A.lb_workspace_bytes(_params(L=32))
+    assert 0 < small < big
+    assert A.lb_workspace_bytes(_params(L=32, storage="f16")) < big
+    # populations dominate: two FP32 buffers of 19 planes
+    assert big > 2 * 19 * 32 ** 3 * 4
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(tau=0.5), "tau"),
+    (dict(tau=float("nan")), "tau"),
+    (dict(rho0=0.0), "rho0"),
+    (dict(L=(16, 1, 16)), "L[1]"),
+    (dict(storage=7), "storage"),
+    (dict(bf_kind=9), "body-force"),
+    (dict(mass=0.0), "mass"),
+    (dict(gamma=-1.0), "gamma"),
+    (dict(L=(16, 16, 7)), "cut-offs"),
+    (dict(n_atoms=0, n_bonds=3), "bonds"),
+    (dict(n_atoms=-1), "n_atoms"),
+])
+def test_invalid_parameters_rejected_before_device_work(kw, msg):
+    p = _params(**kw)
+    assert A.lb_workspace_bytes(p) == 0
+    with pytest.raises(A.LBError) as e:
+        A.lb_init(p, 0, 0, 0, 0, 0, 0, 0)
+    assert e.value.status == A.LB_EINVAL
+    assert msg in str(e.value)
+
+
+def test_workspace_checks():
+    p = _params()
+    need = A.lb_workspace_bytes(p)
+    with pytest.raises(A.LBError) as e:
+        A.lb_init(p, 0, need, 0, 0, 0, 0, 0)
+    assert e.value.status == A.LB_EINVAL
+    with pytest.raises(A.LBError) as e:      # misaligned (never dereferenced)
+        A.lb_init(p, 0x10000 + 8, need, 0, 0, 0, 0, 0)
+    assert e.value.status == A.LB_ENOMEM
+    with pytest.raises(A.LBError) as e:      # too small (never dereferenced)
+        A.lb_init(p, 0x10000, need - 256, 0, 0, 0, 0, 0)
+    assert e.value.status == A.LB_ENOMEM and "needed" in str(e.value)
+    with pytest.raises(A.LBError) as e:      # atoms without positions
+        A.lb_init(p, 0x10000, need, 0, 0, 0, 0, 0)
+    assert e.value.status == A.LB_EINVAL and "x0" in str(e.value)
+
+
+def test_null_context_calls():
+    lib = A.lib()
+    assert lib.lb_couple_step(None, 1) == A.LB_EINVAL
+    assert lib.lb_read_fields(None, None, None, None, None) == A.LB_EINVAL
+    assert lib.lb_destroy(None) == A.LB_EINVAL
+    assert lib.lb_step_count(None) == -1
+    assert lib.lb_state_bytes(None) == 0
+    assert "NULL" in A.lb_last_error(None)

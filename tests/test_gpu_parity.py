@@ -1,0 +1,223 @@
+"""Parity of the HIP path (through the C interface) with the CPU oracle.
+
+Tolerances (FP32 deviation storage, FP32 arithmetic, against the FP64 oracle):
+  * lattice-only and non-chaotic coupled runs: rel. L2 <= 1e-5 on u, rho - rho0, populations,
+    atom displacement and velocity, after 100 steps;
+  * runs with Lennard-Jones: the atom trajectories are chaotic (a rounding-level difference
+    doubles about every 9 steps, measured with the oracle itself in FP32 vs FP64), so the
+    1e-5 gate applies up to 20 steps; at 100 steps the GPU must stay within the spread that
+    an FP32-level perturbation of the initial velocities produces in the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import compare, gpu_run, oracle_run, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _random_state(O, p, seed, amp=1e-3):
+    rng = np.random.default_rng(seed)
+    g = rng.normal(0.0, amp, size=O.pop_shape(p))
+    return g.astype(np.float32).astype(np.float64)
+
+
+# ------------------------------------------------------------------ lattice alone
+
+@pytest.mark.parametrize("L,bf", [((13, 11, 9), 1), ((16, 16, 16), 2), ((24, 10, 7), 3)])
+def test_sweep_from_random_state(O, L, bf):
+    """Random non-equilibrium state on ragged lattices (tiles with a partial tail), all three
+    body-force kinds; 1 and 10 steps."""
+    from workloads import small_workload
+    w = small_workload(L, 0, seed=1, tau=0.7, steps=0, bf_kind=bf, bf_amp=3e-5)
+    if bf == 3:
+        rng = np.random.default_rng(11)
+        w.body_force = rng.normal(0, 1e-5, size=(3, L[2], L[1], L[0])).astype(np.float32)
+    p = O.params_from_workload(w)
+    g0 = _random_state(O, p, seed=5)
+    for steps in (1, 10):
+        gp = gpu_run(w, steps, g0=g0)
+        orc = oracle_run(O, w, steps, g0=g0)
+        r = compare(gp, orc, w)
+        say(L, bf, steps, r)
+        assert r["g"] < 1e-6 and r["u"] < 1e-6 and r["rho"] < 1e-6, r
+
+
+def test_shear_wave_and_kolmogorov_100_steps(O):
+    from workloads import small_workload
+    w = small_workload((8, 32, 8), 0, seed=1, tau=0.6, steps=0, bf_kind=1, bf_amp=1e-6)
+    p = O.params_from_workload(w)
+    g0 = np.zeros(O.pop_shape(p))
+    for y in range(32):
+        g0[:, :, y, :] = O.equilibrium(1.0, 0.0, [1e-3 * np.sin(2 * np.pi * y / 32), 0, 0])[:, None, None]
+    g0 = g0.astype(np.float32).astype(np.float64)
+    gp = gpu_run(w, 100, g0=g0)
+    orc = oracle_run(O, w, 100, g0=g0)
+    r = compare(gp, orc, w)
+    say("shear+kolmogorov", r)
+    assert r["u"] < 1e-5 and r["g"] < 1e-5, r
+
+
+@pytest.mark.parametrize("storage,rel", [("f16", 2.0 ** -11), ("bf16", 2.0 ** -8)])
+def test_narrow_storage_one_step(O, storage, rel):
+    """One step from a state representable in the format: each stored value is the FP32
+    collision result rounded once to the format (within half an ulp of the format)."""
+    import torch
+    from workloads import small_workload
+    L = (12, 10, 9)
+    w = small_workload(L, 0, seed=1, tau=0.7, steps=0, bf_kind=1, bf_amp=1e-5)
+    p = O.params_from_workload(w)
+    g0 = _random_state(O, p, seed=9)
+    dt = torch.float16 if storage == "f16" else torch.bfloat16
+    g0 = torch.tensor(g0).to(dt).double().numpy()
+    gp = gpu_run(w, 1, storage=storage, g0=g0)
+    orc = oracle_run(O, w, 1, g0=g0)
+    err = np.abs(gp["g"] - orc["g"])
+    tiny = 2.0 ** -24 if storage == "f16" else 0.0   # f16 subnormal spacing
+    bound = rel * np.abs(orc["g"]) + tiny + 1e-9
+    say(storage, "max err/bound", float((err / bound).max()))
+    assert (err <= bound).all()
+
+
+# ------------------------------------------------------------------ coupled: configuration 0
+
+def _c0(lj=True):
+    from workloads import make_workload
+    w = make_workload(0)
+    if not lj:
+        w.lj_eps = 0.0
+        w.name += "_nolj"
+    return w
+
+
+@pytest.mark.parametrize("steps", [1, 10, 20])
+def test_config0_short_horizon(O, steps):
+    w = _c0()
+    r = compare(gpu_run(w, steps), oracle_run(O, w, steps), w)
+    say("c0", steps, r)
+    assert max(r.values()) < 1e-5, r
+
+
+def test_config0_without_lj_100_steps(O):
+    """Tethers + friction only: linear, non-chaotic dynamics; the 1e-5 gate at 100 steps."""
+    w = _c0(lj=False)
+    r = compare(gpu_run(w, 100), oracle_run(O, w, 100), w)
+    say("c0 no LJ 100", r)
+    assert max(r.values()) < 1e-5, r
+
+
+def test_config0_100_steps_within_chaotic_spread(O):
+    w = _c0()
+    orc = oracle_run(O, w, 100)
+    # spread of the FP64 scheme itself under an FP32-sized perturbation of v0
+    rng = np.random.default_rng(17)
+    wp = _c0()
+    wp.v0 = (w.v0.astype(np.float64) * (1 + 2.0 ** -24 * rng.choice([-1, 1], size=w.v0.shape)))
+    spread = compare(oracle_run(O, wp, 100), orc, w)
+    r = compare(gpu_run(w, 100), orc, w)
+    say("c0 100 gpu", r, "fp64 spread", spread)
+    for k in r:
+        assert r[k] < max(50 * spread[k], 1e-5), (k, r[k], spread[k])
+
+
+# ------------------------------------------------------------------ coupled: globules
+
+def _globule(L=(40, 36, 30), n=1500, bf=1, seed=6):
+    from workloads import globule_workload
+    w = globule_workload(L, 1, n, seed=seed, tau=0.6, gamma=0.2, name="glob%d" % n,
+                         bf_kind=bf, bf_amp=1e-6 if bf == 1 else 0.0)
+    if bf == 3:
+        rng = np.random.default_rng(seed)
+        w.body_force = rng.normal(0, 1e-6, size=(3, L[2], L[1], L[0])).astype(np.float32)
+    return w
+
+
+@pytest.mark.parametrize("bf", [1, 3])
+def test_globule_short_horizon(O, bf):
+    """Bonds, bonded-pair LJ exclusion, body force, ragged lattice."""
+    w = _globule(bf=bf)
+    for steps in (1, 10):
+        r = compare(gpu_run(w, steps), oracle_run(O, w, steps), w)
+        say("globule", bf, steps, r)
+        assert max(r.values()) < 1e-5, r
+
+
+def test_momentum_and_mass_ledger_on_gpu(O):
+    """No tethers, no net body force: total (fluid + atom) momentum and mass are conserved
+    by the GPU step to rounding, measured by the library's FP64 sums."""
+    w = _globule(bf=0, n=800, L=(24, 24, 24))
+    import torch
+    from paper_2305_05025_amd.coupled import CoupledLB
+    sim = CoupledLB.from_workload(w)
+    inv0 = np.array(sim.invariants())
+    orc0 = O.invariants(O.params_from_workload(w), np.zeros(O.pop_shape(O.params_from_workload(w))), w.v0)
+    np.testing.assert_allclose(inv0, orc0, rtol=1e-7, atol=1e-12)
+    for _ in range(5):
+        sim.step(10)
+        inv = np.array(sim.invariants())
+        say("ledger", inv)
+        assert abs(inv[0] - inv0[0]) < 1e-9 * inv0[0]
+        p_tot = inv[1:4] + inv[4:7]
+        assert np.abs(p_tot - (inv0[1:4] + inv0[4:7])).max() < 1e-6
+    sim.close()
+
+
+def test_determinism_and_checkpoint(O):
+    """Two runs are bitwise identical; save/continue equals load/continue bitwise."""
+    from paper_2305_05025_amd.coupled import CoupledLB
+    w = _globule(n=1000, L=(32, 32, 32))
+    a = CoupledLB.from_workload(w)
+    b = CoupledLB.from_workload(w)
+    a.step(15)
+    b.step(15)
+    snap = a.save_state()
+    a.step(15)
+    b.step(15)
+    ga, gb = a.populations(), b.populations()
+    _, _, xa, va = a.read_fields()
+    _, _, xb, vb = b.read_fields()
+    assert (ga == gb).all() and (xa == xb).all() and (va == vb).all()
+    a.load_state(snap)
+    assert a.step_count == 15
+    a.step(15)
+    _, _, xc, vc = a.read_fields()
+    assert (a.populations() == gb).all() and (xc == xb).all() and (vc == vb).all()
+    assert a.step_count == 30
+    a.close()
+    b.close()
+
+
+def test_error_paths_on_device():
+    import torch
+    from paper_2305_05025_amd import _abi as A
+    from paper_2305_05025_amd.coupled import CoupledLB, make_params
+    x = torch.tensor([[4.0, 4.0, 4.0], [float("nan"), 1.0, 1.0]])
+    v = torch.zeros(2, 3)
+    with pytest.raises(A.LBError) as e:
+        CoupledLB(make_params(12, 0.8, n_atoms=2, mass=8.0), x, v)
+    assert e.value.status == A.LB_EINVAL and "x0" in str(e.value)
+    x = torch.tensor([[4.0, 4.0, 4.0], [5.0, 5.0, 5.0]])
+    with pytest.raises(A.LBError) as e:
+        CoupledLB(make_params(12, 0.8, n_atoms=2, mass=8.0, n_bonds=1), x, v,
+                  bonds=torch.tensor([[0, 2]], dtype=torch.int32))
+    assert e.value.status == A.LB_EINVAL and "bond" in str(e.value)
+    # 60 atoms inside one neighbour-list cell: the capacity check latches an overflow
+    rng = np.random.default_rng(0)
+    # (12 / floor(12 / 2.5025) = 3-wide cells: [3.2, 5.8]^3 lies inside cell (1, 1, 1))
+    xs = torch.tensor(3.2 + rng.uniform(0, 2.6, size=(60, 3)), dtype=torch.float32)
+    sim = CoupledLB(make_params(12, 0.8, n_atoms=60, mass=8.0, lj_eps=1e-9), xs, torch.zeros(60, 3))
+    sim.step(1)
+    with pytest.raises(A.LBError) as e:
+        sim.check()
+    assert e.value.status == A.LB_EOVERFLOW
+    sim.close()
+    # a NaN population is reported after the next step
+    sim = CoupledLB(make_params(8, 0.8))
+    g = np.zeros((19, 8, 8, 8), np.float32)
+    g[3, 2, 2, 2] = np.nan
+    sim.set_populations(g)
+    sim.step(1)
+    with pytest.raises(A.LBError) as e:
+        sim.check()
+    assert e.value.status == A.LB_ENONFINITE
+    sim.close()
