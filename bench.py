@@ -87,7 +87,8 @@ def run(args):
     t0 = time.time()
     w = make_workload(args.config)
     log("workload %s: lattice %s, %d atoms, built in %.1f s" % (w.name, w.L, w.n_atoms, time.time() - t0))
-    sim = CoupledLB.from_workload(w, storage=args.storage, device=dev)
+    flags = A.LB_FLAG_SINGLE_STREAM if args.single_stream else 0
+    sim = CoupledLB.from_workload(w, storage=args.storage, device=dev, flags=flags)
     stream = sim.stream
     sim.step(args.warmup)
     sim.check()
@@ -135,7 +136,8 @@ def run(args):
         "dtype": args.storage,
         "data": "synthetic",
         "config": {"workload": w.name, "lattice": list(w.L), "atoms": w.n_atoms,
-                   "storage": args.storage, "tau": w.tau, "steps_per_call": args.steps},
+                   "storage": args.storage, "tau": w.tau, "steps_per_call": args.steps,
+                   "streams": 1 if args.single_stream else 2},
         "hbm_gbs_step": round(step_gbs, 1),
         "hbm_frac_step": round(step_gbs / HBM_PEAK_GBS, 4),
         "coupling_share": round(atom_ms / (atom_ms + sweep_ms), 4),
@@ -175,6 +177,8 @@ def main():
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--single-stream", action="store_true",
+                    help="queue every kernel on one stream (no overlap of atom and lattice work)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the multi-GPU (domain-decomposed) path is not "

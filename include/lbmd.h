@@ -76,6 +76,9 @@ typedef enum {
 
 /* lb_params.flags */
 #define LB_FLAG_CHECK_FINITE 0x1u  /* lb_couple_step also checks for NaN/Inf every step */
+#define LB_FLAG_SINGLE_STREAM 0x2u /* queue every kernel on the caller's stream; by default the
+                                      atom work runs on a second stream of the library and
+                                      overlaps the sweep of the sites no atom touches */
 
 typedef struct {
   int32_t L[3];              /* nx, ny, nz >= 2; periodic */
@@ -136,6 +139,11 @@ lb_status lb_couple_step(lb_ctx* c, int32_t n_steps);
  * NULL.  Asynchronous. */
 lb_status lb_read_fields(lb_ctx* c, float* rho, float* u, float* x_unwrapped, float* v);
 
+/* Atom displacements X - x0 [N][3] (device pointer): the quantity the library integrates,
+ * at full FP32 precision (an unwrapped position x0 + d rounded to FP32 loses the low bits
+ * of small displacements).  Asynchronous. */
+lb_status lb_read_displacement(lb_ctx* c, float* d);
+
 /* Raw populations of the current pre-collision state as float32 deviations g_i
  * [19][S] (device pointer), in the lb_velocity_set ordering.  Asynchronous. */
 lb_status lb_read_populations(lb_ctx* c, float* g);
@@ -166,8 +174,9 @@ lb_status lb_state_load(lb_ctx* c, const void* src);
 /* Kernel timing with HIP events recorded on the context's stream around each phase of
  * the next max_steps steps (creates 4 * max_steps events).  lb_timing_end synchronises and
  * writes out_ms[0] = summed duration of the lattice sweep kernels, out_ms[1] = summed
- * duration of the atom kernels (binning, coupling, forces and integration), out_ms[2] =
- * number of steps timed (milliseconds; host pointer). */
+ * duration of the atom kernels (binning, coupling, forces and integration; they overlap
+ * the sweep unless LB_FLAG_SINGLE_STREAM is set), out_ms[2] = number of steps timed
+ * (milliseconds; host pointer). */
 lb_status lb_timing_begin(lb_ctx* c, int32_t max_steps);
 lb_status lb_timing_end(lb_ctx* c, double out_ms[3]);
 

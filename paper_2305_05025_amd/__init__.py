@@ -13,6 +13,7 @@ from ._abi import (  # noqa: F401
     lb_invariants,
     lb_last_error,
     lb_read_fields,
+    lb_read_displacement,
     lb_read_populations,
     lb_set_populations,
     lb_state_bytes,

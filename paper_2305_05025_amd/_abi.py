@@ -16,6 +16,7 @@ LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_ESTATE, LB_ENONFINITE, LB_EOVERFLOW 
 LB_STORE_F32, LB_STORE_F16, LB_STORE_BF16 = 0, 1, 2
 LB_BF_NONE, LB_BF_KOLMOGOROV, LB_BF_SIGN_SHEAR, LB_BF_FIELD = 0, 1, 2, 3
 LB_FLAG_CHECK_FINITE = 0x1
+LB_FLAG_SINGLE_STREAM = 0x2
 
 STATUS_NAMES = {0: "LB_OK", 1: "LB_EINVAL", 2: "LB_ENOMEM", 3: "LB_EDEVICE", 4: "LB_ESTATE",
                 5: "LB_ENONFINITE", 6: "LB_EOVERFLOW"}
@@ -61,6 +62,7 @@ _SIGS = [
                                ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     ("lb_couple_step", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     ("lb_read_fields", ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4),
+    ("lb_read_displacement", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("lb_read_populations", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("lb_set_populations", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("lb_invariants", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
@@ -130,6 +132,10 @@ def lb_couple_step(ctx, n_steps: int):
 
 def lb_read_fields(ctx, rho: int = 0, u: int = 0, x: int = 0, v: int = 0):
     _check(lib().lb_read_fields(ctx, rho or None, u or None, x or None, v or None), ctx)
+
+
+def lb_read_displacement(ctx, d: int):
+    _check(lib().lb_read_displacement(ctx, d or None), ctx)
 
 
 def lb_read_populations(ctx, g: int):

@@ -107,6 +107,14 @@ class CoupledLB:
         self.stream.synchronize()
         return rho, u, x, v
 
+    def displacement(self):
+        """X - x0 [N, 3] (the integrated displacement, full FP32 precision)."""
+        d = torch.empty((self.N, 3), dtype=torch.float32, device=self.device)
+        if self.N:
+            A.lb_read_displacement(self.ctx, d.data_ptr())
+            self.stream.synchronize()
+        return d
+
     def populations(self):
         """Pre-collision deviations g [19, nz, ny, nx] (float32)."""
         g = torch.empty((19, self.L[2], self.L[1], self.L[0]), dtype=torch.float32, device=self.device)

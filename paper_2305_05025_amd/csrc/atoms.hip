@@ -7,59 +7,40 @@
 // eight trilinear weights.  The fluid velocity at a node is u_c = (j + F_ext/2)/rho of the
 // pre-collision state (Eqs. 2-3); the atoms' own force is not included.
 //
-// k_couple runs eight lanes per atom (one per stencil node): each lane pulls its node's 19
-// pre-collision values, forms u_c and its weighted share; three xor-shuffles within the
-// 8-lane group give U; every lane then adds its weighted share of -F_c to its node.  The
-// deposit is a fixed-point (2^-40) 64-bit integer atomic add, so the summed force per node
-// does not depend on the order in which atoms arrive.  The lane also raises the flag of
-// the 256-site tile that holds its node, so the sweep reads the force field only there.
+// Per step, in stream order:
+//   k_prep      clear the neighbour-list counts and the force-tile flags
+//   k_bin_mark  one thread per atom: flag its 8 stencil nodes (plain byte stores) and their
+//               64-site tiles, append the atom to the list of its stencil base node (lower
+//               corner), and append a record of it to its neighbour-list cell
+//   k_node_u    u_c at every flagged node, pulled once per node (19 loads) rather than once
+//               per atom corner
+//   k_couple    eight lanes per atom: weighted u_c of its node, xor-shuffle sum -> U,
+//               F_c = gamma (U - v)
+//   k_spread    every flagged node gathers -W F_c from the atoms listed at the 8 base nodes
+//               whose stencil covers it, summed in 2^-40 fixed point (order-independent) and
+//               stored as a float; no atomics on the force
+//   (lattice sweep: adds the spread force on flagged tiles and clears the per-step buffers)
+//   k_forces_integrate  eight lanes per atom, the 27 neighbour cells split among them:
+//               tethers, bonds, Lennard-Jones summed in 2^-32 fixed point (order-independent,
+//               so the result does not depend on the order atoms landed in a cell), then the
+//               symplectic Euler update.
 //
-// Positions are kept as the caller's unwrapped anchors x0 plus a displacement d, so that
-// pair vectors (x0_i - x0_j) + (d_i - d_j) and stencil fractions keep full FP32 precision
-// at any box size.
-#include "lbmd_internal.h"
+// Positions are kept as the caller's unwrapped anchors x0 plus a displacement d.  Stencil
+// fractions and pair vectors are formed from small numbers only (fractions in [0, 1) and
+// small integer offsets), so they keep full FP32 precision at any box size.
+#include "lattice_common.h"
 
 namespace lbmd {
 namespace {
-
-struct CoupleArgs {
-  const void* f;          // current population buffer
-  int storage;
-  long plane;
-  int nx, ny, nz;
-  float rho0, gamma;
-  int bf_kind;
-  const float* fext_tab;
-  const float* fext_field;
-  const float* x0;
-  const float* d;
-  const float* v;
-  float* fc;              // out: friction force on each atom
-  long long* fcoup;       // [3][plane] fixed point
-  uint32_t* tile_flag;
-  int N;
-  // neighbour-list binning (nc[0] == 0 when off)
-  int nc[3];
-  float inv_cw[3];
-  int* cell_count;
-  int* cell_atoms;
-  uint32_t* err;
-};
-
-__device__ __forceinline__ float load_pop(const void* f, int storage, size_t idx) {
-  if (storage == LB_STORE_F32) return reinterpret_cast<const float*>(f)[idx];
-  if (storage == LB_STORE_F16) return (float)reinterpret_cast<const _Float16*>(f)[idx];
-  return __uint_as_float((uint32_t)reinterpret_cast<const uint16_t*>(f)[idx] << 16);
-}
 
 __device__ __forceinline__ int wrapi(int a, int n) {
   int r = a % n;
   return r < 0 ? r + n : r;
 }
 
-// integer cell and fraction of (x0 + d) along one axis, with the integer part wrapped
-// (the clamp keeps a diverging displacement, which the velocity check reports, from
-// producing out-of-range integer conversions)
+// Integer node and fraction of (x0 + d) along one axis, the node wrapped into [0, n).
+// The clamp keeps a diverging displacement (reported by the velocity check) from
+// producing out-of-range integer conversions.
 __device__ __forceinline__ void split(float x0, float d, int n, int& i0, float& frac) {
   const float ia = floorf(x0);
   const float t = fminf(fmaxf((x0 - ia) + d, -1.0e6f), 1.0e6f);
@@ -68,65 +49,263 @@ __device__ __forceinline__ void split(float x0, float d, int n, int& i0, float& 
   i0 = wrapi((int)ia + (int)fl, n);
 }
 
-// value * 2^40 rounded to an integer; clamped so that a diverging state (which the velocity
+// Neighbour-list cell of a wrapped position, and the integer origin of that cell.
+__device__ __forceinline__ int cell_of(int i0, float frac, float inv_cw, int nc) {
+  const int q = (int)(((float)i0 + frac) * inv_cw);
+  return q >= nc ? nc - 1 : q;
+}
+__device__ __forceinline__ int cell_origin(int q, int n, int nc) { return (q * n) / nc; }
+
+// Position of an atom inside its neighbour-list cell in 8.24 fixed point: (node offset from
+// the cell's integer origin, biased by 1) + fraction.  Differences of these integers are
+// exact, and one conversion turns a pair difference into a float.
+constexpr float kCellFix = 16777216.0f;      // 2^24
+constexpr float kCellFixInv = 1.0f / 16777216.0f;
+__device__ __forceinline__ int cell_fixed(int node_offset, float frac) {
+  return ((node_offset + 1) << 24) + (int)rintf(frac * kCellFix);
+}
+
+// value * scale rounded to an integer, clamped so a diverging state (which the velocity
 // check reports) cannot overflow the conversion
-__device__ __forceinline__ long long to_fixed(float v) {
-  float q = rintf(v * kFixScale);
+__device__ __forceinline__ long long to_fixed(float v, float scale) {
+  float q = rintf(v * scale);
   q = fminf(fmaxf(q, -4.0e18f), 4.0e18f);
   return (long long)q;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.  Kernels whose
+// neighbouring work items share data (atoms of one globule, nodes of one region) renumber
+// their workgroups so that each XCD gets one contiguous eighth of the grid.  The grid must be
+// a multiple of 8 workgroups.
+__device__ __forceinline__ int xcd_block() {
+  const int per = (int)(gridDim.x >> 3);
+  return (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
+}
+
+
+struct AtomGeo {
+  int n[3];          // lattice extents
+  int nc[3];         // neighbour-list cells per axis (nc[0] == 0: no Lennard-Jones)
+  float inv_cw[3];
+};
+
+// ------------------------------------------------------------------------------------------
+struct PrepArgs {
+  int* cell_count;
+  long ncell;
+  uint32_t* tile_flag;
+  int ntiles;
+  int* occ_count;
+};
+
+__global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
+  const long t = blockIdx.x * 256L + threadIdx.x;
+  if (t < a.ncell) a.cell_count[t] = 0;
+  if (t < a.ntiles) a.tile_flag[t] = 0u;
+  if (t < 2) a.occ_count[t] = 0;
+}
+
+// ------------------------------------------------------------------------------------------
+// Stream compaction of the occupied neighbour-list cells and of the flagged force tiles:
+// one ballot and one counter atomic per wavefront.  The lists' order depends on scheduling;
+// every consumer treats each entry independently, so results do not.
+struct CompactArgs {
+  const int* cell_count;
+  long ncell;
+  int* occ_cells;
+  const uint32_t* tile_flag;
+  int ntiles;
+  int* occ_tiles;
+  int* occ_count;
+};
+
+// block-wide compaction: one counter atomic per workgroup that has anything to append
+__device__ __forceinline__ void compact_block(bool keep, int item, int* list, int* count) {
+  __shared__ int wave_n[4];
+  __shared__ int block_base;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const unsigned long long m = __ballot(keep);
+  if (lane == 0) wave_n[wid] = __popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int tot = wave_n[0] + wave_n[1] + wave_n[2] + wave_n[3];
+    block_base = tot ? atomicAdd(count, tot) : 0;
+  }
+  __syncthreads();
+  int off = block_base;
+  for (int w = 0; w < wid; ++w) off += wave_n[w];
+  if (keep) list[off + __popcll(m & ((1ull << lane) - 1ull))] = item;
+}
+
+__global__ __launch_bounds__(256) void k_compact(CompactArgs a) {
+  const long t = blockIdx.x * 256L + threadIdx.x;
+  const long n_cell_blocks = (a.ncell + 255) / 256;
+  if ((long)blockIdx.x < n_cell_blocks) {
+    compact_block(t < a.ncell && a.cell_count[t] > 0, (int)t, a.occ_cells, a.occ_count);
+  } else {
+    const long u = t - n_cell_blocks * 256;
+    compact_block(u < a.ntiles && a.tile_flag[u] != 0u, (int)u, a.occ_tiles, a.occ_count + 1);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Order each occupied cell's records by atom index (their slots came from atomics), so that
+// the pair sums below run in a fixed order: one wavefront per occupied cell, lane = slot,
+// rank by shuffles, then every lane writes its record to its rank.
+struct SortArgs {
+  const int* occ_cells;
+  const int* occ_count;
+  const int* cell_count;
+  int4* cell_rec;
+};
+
+__global__ __launch_bounds__(256) void k_cell_sort(SortArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6, nwave = gridDim.x * 4;
+  const int nocc = *a.occ_count;
+  for (int k = wave; k < nocc; k += nwave) {
+    const long cell = a.occ_cells[k];
+    int n = a.cell_count[cell];
+    n = n > kCellCap ? kCellCap : n;
+    const bool mine = lane < n;
+    const int4 rec = mine ? a.cell_rec[cell * kCellCap + lane] : make_int4(0, 0, 0, 0x7fffffff);
+    int rank = 0;
+    for (int j = 0; j < n; ++j) rank += __shfl(rec.w, j, 64) < rec.w ? 1 : 0;
+    if (mine) a.cell_rec[cell * kCellCap + rank] = rec;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+struct BinArgs {
+  int N;
+  AtomGeo g;
+  const float* x0;
+  const float* d;
+  uint32_t* tile_flag;
+  uint8_t* node_flag;
+  int* base_count;
+  int* base_list;     // [plane][kBaseCap]
+  float4* atom_frac;  // [N]: stencil fractions
+  int* cell_count;
+  int4* cell_rec;     // [ncell][kCellCap]: fixed-point position in the cell xyz, atom index
+  uint32_t* err;
+};
+
+__global__ __launch_bounds__(256) void k_bin_mark(BinArgs a) {
+  const int i = xcd_block() * 256 + threadIdx.x;
+  if (i >= a.N) return;
+  int i0[3];
+  float fr[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) split(a.x0[3 * i + c], a.d[3 * i + c], a.g.n[c], i0[c], fr[c]);
+  const int x1 = i0[0] + 1 == a.g.n[0] ? 0 : i0[0] + 1;
+  const int y1 = i0[1] + 1 == a.g.n[1] ? 0 : i0[1] + 1;
+  const int z1 = i0[2] + 1 == a.g.n[2] ? 0 : i0[2] + 1;
+  const int nx = a.g.n[0], nxy = a.g.n[0] * a.g.n[1];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int node = ((k & 1) ? x1 : i0[0]) + nx * ((k & 2) ? y1 : i0[1]) + nxy * ((k & 4) ? z1 : i0[2]);
+    a.node_flag[node] = 1;
+    a.tile_flag[node >> kTileShift] = 1u;
+  }
+  a.atom_frac[i] = make_float4(fr[0], fr[1], fr[2], 0.f);
+  const int base = i0[0] + nx * i0[1] + nxy * i0[2];
+  const int bslot = atomicAdd(a.base_count + base, 1);
+  if (bslot < kBaseCap)
+    a.base_list[(size_t)base * kBaseCap + bslot] = i;
+  else
+    atomicOr(a.err, kErrOverflow);
+  if (a.g.nc[0] > 0) {
+    int q[3], P[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      q[c] = cell_of(i0[c], fr[c], a.g.inv_cw[c], a.g.nc[c]);
+      P[c] = cell_fixed(i0[c] - cell_origin(q[c], a.g.n[c], a.g.nc[c]), fr[c]);
+    }
+    const long cell = q[0] + (long)a.g.nc[0] * (q[1] + (long)a.g.nc[1] * q[2]);
+    const int slot = atomicAdd(a.cell_count + cell, 1);
+    if (slot < kCellCap)
+      a.cell_rec[cell * kCellCap + slot] = make_int4(P[0], P[1], P[2], i);
+    else
+      atomicOr(a.err, kErrOverflow);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+struct NodeArgs {
+  const void* f;
+  long plane;
+  int nx, ny, nz, S;
+  int ntiles;
+  float rho0;
+  int bf_kind;
+  const float* fext_tab;
+  const float* fext_field;
+  const int* occ_tiles;
+  const int* occ_count;   // [1]: number of flagged tiles
+  const uint8_t* node_flag;
+  float* uc;   // [3][plane]
+};
+
+// one wavefront per flagged 64-site tile (persistent over the tile list), lane = site
+template <int ST>
+__global__ __launch_bounds__(256) void k_node_u(NodeArgs a) {
+  using T = typename Store<ST>::T;
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6, nwave = gridDim.x * 4;
+  const int ntile = *a.occ_count;
+  for (int k = wave; k < ntile; k += nwave) {
+    const int s = (a.occ_tiles[k] << kTileShift) + lane;
+    if (s >= a.S || a.node_flag[s] == 0) continue;
+    const int x = s % a.nx;
+    const int t = s / a.nx;
+    const int y = t % a.ny;
+    const int z = t / a.ny;
+    float g[19];
+    gather<ST>(reinterpret_cast<const T*>(a.f), a.plane, x, y, z, a.nx, a.ny, a.nz, g);
+    float drho, jx, jy, jz, Fx, Fy, Fz;
+    moments(g, drho, jx, jy, jz);
+    external_force(a.bf_kind, a.fext_tab, a.fext_field, a.plane, s, y, Fx, Fy, Fz);
+    const float inv = 1.0f / (a.rho0 + drho);
+    a.uc[s] = (jx + 0.5f * Fx) * inv;
+    a.uc[a.plane + s] = (jy + 0.5f * Fy) * inv;
+    a.uc[2 * a.plane + s] = (jz + 0.5f * Fz) * inv;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+struct CoupleArgs {
+  int N;
+  int n[3];
+  long plane;
+  float gamma;
+  const float* x0;
+  const float* d;
+  const float* v;
+  const float* uc;
+  float* fc;              // out: friction force on each atom
+};
+
 __global__ __launch_bounds__(256) void k_couple(CoupleArgs a) {
-  const int tid = blockIdx.x * 256 + threadIdx.x;
+  const int tid = xcd_block() * 256 + threadIdx.x;
   const int atom = tid >> 3;
   const int k = tid & 7;
   const bool valid = atom < a.N;
   const int at = valid ? atom : a.N - 1;
   int i0[3];
   float fr[3];
-  const int n3[3] = {a.nx, a.ny, a.nz};
 #pragma unroll
-  for (int c = 0; c < 3; ++c) split(a.x0[3 * at + c], a.d[3 * at + c], n3[c], i0[c], fr[c]);
+  for (int c = 0; c < 3; ++c) split(a.x0[3 * at + c], a.d[3 * at + c], a.n[c], i0[c], fr[c]);
   const int dx = k & 1, dy = (k >> 1) & 1, dz = (k >> 2) & 1;
-  const int x = dx ? (i0[0] + 1 == a.nx ? 0 : i0[0] + 1) : i0[0];
-  const int y = dy ? (i0[1] + 1 == a.ny ? 0 : i0[1] + 1) : i0[1];
-  const int z = dz ? (i0[2] + 1 == a.nz ? 0 : i0[2] + 1) : i0[2];
+  const int x = dx ? (i0[0] + 1 == a.n[0] ? 0 : i0[0] + 1) : i0[0];
+  const int y = dy ? (i0[1] + 1 == a.n[1] ? 0 : i0[1] + 1) : i0[1];
+  const int z = dz ? (i0[2] + 1 == a.n[2] ? 0 : i0[2] + 1) : i0[2];
   const float w = (dx ? fr[0] : 1.0f - fr[0]) * (dy ? fr[1] : 1.0f - fr[1]) *
                   (dz ? fr[2] : 1.0f - fr[2]);
-  // pre-collision values at the node, pulled from its upstream neighbours
-  const int xm = x == 0 ? a.nx - 1 : x - 1, xp = x == a.nx - 1 ? 0 : x + 1;
-  const int ym = y == 0 ? a.ny - 1 : y - 1, yp = y == a.ny - 1 ? 0 : y + 1;
-  const int zm = z == 0 ? a.nz - 1 : z - 1, zp = z == a.nz - 1 ? 0 : z + 1;
-  const int nxy = a.nx * a.ny;
-  const int X3[3] = {xm, x, xp};
-  const int Y3[3] = {ym * a.nx, y * a.nx, yp * a.nx};
-  const int Z3[3] = {zm * nxy, z * nxy, zp * nxy};
-  float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
-#pragma unroll
-  for (int i = 0; i < 19; ++i) {
-    const int src = X3[1 - CX[i]] + Y3[1 - CY[i]] + Z3[1 - CZ[i]];
-    const float gi = load_pop(a.f, a.storage, (size_t)i * a.plane + src);
-    drho += gi;
-    if (CX[i] == 1) jx += gi;
-    if (CX[i] == -1) jx -= gi;
-    if (CY[i] == 1) jy += gi;
-    if (CY[i] == -1) jy -= gi;
-    if (CZ[i] == 1) jz += gi;
-    if (CZ[i] == -1) jz -= gi;
-  }
-  const int node = x + a.nx * y + nxy * z;
-  float Fx = 0.f, Fy = 0.f, Fz = 0.f;
-  if (a.bf_kind == LB_BF_KOLMOGOROV || a.bf_kind == LB_BF_SIGN_SHEAR) {
-    Fx = a.fext_tab[y];
-  } else if (a.bf_kind == LB_BF_FIELD) {
-    Fx = a.fext_field[node];
-    Fy = a.fext_field[a.plane + node];
-    Fz = a.fext_field[2 * a.plane + node];
-  }
-  const float inv = 1.0f / (a.rho0 + drho);
-  float Ux = w * ((jx + 0.5f * Fx) * inv);
-  float Uy = w * ((jy + 0.5f * Fy) * inv);
-  float Uz = w * ((jz + 0.5f * Fz) * inv);
+  const int node = x + a.n[0] * (y + a.n[1] * z);
+  float Ux = w * a.uc[node];
+  float Uy = w * a.uc[a.plane + node];
+  float Uz = w * a.uc[2 * a.plane + node];
   // sum over the 8 lanes of this atom (lanes 8a..8a+7 of the wavefront)
 #pragma unroll
   for (int o = 1; o < 8; o <<= 1) {
@@ -134,79 +313,87 @@ __global__ __launch_bounds__(256) void k_couple(CoupleArgs a) {
     Uy += __shfl_xor(Uy, o, 64);
     Uz += __shfl_xor(Uz, o, 64);
   }
-  if (!valid) return;
-  const float fcx = a.gamma * (Ux - a.v[3 * atom]);
-  const float fcy = a.gamma * (Uy - a.v[3 * atom + 1]);
-  const float fcz = a.gamma * (Uz - a.v[3 * atom + 2]);
-  // the fluid receives -F_c with the interpolation weights
-  const long long qx = to_fixed(-w * fcx);
-  const long long qy = to_fixed(-w * fcy);
-  const long long qz = to_fixed(-w * fcz);
-  unsigned long long* fq = reinterpret_cast<unsigned long long*>(a.fcoup);
-  if (qx) atomicAdd(fq + node, (unsigned long long)qx);
-  if (qy) atomicAdd(fq + a.plane + node, (unsigned long long)qy);
-  if (qz) atomicAdd(fq + 2 * a.plane + node, (unsigned long long)qz);
-  a.tile_flag[node >> kTileShift] = 1u;
-  if (k == 0) {
-    a.fc[3 * atom] = fcx;
-    a.fc[3 * atom + 1] = fcy;
-    a.fc[3 * atom + 2] = fcz;
-    if (a.nc[0] > 0) {
-      int cc[3];
+  if (!valid || k != 0) return;
+  a.fc[3 * atom] = a.gamma * (Ux - a.v[3 * atom]);
+  a.fc[3 * atom + 1] = a.gamma * (Uy - a.v[3 * atom + 1]);
+  a.fc[3 * atom + 2] = a.gamma * (Uz - a.v[3 * atom + 2]);
+}
+
+// ------------------------------------------------------------------------------------------
+struct SpreadArgs {
+  int S;
+  int n[3];
+  long plane;
+  const int* occ_tiles;
+  const int* occ_count;
+  uint8_t* node_flag;        // cleared here
+  const int* base_count;
+  const int* base_list;
+  const float4* atom_frac;
+  const float* fc;
+  float* fcoup;              // [3][plane]
+};
+
+// The transpose of the interpolation: node x is corner delta of every atom whose base node
+// is x - delta; its share of that atom's -F_c is the same trilinear weight.  One wavefront
+// per flagged 64-site tile (persistent over the tile list), lane = site.
+__global__ __launch_bounds__(256) void k_spread(SpreadArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
+  const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6, nwave = gridDim.x * 4;
+  const int ntile = *a.occ_count;
+  for (int kt = wave; kt < ntile; kt += nwave) {
+    const int s = (a.occ_tiles[kt] << kTileShift) + lane;
+    if (s >= a.S || a.node_flag[s] == 0) continue;
+    const int x = s % nx;
+    const int t = s / nx;
+    const int y = t % ny;
+    const int z = t / ny;
+    long long Sx = 0, Sy = 0, Sz = 0;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const float Y = (float)i0[c] + fr[c];
-        int q = (int)(Y * a.inv_cw[c]);
-        cc[c] = q >= a.nc[c] ? a.nc[c] - 1 : q;
+    for (int k = 0; k < 8; ++k) {
+      const int dx = k & 1, dy = (k >> 1) & 1, dz = (k >> 2) & 1;
+      const int bx = dx ? (x == 0 ? nx - 1 : x - 1) : x;
+      const int by = dy ? (y == 0 ? ny - 1 : y - 1) : y;
+      const int bz = dz ? (z == 0 ? nz - 1 : z - 1) : z;
+      const int base = bx + nx * (by + ny * bz);
+      int n = a.base_count[base];
+      n = n > kBaseCap ? kBaseCap : n;
+      for (int q = 0; q < n; ++q) {
+        const int at = a.base_list[(size_t)base * kBaseCap + q];
+        const float4 fr = a.atom_frac[at];
+        const float w = (dx ? fr.x : 1.0f - fr.x) * (dy ? fr.y : 1.0f - fr.y) * (dz ? fr.z : 1.0f - fr.z);
+        Sx += to_fixed(-w * a.fc[3 * at], kFixScale);
+        Sy += to_fixed(-w * a.fc[3 * at + 1], kFixScale);
+        Sz += to_fixed(-w * a.fc[3 * at + 2], kFixScale);
       }
-      const int cell = cc[0] + a.nc[0] * (cc[1] + a.nc[1] * cc[2]);
-      const int slot = atomicAdd(a.cell_count + cell, 1);
-      if (slot < kCellCap)
-        a.cell_atoms[(size_t)cell * kCellCap + slot] = atom;
-      else
-        atomicOr(a.err, kErrOverflow);
     }
+    a.fcoup[s] = (float)Sx * kFixInv;
+    a.fcoup[a.plane + s] = (float)Sy * kFixInv;
+    a.fcoup[2 * a.plane + s] = (float)Sz * kFixInv;
+    a.node_flag[s] = 0;
   }
 }
 
-// Order each cell's atoms by index, so that the pair sums below run in a fixed order and
-// the whole step is bitwise reproducible.
-__global__ __launch_bounds__(256) void k_cell_sort(int* count, int* atoms, long ncell) {
-  const long c = blockIdx.x * 256L + threadIdx.x;
-  if (c >= ncell) return;
-  int n = count[c];
-  if (n > kCellCap) n = kCellCap;
-  int* p = atoms + c * kCellCap;
-  for (int i = 1; i < n; ++i) {
-    const int v = p[i];
-    int j = i - 1;
-    while (j >= 0 && p[j] > v) {
-      p[j + 1] = p[j];
-      --j;
-    }
-    p[j + 1] = v;
-  }
-}
-
+// ------------------------------------------------------------------------------------------
 struct ForceArgs {
   int N;
+  AtomGeo g;
+  long ncell;
   float L[3], invL[3];
   const float* x0;
   const float* d;       // X^n - x0
-  float* d_next;        // X^{n+1} - x0
-  float* v;             // in/out
-  const float* fc;
-  float inv_mass;
+  float* ff;            // out: stand-in force field at X^n
   float k_tether;
   const int* bond_off;
   const int* bond_nbr;
   float k_bond, r0_bond;
   float lj_eps24, lj_sigma2, lj_rc2;
   int lj_exclude_bonded;
-  int nc[3];
-  float inv_cw[3];
   const int* cell_count;
-  const int* cell_atoms;
+  const int4* cell_rec;
+  const int* occ_cells;
+  const int* occ_count;   // [1]: number of occupied cells
   uint32_t* err;
 };
 
@@ -214,12 +401,32 @@ __device__ __forceinline__ float min_image(float r, float L, float invL) {
   return r - L * rintf(r * invL);
 }
 
-__global__ __launch_bounds__(256) void k_forces_integrate(ForceArgs a) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= a.N) return;
+// per-axis neighbour-cell index after periodic wrap, and the integer shift (own cell origin
+// minus neighbour cell origin, across the periodic seam if it wrapped) that expresses the
+// neighbour's cell-relative positions in the own cell's frame
+__device__ __forceinline__ void nbr_cell(int q, int o, int n, int nc, int& cq, int& shift) {
+  int c = q + o, s = 0;
+  if (c < 0) {
+    c += nc;
+    s = n;
+  }
+  if (c >= nc) {
+    c -= nc;
+    s = -n;
+  }
+  cq = c;
+  shift = cell_origin(q, n, nc) - cell_origin(c, n, nc) + s;
+}
+
+// Tethers and bonds of atom i added to its Lennard-Jones force; the total stand-in force
+// field at X^n is stored for the integration.
+__device__ __forceinline__ void bonded_and_store(const ForceArgs& a, int i, float Fx, float Fy,
+                                                 float Fz) {
   const float xi = a.x0[3 * i], yi = a.x0[3 * i + 1], zi = a.x0[3 * i + 2];
   const float dxi = a.d[3 * i], dyi = a.d[3 * i + 1], dzi = a.d[3 * i + 2];
-  float Fx = -a.k_tether * dxi, Fy = -a.k_tether * dyi, Fz = -a.k_tether * dzi;
+  Fx -= a.k_tether * dxi;
+  Fy -= a.k_tether * dyi;
+  Fz -= a.k_tether * dzi;
   const int b0 = a.bond_off[i], b1 = a.bond_off[i + 1];
   for (int b = b0; b < b1; ++b) {
     const int j = a.bond_nbr[b];
@@ -232,81 +439,190 @@ __global__ __launch_bounds__(256) void k_forces_integrate(ForceArgs a) {
     Fy += f * ry;
     Fz += f * rz;
   }
-  if (a.nc[0] > 0) {
-    // the atom's own cell, from its wrapped position
-    int cc[3];
-    const float xs[3] = {xi, yi, zi}, ds[3] = {dxi, dyi, dzi};
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      int i0;
-      float fr;
-      split(xs[c], ds[c], (int)a.L[c], i0, fr);
-      const float Y = (float)i0 + fr;
-      const int q = (int)(Y * a.inv_cw[c]);
-      cc[c] = q >= a.nc[c] ? a.nc[c] - 1 : q;
-    }
-    for (int oz = -1; oz <= 1; ++oz) {
-      int cz = cc[2] + oz;
-      cz = cz < 0 ? cz + a.nc[2] : (cz >= a.nc[2] ? cz - a.nc[2] : cz);
-      for (int oy = -1; oy <= 1; ++oy) {
-        int cy = cc[1] + oy;
-        cy = cy < 0 ? cy + a.nc[1] : (cy >= a.nc[1] ? cy - a.nc[1] : cy);
-        for (int ox = -1; ox <= 1; ++ox) {
-          int cx = cc[0] + ox;
-          cx = cx < 0 ? cx + a.nc[0] : (cx >= a.nc[0] ? cx - a.nc[0] : cx);
-          const long cell = cx + (long)a.nc[0] * (cy + (long)a.nc[1] * cz);
-          int n = a.cell_count[cell];
-          n = n > kCellCap ? kCellCap : n;
-          const int* list = a.cell_atoms + cell * kCellCap;
-          for (int q = 0; q < n; ++q) {
-            const int j = list[q];
-            if (j == i) continue;
-            const float rx = min_image((xi - a.x0[3 * j]) + (dxi - a.d[3 * j]), a.L[0], a.invL[0]);
-            const float ry = min_image((yi - a.x0[3 * j + 1]) + (dyi - a.d[3 * j + 1]), a.L[1], a.invL[1]);
-            const float rz = min_image((zi - a.x0[3 * j + 2]) + (dzi - a.d[3 * j + 2]), a.L[2], a.invL[2]);
-            const float r2 = rx * rx + ry * ry + rz * rz;
-            if (!(r2 < a.lj_rc2)) continue;
-            if (a.lj_exclude_bonded) {
-              bool bonded = false;
-              for (int b = b0; b < b1; ++b) bonded = bonded || (a.bond_nbr[b] == j);
-              if (bonded) continue;
-            }
-            const float inv2 = 1.0f / r2;
-            const float sr2 = a.lj_sigma2 * inv2;
-            const float sr6 = sr2 * sr2 * sr2;
-            const float f = a.lj_eps24 * (2.0f * sr6 * sr6 - sr6) * inv2;
-            Fx += f * rx;
-            Fy += f * ry;
-            Fz += f * rz;
-          }
-        }
-      }
-    }
-  }
-  // symplectic Euler: v^{n+1} = v^n + (F_ff + F_c)/m, X^{n+1} = X^n + v^{n+1}
-  const float vx = a.v[3 * i] + (Fx + a.fc[3 * i]) * a.inv_mass;
-  const float vy = a.v[3 * i + 1] + (Fy + a.fc[3 * i + 1]) * a.inv_mass;
-  const float vz = a.v[3 * i + 2] + (Fz + a.fc[3 * i + 2]) * a.inv_mass;
-  if (!__builtin_isfinite(vx + vy + vz)) atomicOr(a.err, kErrNonFinite);
-  a.v[3 * i] = vx;
-  a.v[3 * i + 1] = vy;
-  a.v[3 * i + 2] = vz;
-  a.d_next[3 * i] = dxi + vx;
-  a.d_next[3 * i + 1] = dyi + vy;
-  a.d_next[3 * i + 2] = dzi + vz;
+  a.ff[3 * i] = Fx;
+  a.ff[3 * i + 1] = Fy;
+  a.ff[3 * i + 2] = Fz;
 }
 
-struct PrepArgs {
-  int* cell_count;
-  long ncell;
-  uint32_t* tile_flag;
-  int ntiles;
+// Lennard-Jones, cell-centric, staged in LDS.  A wavefront takes one occupied cell at a time
+// (persistent over the occupied-cell list):
+//   1. lanes 0..26 find the 27 neighbour cells (with the periodic shift of each) and their
+//      counts; a wave scan gives each cell's offset in the staged list;
+//   2. the records of those cells are copied into LDS (one coalesced load per cell, issued
+//      back to back), already shifted into the home cell's frame; if they exceed the stage,
+//      cells are staged in several rounds;
+//   3. lane = (home slot 0..15) + 16 * (group 0..3); group g takes staged records g, g+4,
+//      ...; all lanes of a group read the same LDS record (a broadcast).  Home cells with
+//      more than 16 atoms run up to 3 passes over the same staged records.
+// Each lane sums in FP32 in a fixed order (records in cell order, atom-index order inside a
+// cell); the 4 group partials meet through two xor-shuffles in a fixed order; group 0 then
+// adds tethers and bonds and updates the atom.  Pair vectors come from exact fixed-point
+// differences.  Each atom sits in exactly one cell slot, so every atom is updated once.
+constexpr int kStage = 640;   // staged records per wavefront (27 cells of ~9.5 atoms need ~260)
+constexpr int kPasses = kCellCap / 16;
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(256) void k_forces_cells(ForceArgs a) {
+  __shared__ int4 stage_all[4][kStage];
+  const int lane = threadIdx.x & 63;
+  const int hl = lane & 15, grp = lane >> 4;
+  int4* stage = stage_all[threadIdx.x >> 6];
+  const int nc0 = a.g.nc[0], nc1 = a.g.nc[1], nc2 = a.g.nc[2];
+  const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6, nwave = gridDim.x * 4;
+  const int nocc = *a.occ_count;
+  for (int k = wave; k < nocc; k += nwave) {
+    const long cell = a.occ_cells[k];
+    int nh = a.cell_count[cell];
+    nh = nh > kCellCap ? kCellCap : nh;
+    const int q[3] = {(int)(cell % nc0), (int)((cell / nc0) % nc1), (int)(cell / ((long)nc0 * nc1))};
+    // home atoms of each pass
+    int4 me[kPasses];
+    int pb[kPasses][4], b0s[kPasses], b1s[kPasses];
+    bool hv[kPasses];
+    float Fx[kPasses], Fy[kPasses], Fz[kPasses];
+#pragma unroll
+    for (int p = 0; p < kPasses; ++p) {
+      const int h = 16 * p + hl;
+      hv[p] = h < nh;
+      me[p] = a.cell_rec[cell * kCellCap + (hv[p] ? h : 0)];
+      const int i = me[p].w;
+      b0s[p] = a.bond_off[i];
+      b1s[p] = a.bond_off[i + 1];
+      pb[p][0] = pb[p][1] = pb[p][2] = pb[p][3] = -1;
+      if (a.lj_exclude_bonded) {
+        const int deg = b1s[p] - b0s[p];
+        if (deg > 0) pb[p][0] = a.bond_nbr[b0s[p]];
+        if (deg > 1) pb[p][1] = a.bond_nbr[b0s[p] + 1];
+        if (deg > 2) pb[p][2] = a.bond_nbr[b0s[p] + 2];
+        if (deg > 3) pb[p][3] = a.bond_nbr[b0s[p] + 3];
+      }
+      Fx[p] = Fy[p] = Fz[p] = 0.f;
+    }
+    // neighbour cells: lane l < 27 holds cell l of the 3x3x3 block
+    long nbc = 0;
+    int nbn = 0, shx = 0, shy = 0, shz = 0;
+    if (lane < 27) {
+      int cx, cy, cz;
+      nbr_cell(q[0], lane % 3 - 1, a.g.n[0], nc0, cx, shx);
+      nbr_cell(q[1], (lane / 3) % 3 - 1, a.g.n[1], nc1, cy, shy);
+      nbr_cell(q[2], lane / 9 - 1, a.g.n[2], nc2, cz, shz);
+      nbc = cx + (long)nc0 * (cy + (long)nc1 * cz);
+      nbn = a.cell_count[nbc];
+      nbn = nbn > kCellCap ? kCellCap : nbn;
+    }
+    int pre = nbn;   // inclusive scan over lanes
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1) {
+      const int t = __shfl_up(pre, o, 64);
+      if (lane >= o) pre += t;
+    }
+    for (int kc = 0; kc < 27;) {
+      const int base = kc ? __shfl(pre, kc - 1, 64) : 0;
+      // stage cells kc .. kend-1 (as many as fit)
+      int kend = kc;
+      while (kend < 27 && __shfl(pre, kend, 64) - base <= kStage) ++kend;
+      for (int c = kc; c < kend; ++c) {
+        const int n_c = __shfl(nbn, c, 64);
+        const int off = (c ? __shfl(pre, c - 1, 64) : 0) - base;
+        const long cc = __shfl(nbc, c, 64);
+        const int sx = __shfl(shx, c, 64) << 24, sy = __shfl(shy, c, 64) << 24, sz = __shfl(shz, c, 64) << 24;
+        if (lane < n_c) {
+          int4 r = a.cell_rec[cc * kCellCap + lane];
+          // neighbour position in the home cell's frame (fixed point)
+          r.x -= sx;
+          r.y -= sy;
+          r.z -= sz;
+          stage[off + lane] = r;
+        }
+      }
+      wave_lds_sync();
+      const int ntot = __shfl(pre, kend - 1, 64) - base;
+#pragma unroll
+      for (int p = 0; p < kPasses; ++p) {
+        if (16 * p >= nh) break;
+        if (!hv[p]) continue;
+        const int i = me[p].w;
+        const bool excl = a.lj_exclude_bonded && b1s[p] > b0s[p];
+        for (int c = grp; c < ntot; c += 4) {
+          const int4 r4 = stage[c];
+          // pair vector X_i - X_j: exact integer difference, one rounding
+          const float rx = (float)(me[p].x - r4.x) * kCellFixInv;
+          const float ry = (float)(me[p].y - r4.y) * kCellFixInv;
+          const float rz = (float)(me[p].z - r4.z) * kCellFixInv;
+          const float r2 = rx * rx + ry * ry + rz * rz;
+          const int j = r4.w;
+          if (!(r2 < a.lj_rc2) || j == i) continue;
+          if (excl) {
+            bool bonded = j == pb[p][0] || j == pb[p][1] || j == pb[p][2] || j == pb[p][3];
+            for (int bb = b0s[p] + 4; bb < b1s[p]; ++bb) bonded = bonded || (a.bond_nbr[bb] == j);
+            if (bonded) continue;
+          }
+          const float inv2 = __builtin_amdgcn_rcpf(r2);
+          const float sr2 = a.lj_sigma2 * inv2;
+          const float sr6 = sr2 * sr2 * sr2;
+          const float f = a.lj_eps24 * (2.0f * sr6 * sr6 - sr6) * inv2;
+          Fx[p] += f * rx;
+          Fy[p] += f * ry;
+          Fz[p] += f * rz;
+        }
+      }
+      wave_lds_sync();
+      kc = kend;
+    }
+#pragma unroll
+    for (int p = 0; p < kPasses; ++p) {
+      if (16 * p >= nh) break;
+      // groups 0+1 and 2+3, then the two pairs: a fixed summation order
+      float fx = Fx[p], fy = Fy[p], fz = Fz[p];
+      fx += __shfl_xor(fx, 16, 64);
+      fy += __shfl_xor(fy, 16, 64);
+      fz += __shfl_xor(fz, 16, 64);
+      fx += __shfl_xor(fx, 32, 64);
+      fy += __shfl_xor(fy, 32, 64);
+      fz += __shfl_xor(fz, 32, 64);
+      if (hv[p] && grp == 0) bonded_and_store(a, me[p].w, fx, fy, fz);
+    }
+  }
+}
+
+// Without Lennard-Jones: one thread per atom, tethers + bonds.
+__global__ __launch_bounds__(256) void k_bonded_forces(ForceArgs a) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.N) return;
+  bonded_and_store(a, i, 0.f, 0.f, 0.f);
+}
+
+// Symplectic Euler with the force field at X^n and the friction of this step:
+// v^{n+1} = v^n + (F_ff + F_c)/m, X^{n+1} = X^n + v^{n+1}.
+struct IntegrateArgs {
+  int N;
+  float inv_mass;
+  const float* ff;
+  const float* fc;
+  const float* d;
+  float* d_next;
+  float* v;
+  uint32_t* err;
 };
 
-__global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
-  const long t = blockIdx.x * 256L + threadIdx.x;
-  if (t < a.ncell) a.cell_count[t] = 0;
-  if (t < a.ntiles) a.tile_flag[t] = 0u;
+__global__ __launch_bounds__(256) void k_integrate(IntegrateArgs a) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= a.N) return;
+  bool finite = true;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int k = 3 * t + c;
+    const float vn = a.v[k] + (a.ff[k] + a.fc[k]) * a.inv_mass;
+    finite = finite && __builtin_isfinite(vn);
+    a.v[k] = vn;
+    a.d_next[k] = a.d[k] + vn;
+  }
+  if (!finite) atomicOr(a.err, kErrNonFinite);
 }
 
 __global__ __launch_bounds__(256) void k_read_atoms(int N, const float* x0, const float* d,
@@ -317,76 +633,164 @@ __global__ __launch_bounds__(256) void k_read_atoms(int N, const float* x0, cons
   if (vo) vo[t] = v[t];
 }
 
+AtomGeo atom_geo(const lb_ctx* c) {
+  AtomGeo g;
+  const int n3[3] = {c->geo.nx, c->geo.ny, c->geo.nz};
+  for (int k = 0; k < 3; ++k) {
+    g.n[k] = n3[k];
+    g.nc[k] = c->geo.nc[k];
+    g.inv_cw[k] = c->geo.inv_cw[k];
+  }
+  return g;
+}
+
+unsigned blocks(long n, int per) { return (unsigned)((n + per - 1) / per); }
+
+// grids of the XCD-mapped kernels are a multiple of 8 workgroups
+unsigned blocks8(long n, int per) { return (blocks(n, per) + 7u) & ~7u; }
+
+// persistent kernels: enough 4-wavefront workgroups for the items (one per wavefront), at
+// most 8 per CU
+unsigned persistent_grid(long nitems) {
+  long b = (nitems + 3) / 4;
+  if (b > 2048) b = 2048;
+  if (b < 8) b = 8;
+  return (unsigned)((b + 7) & ~7L);
+}
+
 }  // namespace
 
 hipError_t launch_prep(lb_ctx* c) {
   PrepArgs a;
   a.cell_count = (int*)(c->ws + c->lay.cell_count);
   a.ncell = c->geo.ncell;
-  a.tile_flag = (uint32_t*)(c->ws + c->lay.tile_flag);
+  a.tile_flag = (uint32_t*)(c->ws + c->lay.tile_flag[c->step & 1]);
   a.ntiles = c->geo.ntiles;
+  a.occ_count = (int*)(c->ws + c->lay.occ_count[c->step & 1]);
   const long n = a.ncell > a.ntiles ? a.ncell : a.ntiles;
-  hipLaunchKernelGGL(k_prep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, a);
+  hipLaunchKernelGGL(k_prep, dim3(blocks(n, 256)), dim3(256), 0, c->astream, a);
   return hipGetLastError();
 }
 
-hipError_t launch_couple(lb_ctx* c) {
-  const Geometry& g = c->geo;
-  CoupleArgs a;
-  a.f = c->ws + c->lay.pop[c->cur];
-  a.storage = c->p.storage;
-  a.plane = g.plane;
-  a.nx = g.nx;
-  a.ny = g.ny;
-  a.nz = g.nz;
-  a.rho0 = c->p.rho0;
-  a.gamma = c->p.gamma;
-  a.bf_kind = c->p.bf_kind;
-  a.fext_tab = (const float*)(c->ws + c->lay.fext_tab);
-  a.fext_field = (const float*)(c->ws + c->lay.fext_field);
-  a.x0 = (const float*)(c->ws + c->lay.x0);
-  a.d = (const float*)(c->ws + c->lay.disp[c->dcur]);
-  a.v = (const float*)(c->ws + c->lay.vel);
-  a.fc = (float*)(c->ws + c->lay.fc);
-  a.fcoup = (long long*)(c->ws + c->lay.fcoup);
-  a.tile_flag = (uint32_t*)(c->ws + c->lay.tile_flag);
-  a.N = c->p.n_atoms;
-  for (int k = 0; k < 3; ++k) {
-    a.nc[k] = g.nc[k];
-    a.inv_cw[k] = g.inv_cw[k];
-  }
-  a.cell_count = (int*)(c->ws + c->lay.cell_count);
-  a.cell_atoms = (int*)(c->ws + c->lay.cell_atoms);
-  a.err = (uint32_t*)(c->ws + c->lay.err);
-  const long threads = 8L * a.N;
-  hipLaunchKernelGGL(k_couple, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, c->stream, a);
+hipError_t launch_compact(lb_ctx* c) {
+  CompactArgs a;
+  a.cell_count = (const int*)(c->ws + c->lay.cell_count);
+  a.ncell = c->geo.ncell;
+  a.occ_cells = (int*)(c->ws + c->lay.occ_cells);
+  a.tile_flag = (const uint32_t*)(c->ws + c->lay.tile_flag[c->step & 1]);
+  a.ntiles = c->geo.ntiles;
+  a.occ_tiles = (int*)(c->ws + c->lay.occ_tiles[c->step & 1]);
+  a.occ_count = (int*)(c->ws + c->lay.occ_count[c->step & 1]);
+  const long nb = (a.ncell + 255) / 256 + (a.ntiles + 255) / 256;
+  hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(256), 0, c->astream, a);
   return hipGetLastError();
 }
 
 hipError_t launch_cell_sort(lb_ctx* c) {
-  const long n = c->geo.ncell;
-  hipLaunchKernelGGL(k_cell_sort, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
-                     (int*)(c->ws + c->lay.cell_count), (int*)(c->ws + c->lay.cell_atoms), n);
+  SortArgs a;
+  a.occ_cells = (const int*)(c->ws + c->lay.occ_cells);
+  a.occ_count = (const int*)(c->ws + c->lay.occ_count[c->step & 1]);
+  a.cell_count = (const int*)(c->ws + c->lay.cell_count);
+  a.cell_rec = (int4*)(c->ws + c->lay.cell_rec);
+  hipLaunchKernelGGL(k_cell_sort, dim3(persistent_grid(std::min(c->geo.ncell, (long)c->p.n_atoms))),
+                     dim3(256), 0, c->fstream, a);
   return hipGetLastError();
 }
 
-hipError_t launch_forces_integrate(lb_ctx* c) {
+hipError_t launch_bin_mark(lb_ctx* c) {
+  BinArgs a;
+  a.N = c->p.n_atoms;
+  a.g = atom_geo(c);
+  a.x0 = (const float*)(c->ws + c->lay.x0);
+  a.d = (const float*)(c->ws + c->lay.disp[c->dcur]);
+  const int par = (int)(c->step & 1);
+  a.tile_flag = (uint32_t*)(c->ws + c->lay.tile_flag[par]);
+  a.node_flag = (uint8_t*)(c->ws + c->lay.node_flag);
+  a.base_count = (int*)(c->ws + c->lay.base_count[par]);
+  a.base_list = (int*)(c->ws + c->lay.base_list[par]);
+  a.atom_frac = (float4*)(c->ws + c->lay.atom_frac);
+  a.cell_count = (int*)(c->ws + c->lay.cell_count);
+  a.cell_rec = (int4*)(c->ws + c->lay.cell_rec);
+  a.err = (uint32_t*)(c->ws + c->lay.err);
+  hipLaunchKernelGGL(k_bin_mark, dim3(blocks8(a.N, 256)), dim3(256), 0, c->astream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_node_u(lb_ctx* c) {
   const Geometry& g = c->geo;
+  NodeArgs a;
+  a.f = c->ws + c->lay.pop[c->cur];
+  a.plane = g.plane;
+  a.nx = g.nx;
+  a.ny = g.ny;
+  a.nz = g.nz;
+  a.S = (int)g.S;
+  a.rho0 = c->p.rho0;
+  a.bf_kind = c->p.bf_kind;
+  a.fext_tab = (const float*)(c->ws + c->lay.fext_tab);
+  a.fext_field = (const float*)(c->ws + c->lay.fext_field);
+  a.occ_tiles = (const int*)(c->ws + c->lay.occ_tiles[c->step & 1]);
+  a.occ_count = (const int*)(c->ws + c->lay.occ_count[c->step & 1]) + 1;
+  a.node_flag = (const uint8_t*)(c->ws + c->lay.node_flag);
+  a.uc = (float*)(c->ws + c->lay.uc);
+  const dim3 grid(persistent_grid(g.ntiles)), block(256);
+  switch (c->p.storage) {
+    case LB_STORE_F32: hipLaunchKernelGGL(k_node_u<LB_STORE_F32>, grid, block, 0, c->astream, a); break;
+    case LB_STORE_F16: hipLaunchKernelGGL(k_node_u<LB_STORE_F16>, grid, block, 0, c->astream, a); break;
+    default: hipLaunchKernelGGL(k_node_u<LB_STORE_BF16>, grid, block, 0, c->astream, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_couple(lb_ctx* c) {
+  CoupleArgs a;
+  a.N = c->p.n_atoms;
+  a.n[0] = c->geo.nx;
+  a.n[1] = c->geo.ny;
+  a.n[2] = c->geo.nz;
+  a.plane = c->geo.plane;
+  a.gamma = c->p.gamma;
+  a.x0 = (const float*)(c->ws + c->lay.x0);
+  a.d = (const float*)(c->ws + c->lay.disp[c->dcur]);
+  a.v = (const float*)(c->ws + c->lay.vel);
+  a.uc = (const float*)(c->ws + c->lay.uc);
+  a.fc = (float*)(c->ws + c->lay.fc);
+  hipLaunchKernelGGL(k_couple, dim3(blocks8(8L * a.N, 256)), dim3(256), 0, c->astream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_spread(lb_ctx* c) {
+  SpreadArgs a;
+  a.S = (int)c->geo.S;
+  a.n[0] = c->geo.nx;
+  a.n[1] = c->geo.ny;
+  a.n[2] = c->geo.nz;
+  a.plane = c->geo.plane;
+  const int par = (int)(c->step & 1);
+  a.occ_tiles = (const int*)(c->ws + c->lay.occ_tiles[par]);
+  a.occ_count = (const int*)(c->ws + c->lay.occ_count[par]) + 1;
+  a.node_flag = (uint8_t*)(c->ws + c->lay.node_flag);
+  a.base_count = (const int*)(c->ws + c->lay.base_count[par]);
+  a.base_list = (const int*)(c->ws + c->lay.base_list[par]);
+  a.atom_frac = (const float4*)(c->ws + c->lay.atom_frac);
+  a.fc = (const float*)(c->ws + c->lay.fc);
+  a.fcoup = (float*)(c->ws + c->lay.fcoup[par]);
+  hipLaunchKernelGGL(k_spread, dim3(persistent_grid(c->geo.ntiles)), dim3(256), 0, c->astream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_forces(lb_ctx* c) {
   ForceArgs a;
   a.N = c->p.n_atoms;
-  const int n3[3] = {g.nx, g.ny, g.nz};
+  a.g = atom_geo(c);
+  a.ncell = c->geo.ncell;
   for (int k = 0; k < 3; ++k) {
-    a.L[k] = (float)n3[k];
-    a.invL[k] = 1.0f / (float)n3[k];
-    a.nc[k] = g.nc[k];
-    a.inv_cw[k] = g.inv_cw[k];
+    a.L[k] = (float)a.g.n[k];
+    a.invL[k] = 1.0f / (float)a.g.n[k];
   }
   a.x0 = (const float*)(c->ws + c->lay.x0);
   a.d = (const float*)(c->ws + c->lay.disp[c->dcur]);
-  a.d_next = (float*)(c->ws + c->lay.disp[c->dcur ^ 1]);
-  a.v = (float*)(c->ws + c->lay.vel);
-  a.fc = (const float*)(c->ws + c->lay.fc);
-  a.inv_mass = 1.0f / c->p.mass;
+  a.ff = (float*)(c->ws + c->lay.ff);
   a.k_tether = c->p.k_tether;
   a.bond_off = (const int*)(c->ws + c->lay.bond_off);
   a.bond_nbr = (const int*)(c->ws + c->lay.bond_nbr);
@@ -397,18 +801,35 @@ hipError_t launch_forces_integrate(lb_ctx* c) {
   a.lj_rc2 = c->p.lj_rc * c->p.lj_rc;
   a.lj_exclude_bonded = c->p.lj_exclude_bonded;
   a.cell_count = (const int*)(c->ws + c->lay.cell_count);
-  a.cell_atoms = (const int*)(c->ws + c->lay.cell_atoms);
+  a.cell_rec = (const int4*)(c->ws + c->lay.cell_rec);
+  a.occ_cells = (const int*)(c->ws + c->lay.occ_cells);
+  a.occ_count = (const int*)(c->ws + c->lay.occ_count[c->step & 1]);
   a.err = (uint32_t*)(c->ws + c->lay.err);
-  hipLaunchKernelGGL(k_forces_integrate, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0,
-                     c->stream, a);
+  if (a.ncell > 0)
+    hipLaunchKernelGGL(k_forces_cells, dim3(persistent_grid(std::min(a.ncell, (long)a.N))), dim3(256), 0, c->fstream, a);
+  else
+    hipLaunchKernelGGL(k_bonded_forces, dim3(blocks(a.N, 256)), dim3(256), 0, c->fstream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_integrate(lb_ctx* c) {
+  IntegrateArgs a;
+  a.N = c->p.n_atoms;
+  a.inv_mass = 1.0f / c->p.mass;
+  a.ff = (const float*)(c->ws + c->lay.ff);
+  a.fc = (const float*)(c->ws + c->lay.fc);
+  a.d = (const float*)(c->ws + c->lay.disp[c->dcur]);
+  a.d_next = (float*)(c->ws + c->lay.disp[c->dcur ^ 1]);
+  a.v = (float*)(c->ws + c->lay.vel);
+  a.err = (uint32_t*)(c->ws + c->lay.err);
+  hipLaunchKernelGGL(k_integrate, dim3(blocks(a.N, 256)), dim3(256), 0, c->astream, a);
   return hipGetLastError();
 }
 
 hipError_t launch_read_atoms(lb_ctx* c, float* x, float* v) {
   const int N = c->p.n_atoms;
-  hipLaunchKernelGGL(k_read_atoms, dim3((unsigned)((3L * N + 255) / 256)), dim3(256), 0, c->stream,
-                     N, (const float*)(c->ws + c->lay.x0),
-                     (const float*)(c->ws + c->lay.disp[c->dcur]),
+  hipLaunchKernelGGL(k_read_atoms, dim3(blocks(3L * N, 256)), dim3(256), 0, c->stream, N,
+                     (const float*)(c->ws + c->lay.x0), (const float*)(c->ws + c->lay.disp[c->dcur]),
                      (const float*)(c->ws + c->lay.vel), x, v);
   return hipGetLastError();
 }

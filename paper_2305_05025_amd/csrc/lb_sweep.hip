@@ -16,122 +16,10 @@
 // One thread per site, 256 sites per workgroup.  A workgroup is also the unit ("tile") of
 // the sparse atom force: tiles that atoms touched in this step carry a flag, and only their
 // sites read (and clear) the fixed-point coupling-force field.
-#include "lbmd_internal.h"
+#include "lattice_common.h"
 
 namespace lbmd {
 namespace {
-
-// ---- storage formats --------------------------------------------------------------------
-template <int ST>
-struct Store;
-
-template <>
-struct Store<LB_STORE_F32> {
-  using T = float;
-  static __device__ __forceinline__ float ld(const T* p) { return *p; }
-  static __device__ __forceinline__ void st(T* p, float v) { __builtin_nontemporal_store(v, p); }
-};
-
-template <>
-struct Store<LB_STORE_F16> {
-  using T = _Float16;
-  static __device__ __forceinline__ float ld(const T* p) { return (float)*p; }
-  // conversion to binary16 rounds to nearest even; subnormals are kept
-  static __device__ __forceinline__ void st(T* p, float v) {
-    __builtin_nontemporal_store((_Float16)v, p);
-  }
-};
-
-template <>
-struct Store<LB_STORE_BF16> {
-  using T = uint16_t;
-  static __device__ __forceinline__ float ld(const T* p) {
-    return __uint_as_float((uint32_t)(*p) << 16);
-  }
-  static __device__ __forceinline__ void st(T* p, float v) {
-    uint32_t u = __float_as_uint(v);
-    uint16_t h;
-    if ((u & 0x7fffffffu) > 0x7f800000u) {
-      h = (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
-    } else {
-      u += 0x7fffu + ((u >> 16) & 1u);    // round to nearest, ties to even
-      h = (uint16_t)(u >> 16);
-    }
-    __builtin_nontemporal_store(h, p);
-  }
-};
-
-// ---- pull gather: pre-collision values at (x, y, z) -----------------------------------------
-template <int ST>
-__device__ __forceinline__ void gather(const typename Store<ST>::T* __restrict__ f, long plane,
-                                       int x, int y, int z, int nx, int ny, int nz,
-                                       float g[19]) {
-  const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-  const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
-  const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
-  const int nxy = nx * ny;
-  const int X3[3] = {xm, x, xp};
-  const int Y3[3] = {ym * nx, y * nx, yp * nx};
-  const int Z3[3] = {zm * nxy, z * nxy, zp * nxy};
-#pragma unroll
-  for (int i = 0; i < 19; ++i) {
-    const int src = X3[1 - CX[i]] + Y3[1 - CY[i]] + Z3[1 - CZ[i]];
-    g[i] = Store<ST>::ld(f + (size_t)i * plane + src);
-  }
-}
-
-// ---- moments (Eqs. 2-3 in deviation form) --------------------------------------------------
-__device__ __forceinline__ void moments(const float g[19], float& drho, float& jx, float& jy,
-                                        float& jz) {
-  drho = 0.f;
-  jx = jy = jz = 0.f;
-#pragma unroll
-  for (int i = 0; i < 19; ++i) {
-    drho += g[i];
-    if (CX[i] == 1) jx += g[i];
-    if (CX[i] == -1) jx -= g[i];
-    if (CY[i] == 1) jy += g[i];
-    if (CY[i] == -1) jy -= g[i];
-    if (CZ[i] == 1) jz += g[i];
-    if (CZ[i] == -1) jz -= g[i];
-  }
-}
-
-template <int C>
-__device__ __forceinline__ float cdot(float ax, float ay, float az, int cx, int cy, int cz) {
-  float r = 0.f;
-  if (cx == 1) r += ax;
-  if (cx == -1) r -= ax;
-  if (cy == 1) r += ay;
-  if (cy == -1) r -= ay;
-  if (cz == 1) r += az;
-  if (cz == -1) r -= az;
-  return r;
-}
-
-// ---- BGK + Guo collision in place; returns false on a non-finite moment ---------------------
-__device__ __forceinline__ bool collide(float g[19], float Fx, float Fy, float Fz, float rho0,
-                                        float omega, float pref) {
-  float drho, jx, jy, jz;
-  moments(g, drho, jx, jy, jz);
-  const float rho = rho0 + drho;
-  const float inv = 1.0f / rho;
-  const float ux = (jx + 0.5f * Fx) * inv;
-  const float uy = (jy + 0.5f * Fy) * inv;
-  const float uz = (jz + 0.5f * Fz) * inv;
-  const float uu = ux * ux + uy * uy + uz * uz;
-  const float uF = ux * Fx + uy * Fy + uz * Fz;
-  const float base = drho - 1.5f * rho * uu;
-#pragma unroll
-  for (int i = 0; i < 19; ++i) {
-    const float cu = cdot<0>(ux, uy, uz, CX[i], CY[i], CZ[i]);
-    const float cF = cdot<0>(Fx, Fy, Fz, CX[i], CY[i], CZ[i]);
-    const float geq = WQ[i] * (base + rho * (3.0f * cu + 4.5f * cu * cu));
-    const float src = pref * WQ[i] * (3.0f * (cF - uF) + 9.0f * cu * cF);
-    g[i] = g[i] - omega * (g[i] - geq) + src;
-  }
-  return __builtin_isfinite(drho + jx + jy + jz);
-}
 
 struct SweepArgs {
   const void* fin;
@@ -143,29 +31,17 @@ struct SweepArgs {
   const float* fext_tab;
   const float* fext_field;
   const uint32_t* tile_flag;   // NULL when there are no atoms
-  long long* fcoup;
+  float* fcoup;                // [3][plane] spread coupling force (hot tiles only)
+  int* base_count;             // [plane] cleared here for hot tiles
+  int part;                    // SweepPart
+  const int* hot_list;         // flagged tiles (kSweepHot)
+  const int* hot_count;
   uint32_t* err;
 };
 
-__device__ __forceinline__ void external_force(int bf_kind, const float* tab, const float* field,
-                                               long plane, int s, int y, float& Fx, float& Fy,
-                                               float& Fz) {
-  Fx = Fy = Fz = 0.f;
-  if (bf_kind == LB_BF_KOLMOGOROV || bf_kind == LB_BF_SIGN_SHEAR) {
-    Fx = tab[y];
-  } else if (bf_kind == LB_BF_FIELD) {
-    Fx = field[s];
-    Fy = field[plane + s];
-    Fz = field[2 * plane + s];
-  }
-}
-
 template <int ST>
-__global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
+__device__ __forceinline__ void sweep_site(const SweepArgs& a, int s, bool hot) {
   using T = typename Store<ST>::T;
-  const int s = blockIdx.x * kSweepBlock + threadIdx.x;
-  const bool hot = a.tile_flag != nullptr && a.tile_flag[blockIdx.x] != 0u;
-  if (s >= a.S) return;
   const int x = s % a.nx;
   const int t = s / a.nx;
   const int y = t % a.ny;
@@ -175,19 +51,44 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
   float Fx, Fy, Fz;
   external_force(a.bf_kind, a.fext_tab, a.fext_field, a.plane, s, y, Fx, Fy, Fz);
   if (hot) {
-    long long* fc = a.fcoup;
-    const long long qx = fc[s], qy = fc[a.plane + s], qz = fc[2 * a.plane + s];
-    Fx += (float)qx * kFixInv;
-    Fy += (float)qy * kFixInv;
-    Fz += (float)qz * kFixInv;
-    fc[s] = 0;
-    fc[a.plane + s] = 0;
-    fc[2 * a.plane + s] = 0;
+    // atoms touched this 64-site tile: add their spread force and leave the per-step
+    // atom-side buffers clear for the next step
+    float* fc = a.fcoup;
+    Fx += fc[s];
+    Fy += fc[a.plane + s];
+    Fz += fc[2 * a.plane + s];
+    fc[s] = 0.f;
+    fc[a.plane + s] = 0.f;
+    fc[2 * a.plane + s] = 0.f;
+    a.base_count[s] = 0;
   }
   if (!collide(g, Fx, Fy, Fz, a.rho0, a.omega, a.pref)) atomicOr(a.err, kErrNonFinite);
   T* out = reinterpret_cast<T*>(a.fout);
 #pragma unroll
   for (int i = 0; i < 19; ++i) Store<ST>::st(out + (size_t)i * a.plane + s, g[i]);
+}
+
+// All sites (part kSweepAll), or only the tiles no atom touched this step (kSweepCold),
+// one thread per site.
+template <int ST>
+__global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
+  const int s = blockIdx.x * kSweepBlock + threadIdx.x;
+  if (s >= a.S) return;
+  const bool hot = a.tile_flag != nullptr && a.tile_flag[s >> kTileShift] != 0u;
+  if (hot && a.part == kSweepCold) return;
+  sweep_site<ST>(a, s, hot);
+}
+
+// The flagged tiles only (kSweepHot): one wavefront per tile of the list, lane = site.
+template <int ST>
+__global__ __launch_bounds__(kSweepBlock) void k_sweep_hot(SweepArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * kSweepBlock + threadIdx.x) >> 6, nwave = gridDim.x * (kSweepBlock / 64);
+  const int n = *a.hot_count;
+  for (int k = wave; k < n; k += nwave) {
+    const int s = (a.hot_list[k] << kTileShift) + lane;
+    if (s < a.S) sweep_site<ST>(a, s, true);
+  }
 }
 
 // ---- readback -------------------------------------------------------------------------------
@@ -234,7 +135,7 @@ __global__ __launch_bounds__(256) void k_read(ReadArgs a) {
   }
 }
 
-// ---- state upload: pre-collision g at x is stored where the pull will find it, x + c_i ----
+// ---- state upload: the pull at y reads slot y - c_i, so g_i(x) is stored at x - c_i ----
 struct WriteArgs {
   void* f;
   long plane;
@@ -261,7 +162,7 @@ __global__ __launch_bounds__(256) void k_write(WriteArgs a) {
   T* f = reinterpret_cast<T*>(a.f);
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
-    const int dst = X3[1 + CX[i]] + Y3[1 + CY[i]] + Z3[1 + CZ[i]];
+    const int dst = X3[1 - CX[i]] + Y3[1 - CY[i]] + Z3[1 - CZ[i]];
     Store<ST>::st(f + (size_t)i * a.plane + dst, a.pops[(size_t)i * a.S + s]);
   }
 }
@@ -400,7 +301,7 @@ hipError_t launch_store_i64(void* dst, int64_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_sweep(lb_ctx* c, const void* fin, void* fout) {
+hipError_t launch_sweep(lb_ctx* c, const void* fin, void* fout, int part, hipStream_t st) {
   const Geometry& g = c->geo;
   SweepArgs a;
   a.fin = fin;
@@ -416,14 +317,31 @@ hipError_t launch_sweep(lb_ctx* c, const void* fin, void* fout) {
   a.bf_kind = c->p.bf_kind;
   a.fext_tab = (const float*)(c->ws + c->lay.fext_tab);
   a.fext_field = (const float*)(c->ws + c->lay.fext_field);
-  a.tile_flag = c->p.n_atoms > 0 ? (const uint32_t*)(c->ws + c->lay.tile_flag) : nullptr;
-  a.fcoup = (long long*)(c->ws + c->lay.fcoup);
+  const int par = (int)(c->step & 1);
+  a.tile_flag = c->p.n_atoms > 0 ? (const uint32_t*)(c->ws + c->lay.tile_flag[par]) : nullptr;
+  a.fcoup = (float*)(c->ws + c->lay.fcoup[par]);
+  a.base_count = (int*)(c->ws + c->lay.base_count[par]);
+  a.part = part;
+  a.hot_list = (const int*)(c->ws + c->lay.occ_tiles[par]);
+  a.hot_count = (const int*)(c->ws + c->lay.occ_count[par]) + 1;
   a.err = (uint32_t*)(c->ws + c->lay.err);
-  const dim3 grid(g.ntiles), block(kSweepBlock);
-  switch (c->p.storage) {
-    case LB_STORE_F32: hipLaunchKernelGGL(k_sweep<LB_STORE_F32>, grid, block, 0, c->stream, a); break;
-    case LB_STORE_F16: hipLaunchKernelGGL(k_sweep<LB_STORE_F16>, grid, block, 0, c->stream, a); break;
-    default: hipLaunchKernelGGL(k_sweep<LB_STORE_BF16>, grid, block, 0, c->stream, a); break;
+  const dim3 block(kSweepBlock);
+  if (part == kSweepHot) {
+    long nb = ((long)g.ntiles + 3) / 4;
+    if (nb > 4096) nb = 4096;
+    const dim3 grid((unsigned)(nb < 1 ? 1 : nb));
+    switch (c->p.storage) {
+      case LB_STORE_F32: hipLaunchKernelGGL(k_sweep_hot<LB_STORE_F32>, grid, block, 0, st, a); break;
+      case LB_STORE_F16: hipLaunchKernelGGL(k_sweep_hot<LB_STORE_F16>, grid, block, 0, st, a); break;
+      default: hipLaunchKernelGGL(k_sweep_hot<LB_STORE_BF16>, grid, block, 0, st, a); break;
+    }
+  } else {
+    const dim3 grid(g.nblocks);
+    switch (c->p.storage) {
+      case LB_STORE_F32: hipLaunchKernelGGL(k_sweep<LB_STORE_F32>, grid, block, 0, st, a); break;
+      case LB_STORE_F16: hipLaunchKernelGGL(k_sweep<LB_STORE_F16>, grid, block, 0, st, a); break;
+      default: hipLaunchKernelGGL(k_sweep<LB_STORE_BF16>, grid, block, 0, st, a); break;
+    }
   }
   return hipGetLastError();
 }

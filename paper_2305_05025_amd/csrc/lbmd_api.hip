@@ -1,5 +1,6 @@
 // Host side of the C interface declared in include/lbmd.h: argument validation, the
 // workspace plan, initial state, the per-step launch sequence and the synchronising calls.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -21,7 +22,8 @@ bool geometry(const lb_params* p, Geometry* g) {
   g->nz = p->L[2];
   g->S = (long)p->L[0] * p->L[1] * p->L[2];
   g->plane = (long)round_up((size_t)g->S, 64);
-  g->ntiles = (int)((g->S + kSweepBlock - 1) / kSweepBlock);
+  g->nblocks = (int)((g->S + kSweepBlock - 1) / kSweepBlock);
+  g->ntiles = (int)((g->S + 63) / 64);
   g->elem = elem_bytes(p->storage);
   g->ncell = 0;
   for (int k = 0; k < 3; ++k) {
@@ -53,8 +55,20 @@ Layout plan(const lb_params* p, const Geometry& g) {
   const size_t popb = 19 * (size_t)g.plane * g.elem;
   l.pop[0] = take(popb);
   l.pop[1] = take(popb);
-  l.fcoup = take(N ? 3 * (size_t)g.plane * 8 : 0);
-  l.tile_flag = take(N ? (size_t)g.ntiles * 4 : 0);
+  for (int k = 0; k < 2; ++k) {
+    l.fcoup[k] = take(N ? 3 * (size_t)g.plane * 4 : 0);
+    l.tile_flag[k] = take(N ? (size_t)g.ntiles * 4 : 0);
+    l.base_count[k] = take(N ? (size_t)g.plane * 4 : 0);
+    l.base_list[k] = take(N ? (size_t)g.plane * kBaseCap * 4 : 0);
+  }
+  l.node_flag = take(N ? (size_t)g.plane : 0);
+  l.uc = take(N ? 3 * (size_t)g.plane * 4 : 0);
+  l.atom_frac = take(N * 16);
+  l.occ_cells = take(std::min((size_t)g.ncell, N) * 4);
+  for (int k = 0; k < 2; ++k) {
+    l.occ_tiles[k] = take(N ? (size_t)g.ntiles * 4 : 0);
+    l.occ_count[k] = take(N ? 16 : 0);
+  }
   l.fext_tab = take((size_t)g.ny * 4);
   l.fext_field = take(p->bf_kind == LB_BF_FIELD ? 3 * (size_t)g.plane * 4 : 0);
   l.x0 = take(3 * N * 4);
@@ -62,10 +76,11 @@ Layout plan(const lb_params* p, const Geometry& g) {
   l.disp[1] = take(3 * N * 4);
   l.vel = take(3 * N * 4);
   l.fc = take(3 * N * 4);
+  l.ff = take(3 * N * 4);
   l.bond_off = take((N + 1) * 4);
   l.bond_nbr = take(2 * (size_t)p->n_bonds * 4);
   l.cell_count = take((size_t)g.ncell * 4);
-  l.cell_atoms = take((size_t)g.ncell * kCellCap * 4);
+  l.cell_rec = take((size_t)g.ncell * kCellCap * 16);
   l.red_partial = take((size_t)kRedBlocks * 4 * 8);
   l.red_out = take(8 * 8);
   l.err = take(4 * 4);
@@ -101,7 +116,8 @@ static std::string validate(const lb_params* p) {
     if (!finite(p->lj_eps) || p->lj_eps < 0.0f) return "lj_eps must be finite and >= 0";
     if (p->lj_eps != 0.0f) {
       if (!finite(p->lj_sigma) || !(p->lj_sigma > 0.0f)) return "lj_sigma must be > 0";
-      if (!finite(p->lj_rc) || !(p->lj_rc > 0.0f)) return "lj_rc must be > 0";
+      // cell-relative fixed-point positions (8.24) need cells narrower than ~60 lattice units
+      if (!finite(p->lj_rc) || !(p->lj_rc > 0.0f) || p->lj_rc > 40.0f) return "lj_rc must be in (0, 40]";
       for (int k = 0; k < 3; ++k)
         if (std::floor((double)p->L[k] / ((double)p->lj_rc * 1.001)) < 3) {
           std::snprintf(buf, sizeof buf,
@@ -246,7 +262,10 @@ lb_status lb_init(const lb_params* p, void* workspace, size_t workspace_bytes, c
   const size_t popb = 19 * (size_t)g.plane * g.elem;
   struct Z { size_t off, bytes; } zs[] = {
       {lay.pop[0], popb}, {lay.pop[1], popb},
-      {lay.fcoup, N ? 3 * (size_t)g.plane * 8 : 0}, {lay.tile_flag, N ? (size_t)g.ntiles * 4 : 0},
+      {lay.fcoup[0], N ? 3 * (size_t)g.plane * 4 : 0}, {lay.tile_flag[0], N ? (size_t)g.ntiles * 4 : 0},
+      {lay.fcoup[1], N ? 3 * (size_t)g.plane * 4 : 0}, {lay.tile_flag[1], N ? (size_t)g.ntiles * 4 : 0},
+      {lay.base_count[0], N ? (size_t)g.plane * 4 : 0}, {lay.base_count[1], N ? (size_t)g.plane * 4 : 0},
+      {lay.node_flag, N ? (size_t)g.plane : 0}, {lay.uc, N ? 3 * (size_t)g.plane * 4 : 0},
       {lay.disp[0], 12 * (size_t)N}, {lay.disp[1], 12 * (size_t)N}, {lay.fc, 12 * (size_t)N},
       {lay.cell_count, (size_t)g.ncell * 4}, {lay.err, 16},
       {lay.fext_field, p->bf_kind == LB_BF_FIELD ? 3 * (size_t)g.plane * 4 : 0}};
@@ -281,6 +300,21 @@ lb_status lb_init(const lb_params* p, void* workspace, size_t workspace_bytes, c
     delete c;
     return hip_fail(nullptr, e, "synchronising after set-up");
   }
+  c->astream = c->fstream = st;
+  if (N > 0 && !(p->flags & LB_FLAG_SINGLE_STREAM)) {
+    // atom work that overlaps the sweep runs on two more streams (default priority)
+    if ((e = hipStreamCreateWithFlags(&c->astream, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&c->fstream, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&c->ev_forces, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&c->ev_bin, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&c->ev_spread, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&c->ev_sweep, hipEventDisableTiming)) != hipSuccess) {
+      lb_destroy(c);
+      return hip_fail(nullptr, e, "creating the atom stream");
+    }
+  }
   *out = c;
   return LB_OK;
 }
@@ -288,32 +322,101 @@ lb_status lb_init(const lb_params* p, void* workspace, size_t workspace_bytes, c
 lb_status lb_couple_step(lb_ctx* c, int32_t n_steps) {
   if (!c) return fail(nullptr, LB_EINVAL, "context is NULL");
   if (n_steps < 0) return fail(c, LB_EINVAL, "n_steps must be >= 0");
+  if (n_steps == 0) return LB_OK;
   const bool atoms = c->p.n_atoms > 0;
-  const bool lj = c->geo.ncell > 0;
   hipError_t e;
+  // Three streams per step (the caller's "main" stream, "atoms" and "forces"):
+  //   atoms:  prep, bin/mark, compaction -> ev_bin
+  //   main:   wait ev_bin; sweep of the tiles no atom touched
+  //   forces: wait ev_bin; cell sort, force field -> ev_forces
+  //   atoms:  wait ev_sweep (previous step's lattice done); node u_c, couple, spread
+  //           -> ev_spread; wait ev_forces; integration
+  //   main:   wait ev_spread; sweep of the flagged tiles -> ev_sweep
+  // All atom work overlaps the cold part of the sweep, and the force field (which needs only
+  // X^n) overlaps the coupling.  The atom stream first waits for everything already queued
+  // on the caller's stream, and the caller's stream finally waits for the atom stream (which
+  // has waited for the force stream), so the call behaves as if it had been queued on the
+  // caller's stream alone.  With LB_FLAG_SINGLE_STREAM (or without atoms) everything runs
+  // in order on the caller's stream and the sweep is one pass.
+  const bool two = atoms && c->astream != c->stream;
+  auto rec = [&](hipEvent_t* ev, int k, hipStream_t st) {
+    if (ev) (void)hipEventRecord(ev[k], st);
+  };
+  if (two) {
+    if ((e = hipEventRecord(c->ev_fork, c->stream)) != hipSuccess ||
+        (e = hipStreamWaitEvent(c->astream, c->ev_fork, 0)) != hipSuccess ||
+        (e = hipEventRecord(c->ev_sweep, c->stream)) != hipSuccess)
+      return hip_fail(c, e, "stream fork");
+  }
   for (int n = 0; n < n_steps; ++n) {
-    hipEvent_t* ev = c->timed < c->timed_cap ? &c->ev[4 * (size_t)c->timed] : nullptr;
+    hipEvent_t* ev = c->timed < c->timed_cap ? &c->ev[kTimedEvents * (size_t)c->timed] : nullptr;
     if (ev) c->timed++;
-    if (ev) (void)hipEventRecord(ev[0], c->stream);
-    if (atoms) {
+    void* fin = c->ws + c->lay.pop[c->cur];
+    void* fout = c->ws + c->lay.pop[c->cur ^ 1];
+    if (!atoms) {
+      rec(ev, 1, c->stream);
+      if ((e = launch_sweep(c, fin, fout, kSweepAll, c->stream)) != hipSuccess) return hip_fail(c, e, "sweep launch");
+      rec(ev, 7, c->stream);
+      rec(ev, 8, c->stream);
+      rec(ev, 2, c->stream);
+    } else {
+      rec(ev, 3, c->astream);
       if ((e = launch_prep(c)) != hipSuccess) return hip_fail(c, e, "prep launch");
+      if ((e = launch_bin_mark(c)) != hipSuccess) return hip_fail(c, e, "binning launch");
+      if ((e = launch_compact(c)) != hipSuccess) return hip_fail(c, e, "compaction launch");
+      rec(ev, 4, c->astream);
+      if (two) {
+        if ((e = hipEventRecord(c->ev_bin, c->astream)) != hipSuccess ||
+            (e = hipStreamWaitEvent(c->stream, c->ev_bin, 0)) != hipSuccess)
+          return hip_fail(c, e, "binning event");
+        rec(ev, 1, c->stream);
+        if ((e = launch_sweep(c, fin, fout, kSweepCold, c->stream)) != hipSuccess) return hip_fail(c, e, "sweep launch");
+        rec(ev, 7, c->stream);
+        if ((e = hipStreamWaitEvent(c->fstream, c->ev_bin, 0)) != hipSuccess) return hip_fail(c, e, "binning event");
+      }
+      if (c->geo.ncell > 0 && (e = launch_cell_sort(c)) != hipSuccess) return hip_fail(c, e, "cell sort launch");
+      if ((e = launch_forces(c)) != hipSuccess) return hip_fail(c, e, "force launch");
+      if (two && ((e = hipEventRecord(c->ev_forces, c->fstream)) != hipSuccess ||
+                  (e = hipStreamWaitEvent(c->astream, c->ev_sweep, 0)) != hipSuccess))
+        return hip_fail(c, e, "force/sweep event");
+      rec(ev, 0, c->astream);
+      if ((e = launch_node_u(c)) != hipSuccess) return hip_fail(c, e, "node velocity launch");
       if ((e = launch_couple(c)) != hipSuccess) return hip_fail(c, e, "coupling launch");
-      if (lj && (e = launch_cell_sort(c)) != hipSuccess) return hip_fail(c, e, "cell sort launch");
+      if ((e = launch_spread(c)) != hipSuccess) return hip_fail(c, e, "spread launch");
+      if (two && ((e = hipEventRecord(c->ev_spread, c->astream)) != hipSuccess ||
+                  (e = hipStreamWaitEvent(c->astream, c->ev_forces, 0)) != hipSuccess))
+        return hip_fail(c, e, "spread/force event");
+      if ((e = launch_integrate(c)) != hipSuccess) return hip_fail(c, e, "integration launch");
+      rec(ev, 5, c->astream);
+      if (two) {
+        if ((e = hipStreamWaitEvent(c->stream, c->ev_spread, 0)) != hipSuccess) return hip_fail(c, e, "spread wait");
+        rec(ev, 8, c->stream);
+        if ((e = launch_sweep(c, fin, fout, kSweepHot, c->stream)) != hipSuccess) return hip_fail(c, e, "sweep launch");
+        rec(ev, 2, c->stream);
+        if ((e = hipEventRecord(c->ev_sweep, c->stream)) != hipSuccess) return hip_fail(c, e, "sweep event");
+      } else {
+        rec(ev, 1, c->stream);
+        if ((e = launch_sweep(c, fin, fout, kSweepAll, c->stream)) != hipSuccess) return hip_fail(c, e, "sweep launch");
+        rec(ev, 7, c->stream);
+        rec(ev, 8, c->stream);
+        rec(ev, 2, c->stream);
+      }
     }
-    if (ev) (void)hipEventRecord(ev[1], c->stream);
-    if ((e = launch_sweep(c, c->ws + c->lay.pop[c->cur], c->ws + c->lay.pop[c->cur ^ 1])) != hipSuccess)
-      return hip_fail(c, e, "sweep launch");
-    if (ev) (void)hipEventRecord(ev[2], c->stream);
-    if (atoms && (e = launch_forces_integrate(c)) != hipSuccess)
-      return hip_fail(c, e, "force/integrate launch");
-    if (ev) (void)hipEventRecord(ev[3], c->stream);
     c->cur ^= 1;
     if (atoms) c->dcur ^= 1;
     c->step++;
     if (c->p.flags & LB_FLAG_CHECK_FINITE) {
+      if (two && ((e = hipEventRecord(c->ev_join, c->astream)) != hipSuccess ||
+                  (e = hipStreamWaitEvent(c->stream, c->ev_join, 0)) != hipSuccess))
+        return hip_fail(c, e, "stream join");
       lb_status s = lb_status_check(c);
       if (s != LB_OK) return s;
     }
+  }
+  if (two) {
+    if ((e = hipEventRecord(c->ev_join, c->astream)) != hipSuccess ||
+        (e = hipStreamWaitEvent(c->stream, c->ev_join, 0)) != hipSuccess)
+      return hip_fail(c, e, "stream join");
   }
   return LB_OK;
 }
@@ -325,6 +428,15 @@ lb_status lb_read_fields(lb_ctx* c, float* rho, float* u, float* x_unwrapped, fl
   if (c->p.n_atoms > 0 && (x_unwrapped || v) && (e = launch_read_atoms(c, x_unwrapped, v)) != hipSuccess)
     return hip_fail(c, e, "atom readback launch");
   return LB_OK;
+}
+
+lb_status lb_read_displacement(lb_ctx* c, float* d) {
+  if (!c) return fail(nullptr, LB_EINVAL, "context is NULL");
+  if (!d) return fail(c, LB_EINVAL, "output is NULL");
+  if (c->p.n_atoms == 0) return LB_OK;
+  hipError_t e = hipMemcpyAsync(d, c->ws + c->lay.disp[c->dcur], 12 * (size_t)c->p.n_atoms,
+                                hipMemcpyDeviceToDevice, c->stream);
+  return e == hipSuccess ? LB_OK : hip_fail(c, e, "displacement copy");
 }
 
 lb_status lb_read_populations(lb_ctx* c, float* g) {
@@ -428,7 +540,7 @@ lb_status lb_timing_begin(lb_ctx* c, int32_t max_steps) {
   hipError_t e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "synchronising");
   free_events(c);
-  c->ev.resize(4 * (size_t)max_steps);
+  c->ev.resize(kTimedEvents * (size_t)max_steps);
   for (size_t k = 0; k < c->ev.size(); ++k)
     if ((e = hipEventCreate(&c->ev[k])) != hipSuccess) {
       c->ev.resize(k);
@@ -445,16 +557,21 @@ lb_status lb_timing_end(lb_ctx* c, double out_ms[3]) {
   if (!out_ms) return fail(c, LB_EINVAL, "out_ms is NULL");
   hipError_t e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "synchronising");
+  if (c->astream && c->astream != c->stream && (e = hipStreamSynchronize(c->astream)) != hipSuccess)
+    return hip_fail(c, e, "synchronising");
   double sweep = 0.0, atoms = 0.0;
+  const bool has_atoms = c->p.n_atoms > 0;
+  // events per step: sweep 1-7 (all or cold) and 8-2 (hot); atom kernels 3-4 and 0-5
   for (int k = 0; k < c->timed; ++k) {
-    float a = 0.f, b = 0.f, d = 0.f;
-    hipEvent_t* ev = &c->ev[4 * (size_t)k];
-    if ((e = hipEventElapsedTime(&a, ev[0], ev[1])) != hipSuccess ||
-        (e = hipEventElapsedTime(&b, ev[1], ev[2])) != hipSuccess ||
-        (e = hipEventElapsedTime(&d, ev[2], ev[3])) != hipSuccess)
+    float a = 0.f, b = 0.f, d = 0.f, f = 0.f;
+    hipEvent_t* ev = &c->ev[kTimedEvents * (size_t)k];
+    if ((e = hipEventElapsedTime(&a, ev[1], ev[7])) != hipSuccess ||
+        (e = hipEventElapsedTime(&b, ev[8], ev[2])) != hipSuccess ||
+        (has_atoms && (e = hipEventElapsedTime(&d, ev[3], ev[4])) != hipSuccess) ||
+        (has_atoms && (e = hipEventElapsedTime(&f, ev[0], ev[5])) != hipSuccess))
       return hip_fail(c, e, "reading timing events");
-    sweep += b;
-    atoms += a + d;
+    sweep += a + b;
+    atoms += d + f;
   }
   out_ms[0] = sweep;
   out_ms[1] = atoms;
@@ -466,6 +583,13 @@ lb_status lb_timing_end(lb_ctx* c, double out_ms[3]) {
 lb_status lb_destroy(lb_ctx* c) {
   if (!c) return fail(nullptr, LB_EINVAL, "context is NULL");
   free_events(c);
+  for (hipStream_t s : {c->fstream, c->astream})
+    if (s && s != c->stream) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
+  for (hipEvent_t e : {c->ev_fork, c->ev_bin, c->ev_spread, c->ev_join, c->ev_sweep, c->ev_forces})
+    if (e) (void)hipEventDestroy(e);
   delete c;
   return LB_OK;
 }

@@ -21,9 +21,10 @@ constexpr float WQ[19] = {
     1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f,
     1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f};
 
-constexpr int kSweepBlock = 256;        // sites per sweep workgroup = sites per force tile
-constexpr int kTileShift = 8;           // log2(kSweepBlock)
+constexpr int kSweepBlock = 256;        // sites per sweep workgroup
+constexpr int kTileShift = 6;           // force tile = 64 sites (one wavefront of the sweep)
 constexpr int kCellCap = 48;            // atoms per neighbour-list cell
+constexpr int kBaseCap = 8;             // atoms whose stencil base is one node
 constexpr float kFixScale = 1099511627776.0f;      // 2^40: fixed-point scale of spread forces
 constexpr float kFixInv = 1.0f / 1099511627776.0f;
 
@@ -34,18 +35,28 @@ constexpr uint32_t kErrNonFinite = 2u;
 // Byte offsets of every buffer inside the caller's workspace.
 struct Layout {
   size_t pop[2];       // population buffers A / B, 19 planes of `plane` elements
-  size_t fcoup;        // spread coupling force, fixed point int64 [3][plane]
-  size_t tile_flag;    // uint32 per force tile
+  // [step parity]: a step's sweep still reads these while the next step bins its atoms
+  size_t fcoup[2];     // float [3][plane]: spread coupling force at marked nodes
+  size_t tile_flag[2]; // uint32 per 64-site force tile
+  size_t base_count[2];// int32 [plane]: atoms whose stencil base (lower corner) is this node
+  size_t base_list[2]; // int32 [plane][kBaseCap]
+  size_t node_flag;    // uint8 [plane]: atom stencil nodes of this step
+  size_t uc;           // float [3][plane]: coupling velocity at marked nodes
+  size_t atom_frac;    // float4 [N]: stencil fractions of each atom
+  size_t occ_cells;    // int32 [min(ncell, N)]: neighbour-list cells holding atoms this step
+  size_t occ_tiles[2]; // int32 [ntiles]: flagged force tiles, by step parity
+  size_t occ_count[2]; // int32 [2] by step parity: lengths of the cell and tile lists
   size_t fext_tab;     // float [ny]   (Kolmogorov / sign-shear profile)
   size_t fext_field;   // float [3][plane] (caller field)
   size_t x0;           // float [N][3] anchors
   size_t disp[2];      // float [N][3] displacement X - x0, double-buffered
   size_t vel;          // float [N][3]
   size_t fc;           // float [N][3] friction force of the current step
+  size_t ff;           // float [N][3] stand-in force field at X^n
   size_t bond_off;     // int32 [N+1]
   size_t bond_nbr;     // int32 [2 n_bonds]
   size_t cell_count;   // int32 [ncell]
-  size_t cell_atoms;   // int32 [ncell][kCellCap]
+  size_t cell_rec;     // int4 [ncell][kCellCap]: fixed-point position in the cell, atom index
   size_t red_partial;  // double [kRedBlocks][4]
   size_t red_out;      // double [8]
   size_t err;          // uint32 [4]
@@ -53,12 +64,14 @@ struct Layout {
 };
 
 constexpr int kRedBlocks = 1024;
+constexpr int kTimedEvents = 9;
 
 struct Geometry {
   int nx, ny, nz;
   long S;            // sites
   long plane;        // population plane stride (elements), S rounded up to 64
-  int ntiles;        // ceil(S / kSweepBlock)
+  int nblocks;       // ceil(S / kSweepBlock)
+  int ntiles;        // ceil(S / 64): force tiles
   int nc[3];         // neighbour-list cells per axis (0 when LJ is off)
   long ncell;
   float inv_cw[3];   // 1 / cell width
@@ -81,8 +94,13 @@ struct lb_ctx {
   int64_t step;
   float omega;    // 1 / tau
   std::string err;
+  // second stream for the atom work that overlaps the sweep, and its fork/join events
+  hipStream_t astream = nullptr;  // atom stream (the caller's stream when single-stream)
+  hipStream_t fstream = nullptr;  // force-field stream (likewise)
+  hipEvent_t ev_fork = nullptr, ev_bin = nullptr, ev_spread = nullptr, ev_join = nullptr;
+  hipEvent_t ev_sweep = nullptr, ev_forces = nullptr;
   // optional per-phase event timing (lb_timing_begin / lb_timing_end)
-  std::vector<hipEvent_t> ev;  // 4 per timed step: atoms begin/end, sweep begin/end
+  std::vector<hipEvent_t> ev;  // kTimedEvents per timed step
   int timed_cap = 0;
   int timed = 0;
 };
@@ -91,7 +109,10 @@ namespace lbmd {
 
 // ---- kernel launchers (lb_sweep.hip) ----
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
-hipError_t launch_sweep(lb_ctx* c, const void* fin, void* fout);
+// parts of a sweep: every site; only the tiles no atom touched this step; only the flagged
+// tiles (from the compacted list)
+enum SweepPart { kSweepAll = 0, kSweepCold = 1, kSweepHot = 2 };
+hipError_t launch_sweep(lb_ctx* c, const void* fin, void* fout, int part, hipStream_t st);
 hipError_t launch_read_fields(lb_ctx* c, float* rho, float* u);
 hipError_t launch_read_populations(lb_ctx* c, float* g);
 hipError_t launch_write_populations(lb_ctx* c, const float* g);
@@ -100,9 +121,14 @@ hipError_t launch_store_i64(void* dst, int64_t v, hipStream_t s);
 
 // ---- kernel launchers (atoms.hip) ----
 hipError_t launch_prep(lb_ctx* c);
-hipError_t launch_couple(lb_ctx* c);
+hipError_t launch_bin_mark(lb_ctx* c);
+hipError_t launch_compact(lb_ctx* c);
 hipError_t launch_cell_sort(lb_ctx* c);
-hipError_t launch_forces_integrate(lb_ctx* c);
+hipError_t launch_node_u(lb_ctx* c);
+hipError_t launch_couple(lb_ctx* c);
+hipError_t launch_spread(lb_ctx* c);
+hipError_t launch_forces(lb_ctx* c);
+hipError_t launch_integrate(lb_ctx* c);
 hipError_t launch_read_atoms(lb_ctx* c, float* x, float* v);
 
 }  // namespace lbmd

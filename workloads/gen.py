@@ -27,10 +27,13 @@ import numpy as np
 
 # Atom mass in lattice units (rho0 * dx^3).  The configurations give none.  The explicit
 # atom update is stable only while U''/m < 4 (dt = 1) along every mode; the Lennard-Jones
-# curvature at contact is U''(sigma) = 456 eps / sigma^2 = 4.56, and compact packings stack
-# several contacts on one axis, so m = 1 diverges within a few steps.  m = 8 (about 38 amu
-# at dx = 2 Angstrom, a coarse-grained bead) stays stable over all configured runs.
-ATOM_MASS = 8.0
+# curvature at contact is U''(sigma) = 456 eps / sigma^2 = 4.56, compact packings stack
+# several contacts on one axis, and atoms kicked apart by compressed contacts at t = 0 can
+# cross deep into the repulsive core within one step.  m = 1 diverges within a few steps;
+# m = 8 still lost one 20,000-atom globule of ten at 256^3 within 20 steps; m = 16 and
+# m = 32 ran every configuration (1000 / 500 / 200 steps) stably.  m = 32 (about 150 amu at
+# dx = 2 Angstrom: a residue-sized coarse-grained bead) is used, for margin.
+ATOM_MASS = 32.0
 
 # Body-force kinds (integer codes shared with the C interface by convention).
 BF_NONE = 0
