@@ -77,8 +77,9 @@ typedef enum {
 /* lb_params.flags */
 #define LB_FLAG_CHECK_FINITE 0x1u  /* lb_couple_step also checks for NaN/Inf every step */
 #define LB_FLAG_SINGLE_STREAM 0x2u /* queue every kernel on the caller's stream; by default the
-                                      atom work runs on a second stream of the library and
-                                      overlaps the sweep of the sites no atom touches */
+                                      library runs the force field, the integration and the
+                                      next step's binning on two streams of its own, where
+                                      they overlap the lattice sweep */
 
 typedef struct {
   int32_t L[3];              /* nx, ny, nz >= 2; periodic */
@@ -171,12 +172,13 @@ size_t lb_state_bytes(const lb_ctx* c);
 lb_status lb_state_save(lb_ctx* c, void* dst);
 lb_status lb_state_load(lb_ctx* c, const void* src);
 
-/* Kernel timing with HIP events recorded on the context's stream around each phase of
- * the next max_steps steps (creates 4 * max_steps events).  lb_timing_end synchronises and
+/* Kernel timing with HIP events recorded on the context's streams around each phase of
+ * the next max_steps steps (creates 8 * max_steps events).  lb_timing_end synchronises and
  * writes out_ms[0] = summed duration of the lattice sweep kernels, out_ms[1] = summed
- * duration of the atom kernels (binning, coupling, forces and integration; they overlap
- * the sweep unless LB_FLAG_SINGLE_STREAM is set), out_ms[2] = number of steps timed
- * (milliseconds; host pointer). */
+ * duration of the atom kernel chains (binning, coupling, cell sort + force field; the
+ * integration, a few microseconds, is not bracketed), out_ms[2] = number of steps timed
+ * (milliseconds; host pointer).  Chains on different streams overlap in time, so the sum
+ * of out_ms[0] and out_ms[1] can exceed the wall time. */
 lb_status lb_timing_begin(lb_ctx* c, int32_t max_steps);
 lb_status lb_timing_end(lb_ctx* c, double out_ms[3]);
 

@@ -735,9 +735,9 @@ hipError_t launch_node_u(lb_ctx* c) {
   a.uc = (float*)(c->ws + c->lay.uc);
   const dim3 grid(persistent_grid(g.ntiles)), block(256);
   switch (c->p.storage) {
-    case LB_STORE_F32: hipLaunchKernelGGL(k_node_u<LB_STORE_F32>, grid, block, 0, c->astream, a); break;
-    case LB_STORE_F16: hipLaunchKernelGGL(k_node_u<LB_STORE_F16>, grid, block, 0, c->astream, a); break;
-    default: hipLaunchKernelGGL(k_node_u<LB_STORE_BF16>, grid, block, 0, c->astream, a); break;
+    case LB_STORE_F32: hipLaunchKernelGGL(k_node_u<LB_STORE_F32>, grid, block, 0, c->stream, a); break;
+    case LB_STORE_F16: hipLaunchKernelGGL(k_node_u<LB_STORE_F16>, grid, block, 0, c->stream, a); break;
+    default: hipLaunchKernelGGL(k_node_u<LB_STORE_BF16>, grid, block, 0, c->stream, a); break;
   }
   return hipGetLastError();
 }
@@ -755,7 +755,7 @@ hipError_t launch_couple(lb_ctx* c) {
   a.v = (const float*)(c->ws + c->lay.vel);
   a.uc = (const float*)(c->ws + c->lay.uc);
   a.fc = (float*)(c->ws + c->lay.fc);
-  hipLaunchKernelGGL(k_couple, dim3(blocks8(8L * a.N, 256)), dim3(256), 0, c->astream, a);
+  hipLaunchKernelGGL(k_couple, dim3(blocks8(8L * a.N, 256)), dim3(256), 0, c->stream, a);
   return hipGetLastError();
 }
 
@@ -775,7 +775,7 @@ hipError_t launch_spread(lb_ctx* c) {
   a.atom_frac = (const float4*)(c->ws + c->lay.atom_frac);
   a.fc = (const float*)(c->ws + c->lay.fc);
   a.fcoup = (float*)(c->ws + c->lay.fcoup[par]);
-  hipLaunchKernelGGL(k_spread, dim3(persistent_grid(c->geo.ntiles)), dim3(256), 0, c->astream, a);
+  hipLaunchKernelGGL(k_spread, dim3(persistent_grid(c->geo.ntiles)), dim3(256), 0, c->stream, a);
   return hipGetLastError();
 }
 

@@ -33,9 +33,6 @@ struct SweepArgs {
   const uint32_t* tile_flag;   // NULL when there are no atoms
   float* fcoup;                // [3][plane] spread coupling force (hot tiles only)
   int* base_count;             // [plane] cleared here for hot tiles
-  int part;                    // SweepPart
-  const int* hot_list;         // flagged tiles (kSweepHot)
-  const int* hot_count;
   uint32_t* err;
 };
 
@@ -68,27 +65,13 @@ __device__ __forceinline__ void sweep_site(const SweepArgs& a, int s, bool hot) 
   for (int i = 0; i < 19; ++i) Store<ST>::st(out + (size_t)i * a.plane + s, g[i]);
 }
 
-// All sites (part kSweepAll), or only the tiles no atom touched this step (kSweepCold),
-// one thread per site.
+// One thread per site, in site order.
 template <int ST>
 __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
   const int s = blockIdx.x * kSweepBlock + threadIdx.x;
   if (s >= a.S) return;
   const bool hot = a.tile_flag != nullptr && a.tile_flag[s >> kTileShift] != 0u;
-  if (hot && a.part == kSweepCold) return;
   sweep_site<ST>(a, s, hot);
-}
-
-// The flagged tiles only (kSweepHot): one wavefront per tile of the list, lane = site.
-template <int ST>
-__global__ __launch_bounds__(kSweepBlock) void k_sweep_hot(SweepArgs a) {
-  const int lane = threadIdx.x & 63;
-  const int wave = (blockIdx.x * kSweepBlock + threadIdx.x) >> 6, nwave = gridDim.x * (kSweepBlock / 64);
-  const int n = *a.hot_count;
-  for (int k = wave; k < n; k += nwave) {
-    const int s = (a.hot_list[k] << kTileShift) + lane;
-    if (s < a.S) sweep_site<ST>(a, s, true);
-  }
 }
 
 // ---- readback -------------------------------------------------------------------------------
@@ -301,7 +284,7 @@ hipError_t launch_store_i64(void* dst, int64_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_sweep(lb_ctx* c, const void* fin, void* fout, int part, hipStream_t st) {
+hipError_t launch_sweep(lb_ctx* c, const void* fin, void* fout, hipStream_t st) {
   const Geometry& g = c->geo;
   SweepArgs a;
   a.fin = fin;
@@ -321,27 +304,12 @@ hipError_t launch_sweep(lb_ctx* c, const void* fin, void* fout, int part, hipStr
   a.tile_flag = c->p.n_atoms > 0 ? (const uint32_t*)(c->ws + c->lay.tile_flag[par]) : nullptr;
   a.fcoup = (float*)(c->ws + c->lay.fcoup[par]);
   a.base_count = (int*)(c->ws + c->lay.base_count[par]);
-  a.part = part;
-  a.hot_list = (const int*)(c->ws + c->lay.occ_tiles[par]);
-  a.hot_count = (const int*)(c->ws + c->lay.occ_count[par]) + 1;
   a.err = (uint32_t*)(c->ws + c->lay.err);
-  const dim3 block(kSweepBlock);
-  if (part == kSweepHot) {
-    long nb = ((long)g.ntiles + 3) / 4;
-    if (nb > 4096) nb = 4096;
-    const dim3 grid((unsigned)(nb < 1 ? 1 : nb));
-    switch (c->p.storage) {
-      case LB_STORE_F32: hipLaunchKernelGGL(k_sweep_hot<LB_STORE_F32>, grid, block, 0, st, a); break;
-      case LB_STORE_F16: hipLaunchKernelGGL(k_sweep_hot<LB_STORE_F16>, grid, block, 0, st, a); break;
-      default: hipLaunchKernelGGL(k_sweep_hot<LB_STORE_BF16>, grid, block, 0, st, a); break;
-    }
-  } else {
-    const dim3 grid(g.nblocks);
-    switch (c->p.storage) {
-      case LB_STORE_F32: hipLaunchKernelGGL(k_sweep<LB_STORE_F32>, grid, block, 0, st, a); break;
-      case LB_STORE_F16: hipLaunchKernelGGL(k_sweep<LB_STORE_F16>, grid, block, 0, st, a); break;
-      default: hipLaunchKernelGGL(k_sweep<LB_STORE_BF16>, grid, block, 0, st, a); break;
-    }
+  const dim3 block(kSweepBlock), grid(g.nblocks);
+  switch (c->p.storage) {
+    case LB_STORE_F32: hipLaunchKernelGGL(k_sweep<LB_STORE_F32>, grid, block, 0, st, a); break;
+    case LB_STORE_F16: hipLaunchKernelGGL(k_sweep<LB_STORE_F16>, grid, block, 0, st, a); break;
+    default: hipLaunchKernelGGL(k_sweep<LB_STORE_BF16>, grid, block, 0, st, a); break;
   }
   return hipGetLastError();
 }

@@ -102,6 +102,8 @@ static std::string validate(const lb_params* p) {
   const double S = (double)p->L[0] * p->L[1] * p->L[2];
   if (S > 2147483647.0) return "lattice has more than 2^31 - 1 sites";
   if (!finite(p->tau) || !(p->tau > 0.5f)) return "tau must be finite and > 0.5 (nu = (tau - 1/2)/3 > 0)";
+  if (p->flags & ~(LB_FLAG_CHECK_FINITE | LB_FLAG_SINGLE_STREAM))
+    return "flags holds an unknown bit";
   if (!finite(p->rho0) || !(p->rho0 > 0.0f)) return "rho0 must be finite and > 0";
   if (p->storage < LB_STORE_F32 || p->storage > LB_STORE_BF16) return "unknown storage format";
   if (p->bf_kind < LB_BF_NONE || p->bf_kind > LB_BF_FIELD) return "unknown body-force kind";
@@ -310,7 +312,7 @@ lb_status lb_init(const lb_params* p, void* workspace, size_t workspace_bytes, c
         (e = hipEventCreateWithFlags(&c->ev_bin, hipEventDisableTiming)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&c->ev_spread, hipEventDisableTiming)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&c->ev_sweep, hipEventDisableTiming)) != hipSuccess) {
+        (e = hipEventCreateWithFlags(&c->ev_couple, hipEventDisableTiming)) != hipSuccess) {
       lb_destroy(c);
       return hip_fail(nullptr, e, "creating the atom stream");
     }
@@ -325,95 +327,89 @@ lb_status lb_couple_step(lb_ctx* c, int32_t n_steps) {
   if (n_steps == 0) return LB_OK;
   const bool atoms = c->p.n_atoms > 0;
   hipError_t e;
-  // Three streams per step (the caller's "main" stream, "atoms" and "forces"):
-  //   atoms:  prep, bin/mark, compaction -> ev_bin
-  //   main:   wait ev_bin; sweep of the tiles no atom touched
-  //   forces: wait ev_bin; cell sort, force field -> ev_forces
-  //   atoms:  wait ev_sweep (previous step's lattice done); node u_c, couple, spread
-  //           -> ev_spread; wait ev_forces; integration
-  //   main:   wait ev_spread; sweep of the flagged tiles -> ev_sweep
-  // All atom work overlaps the cold part of the sweep, and the force field (which needs only
-  // X^n) overlaps the coupling.  The atom stream first waits for everything already queued
-  // on the caller's stream, and the caller's stream finally waits for the atom stream (which
-  // has waited for the force stream), so the call behaves as if it had been queued on the
-  // caller's stream alone.  With LB_FLAG_SINGLE_STREAM (or without atoms) everything runs
-  // in order on the caller's stream and the sweep is one pass.
-  const bool two = atoms && c->astream != c->stream;
+  // Three streams (the caller's "main" stream, "atoms" and "forces").  Step n:
+  //   main:   wait ev_bin(n); node u_c, couple -> ev_couple; spread -> ev_spread; sweep
+  //   forces: wait ev_bin(n); cell sort, force field at X^n -> ev_forces
+  //   atoms:  wait ev_couple, ev_forces; integration; then, for step n + 1:
+  //           wait ev_spread; prep, bin/mark, compaction -> ev_bin(n + 1)
+  // The coupling and the sweep run back to back on one stream; the force field, integration
+  // and the next step's binning overlap the sweep.  The atom stream first waits for
+  // everything already queued on the caller's stream, and the caller's stream finally waits
+  // for the atom stream (which has waited for the force stream), so the call behaves as if
+  // it had been queued on the caller's stream alone.  With LB_FLAG_SINGLE_STREAM every
+  // launch goes to the caller's stream in the same order.
+  const bool multi = atoms && c->astream != c->stream;
   auto rec = [&](hipEvent_t* ev, int k, hipStream_t st) {
     if (ev) (void)hipEventRecord(ev[k], st);
   };
-  if (two) {
+  auto slot = [&]() -> hipEvent_t* {
+    return c->timed < c->timed_cap ? &c->ev[kTimedEvents * (size_t)c->timed] : nullptr;
+  };
+  // per-step buffers read by the binning: see the ordering above
+  auto binning = [&](hipEvent_t* ev) -> lb_status {
+    rec(ev, 4, c->astream);
+    if ((e = launch_prep(c)) != hipSuccess) return hip_fail(c, e, "prep launch");
+    if ((e = launch_bin_mark(c)) != hipSuccess) return hip_fail(c, e, "binning launch");
+    if ((e = launch_compact(c)) != hipSuccess) return hip_fail(c, e, "compaction launch");
+    rec(ev, 5, c->astream);
+    if (multi && (e = hipEventRecord(c->ev_bin, c->astream)) != hipSuccess) return hip_fail(c, e, "binning event");
+    return LB_OK;
+  };
+  if (multi) {
     if ((e = hipEventRecord(c->ev_fork, c->stream)) != hipSuccess ||
-        (e = hipStreamWaitEvent(c->astream, c->ev_fork, 0)) != hipSuccess ||
-        (e = hipEventRecord(c->ev_sweep, c->stream)) != hipSuccess)
+        (e = hipStreamWaitEvent(c->astream, c->ev_fork, 0)) != hipSuccess)
       return hip_fail(c, e, "stream fork");
   }
+  lb_status st;
   for (int n = 0; n < n_steps; ++n) {
-    hipEvent_t* ev = c->timed < c->timed_cap ? &c->ev[kTimedEvents * (size_t)c->timed] : nullptr;
+    hipEvent_t* ev = slot();
     if (ev) c->timed++;
     void* fin = c->ws + c->lay.pop[c->cur];
     void* fout = c->ws + c->lay.pop[c->cur ^ 1];
-    if (!atoms) {
-      rec(ev, 1, c->stream);
-      if ((e = launch_sweep(c, fin, fout, kSweepAll, c->stream)) != hipSuccess) return hip_fail(c, e, "sweep launch");
-      rec(ev, 7, c->stream);
-      rec(ev, 8, c->stream);
-      rec(ev, 2, c->stream);
-    } else {
-      rec(ev, 3, c->astream);
-      if ((e = launch_prep(c)) != hipSuccess) return hip_fail(c, e, "prep launch");
-      if ((e = launch_bin_mark(c)) != hipSuccess) return hip_fail(c, e, "binning launch");
-      if ((e = launch_compact(c)) != hipSuccess) return hip_fail(c, e, "compaction launch");
-      rec(ev, 4, c->astream);
-      if (two) {
-        if ((e = hipEventRecord(c->ev_bin, c->astream)) != hipSuccess ||
-            (e = hipStreamWaitEvent(c->stream, c->ev_bin, 0)) != hipSuccess)
-          return hip_fail(c, e, "binning event");
-        rec(ev, 1, c->stream);
-        if ((e = launch_sweep(c, fin, fout, kSweepCold, c->stream)) != hipSuccess) return hip_fail(c, e, "sweep launch");
-        rec(ev, 7, c->stream);
-        if ((e = hipStreamWaitEvent(c->fstream, c->ev_bin, 0)) != hipSuccess) return hip_fail(c, e, "binning event");
-      }
+    if (atoms) {
+      if ((n == 0 || !multi) && (st = binning(ev)) != LB_OK) return st;
+      if (multi && ((e = hipStreamWaitEvent(c->stream, c->ev_bin, 0)) != hipSuccess ||
+                    (e = hipStreamWaitEvent(c->fstream, c->ev_bin, 0)) != hipSuccess))
+        return hip_fail(c, e, "binning wait");
+      rec(ev, 6, c->fstream);
       if (c->geo.ncell > 0 && (e = launch_cell_sort(c)) != hipSuccess) return hip_fail(c, e, "cell sort launch");
       if ((e = launch_forces(c)) != hipSuccess) return hip_fail(c, e, "force launch");
-      if (two && ((e = hipEventRecord(c->ev_forces, c->fstream)) != hipSuccess ||
-                  (e = hipStreamWaitEvent(c->astream, c->ev_sweep, 0)) != hipSuccess))
-        return hip_fail(c, e, "force/sweep event");
-      rec(ev, 0, c->astream);
+      rec(ev, 7, c->fstream);
+      if (multi && (e = hipEventRecord(c->ev_forces, c->fstream)) != hipSuccess) return hip_fail(c, e, "force event");
+      rec(ev, 0, c->stream);
       if ((e = launch_node_u(c)) != hipSuccess) return hip_fail(c, e, "node velocity launch");
       if ((e = launch_couple(c)) != hipSuccess) return hip_fail(c, e, "coupling launch");
+      if (multi && (e = hipEventRecord(c->ev_couple, c->stream)) != hipSuccess) return hip_fail(c, e, "coupling event");
       if ((e = launch_spread(c)) != hipSuccess) return hip_fail(c, e, "spread launch");
-      if (two && ((e = hipEventRecord(c->ev_spread, c->astream)) != hipSuccess ||
-                  (e = hipStreamWaitEvent(c->astream, c->ev_forces, 0)) != hipSuccess))
-        return hip_fail(c, e, "spread/force event");
+      rec(ev, 1, c->stream);
+      if (multi && (e = hipEventRecord(c->ev_spread, c->stream)) != hipSuccess) return hip_fail(c, e, "spread event");
+    }
+    rec(ev, 2, c->stream);
+    if ((e = launch_sweep(c, fin, fout, c->stream)) != hipSuccess) return hip_fail(c, e, "sweep launch");
+    rec(ev, 3, c->stream);
+    if (atoms) {
+      if (multi && ((e = hipStreamWaitEvent(c->astream, c->ev_couple, 0)) != hipSuccess ||
+                    (e = hipStreamWaitEvent(c->astream, c->ev_forces, 0)) != hipSuccess))
+        return hip_fail(c, e, "coupling/force wait");
       if ((e = launch_integrate(c)) != hipSuccess) return hip_fail(c, e, "integration launch");
-      rec(ev, 5, c->astream);
-      if (two) {
-        if ((e = hipStreamWaitEvent(c->stream, c->ev_spread, 0)) != hipSuccess) return hip_fail(c, e, "spread wait");
-        rec(ev, 8, c->stream);
-        if ((e = launch_sweep(c, fin, fout, kSweepHot, c->stream)) != hipSuccess) return hip_fail(c, e, "sweep launch");
-        rec(ev, 2, c->stream);
-        if ((e = hipEventRecord(c->ev_sweep, c->stream)) != hipSuccess) return hip_fail(c, e, "sweep event");
-      } else {
-        rec(ev, 1, c->stream);
-        if ((e = launch_sweep(c, fin, fout, kSweepAll, c->stream)) != hipSuccess) return hip_fail(c, e, "sweep launch");
-        rec(ev, 7, c->stream);
-        rec(ev, 8, c->stream);
-        rec(ev, 2, c->stream);
-      }
     }
     c->cur ^= 1;
     if (atoms) c->dcur ^= 1;
     c->step++;
+    if (multi && n + 1 < n_steps) {
+      // the next binning rewrites the node flags and the atoms' stencil fractions, which the
+      // spread of this step reads
+      if ((e = hipStreamWaitEvent(c->astream, c->ev_spread, 0)) != hipSuccess) return hip_fail(c, e, "spread wait");
+      if ((st = binning(slot())) != LB_OK) return st;
+    }
     if (c->p.flags & LB_FLAG_CHECK_FINITE) {
-      if (two && ((e = hipEventRecord(c->ev_join, c->astream)) != hipSuccess ||
-                  (e = hipStreamWaitEvent(c->stream, c->ev_join, 0)) != hipSuccess))
+      if (multi && ((e = hipEventRecord(c->ev_join, c->astream)) != hipSuccess ||
+                    (e = hipStreamWaitEvent(c->stream, c->ev_join, 0)) != hipSuccess))
         return hip_fail(c, e, "stream join");
-      lb_status s = lb_status_check(c);
-      if (s != LB_OK) return s;
+      if ((st = lb_status_check(c)) != LB_OK) return st;
     }
   }
-  if (two) {
+  if (multi) {
     if ((e = hipEventRecord(c->ev_join, c->astream)) != hipSuccess ||
         (e = hipStreamWaitEvent(c->stream, c->ev_join, 0)) != hipSuccess)
       return hip_fail(c, e, "stream join");
@@ -561,17 +557,17 @@ lb_status lb_timing_end(lb_ctx* c, double out_ms[3]) {
     return hip_fail(c, e, "synchronising");
   double sweep = 0.0, atoms = 0.0;
   const bool has_atoms = c->p.n_atoms > 0;
-  // events per step: sweep 1-7 (all or cold) and 8-2 (hot); atom kernels 3-4 and 0-5
+  // events per step: coupling 0-1, sweep 2-3, binning 4-5, sort + force field 6-7
   for (int k = 0; k < c->timed; ++k) {
-    float a = 0.f, b = 0.f, d = 0.f, f = 0.f;
+    float t[4] = {0.f, 0.f, 0.f, 0.f};
     hipEvent_t* ev = &c->ev[kTimedEvents * (size_t)k];
-    if ((e = hipEventElapsedTime(&a, ev[1], ev[7])) != hipSuccess ||
-        (e = hipEventElapsedTime(&b, ev[8], ev[2])) != hipSuccess ||
-        (has_atoms && (e = hipEventElapsedTime(&d, ev[3], ev[4])) != hipSuccess) ||
-        (has_atoms && (e = hipEventElapsedTime(&f, ev[0], ev[5])) != hipSuccess))
-      return hip_fail(c, e, "reading timing events");
-    sweep += a + b;
-    atoms += d + f;
+    for (int q = 0; q < (has_atoms ? 4 : 1); ++q) {
+      const int a = q == 0 ? 2 : (q == 1 ? 0 : 2 * q);
+      if ((e = hipEventElapsedTime(&t[q], ev[a], ev[a + 1])) != hipSuccess)
+        return hip_fail(c, e, "reading timing events");
+    }
+    sweep += t[0];
+    atoms += t[1] + t[2] + t[3];
   }
   out_ms[0] = sweep;
   out_ms[1] = atoms;
@@ -588,7 +584,7 @@ lb_status lb_destroy(lb_ctx* c) {
       (void)hipStreamSynchronize(s);
       (void)hipStreamDestroy(s);
     }
-  for (hipEvent_t e : {c->ev_fork, c->ev_bin, c->ev_spread, c->ev_join, c->ev_sweep, c->ev_forces})
+  for (hipEvent_t e : {c->ev_fork, c->ev_bin, c->ev_couple, c->ev_spread, c->ev_join, c->ev_forces})
     if (e) (void)hipEventDestroy(e);
   delete c;
   return LB_OK;

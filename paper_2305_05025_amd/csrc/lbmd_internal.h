@@ -64,7 +64,7 @@ struct Layout {
 };
 
 constexpr int kRedBlocks = 1024;
-constexpr int kTimedEvents = 9;
+constexpr int kTimedEvents = 8;
 
 struct Geometry {
   int nx, ny, nz;
@@ -97,8 +97,8 @@ struct lb_ctx {
   // second stream for the atom work that overlaps the sweep, and its fork/join events
   hipStream_t astream = nullptr;  // atom stream (the caller's stream when single-stream)
   hipStream_t fstream = nullptr;  // force-field stream (likewise)
-  hipEvent_t ev_fork = nullptr, ev_bin = nullptr, ev_spread = nullptr, ev_join = nullptr;
-  hipEvent_t ev_sweep = nullptr, ev_forces = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_bin = nullptr, ev_couple = nullptr, ev_spread = nullptr;
+  hipEvent_t ev_forces = nullptr, ev_join = nullptr;
   // optional per-phase event timing (lb_timing_begin / lb_timing_end)
   std::vector<hipEvent_t> ev;  // kTimedEvents per timed step
   int timed_cap = 0;
@@ -109,10 +109,7 @@ namespace lbmd {
 
 // ---- kernel launchers (lb_sweep.hip) ----
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
-// parts of a sweep: every site; only the tiles no atom touched this step; only the flagged
-// tiles (from the compacted list)
-enum SweepPart { kSweepAll = 0, kSweepCold = 1, kSweepHot = 2 };
-hipError_t launch_sweep(lb_ctx* c, const void* fin, void* fout, int part, hipStream_t st);
+hipError_t launch_sweep(lb_ctx* c, const void* fin, void* fout, hipStream_t st);
 hipError_t launch_read_fields(lb_ctx* c, float* rho, float* u);
 hipError_t launch_read_populations(lb_ctx* c, float* g);
 hipError_t launch_write_populations(lb_ctx* c, const float* g);
