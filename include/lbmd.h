@@ -182,6 +182,37 @@ lb_status lb_state_load(lb_ctx* c, const void* src);
 lb_status lb_timing_begin(lb_ctx* c, int32_t max_steps);
 lb_status lb_timing_end(lb_ctx* c, double out_ms[3]);
 
+/* ---- Gradients (discrete adjoint of lb_couple_step) ------------------------------------
+ * The friction coupling of Section 2.2 and the lattice step (Eqs. 1-3) are differentiated in
+ * reverse mode, so that a loss L of the atoms' final positions (and velocities) yields
+ * dL/dgamma, dL/dtau and dL/dF_ext, the derivative with respect to the external force density
+ * at every site.  The forward pass is recomputed from checkpoints segment by segment
+ * (checkpoint-and-recompute), so memory grows with k, not with the number of steps.
+ *
+ * Usage: save the state with lb_state_save into ckpts + s * lb_state_bytes(c) before each
+ * segment s = 0, 1, ... of k steps (the last segment may be shorter), run all n_steps with
+ * lb_couple_step, then call lb_backward.  Size of the adjoint workspace for segments of k
+ * steps (0 if the context has no atoms or k < 1): */
+size_t lb_adjoint_workspace_bytes(const lb_ctx* c, int32_t k);
+
+/* ckpts     device, 256-aligned: ceil(n_steps / k) states of lb_state_bytes(c) each, the s-th
+ *           taken k * s steps after the first; the context must now be n_steps after it
+ *           (LB_ESTATE otherwise)
+ * adj_ws    device, 256-aligned, adj_ws_bytes >= lb_adjoint_workspace_bytes(c, k) (LB_ENOMEM)
+ * dL_dX     device [N][3]: dL/dX at the final step (unwrapped positions); required
+ * dL_dv     device [N][3] dL/dv at the final step, or NULL for zero
+ * dL_dgamma, dL_dtau   host, out (FP64 accumulation on the device)
+ * dL_db     device [3][nz][ny][nx] out (FP32): dL/dF_ext summed over the steps, or NULL
+ * dL_dX0, dL_dv0  device [N][3] out, or NULL: dL/dX and dL/dv at the first checkpoint's step
+ *           (positions taken with the tether anchors held fixed)
+ * Everything runs on the context's stream; the call synchronises before returning.  The
+ * context's state is restored to the one before the call.  Rounding of FP16/BF16 storage is
+ * treated as the identity. */
+lb_status lb_backward(lb_ctx* c, const void* ckpts, int32_t n_steps, int32_t k, void* adj_ws,
+                      size_t adj_ws_bytes, const float* dL_dX, const float* dL_dv,
+                      double* dL_dgamma, double* dL_dtau, float* dL_db, float* dL_dX0,
+                      float* dL_dv0);
+
 /* Release the context (host memory only; the workspace stays the caller's). */
 lb_status lb_destroy(lb_ctx* c);
 

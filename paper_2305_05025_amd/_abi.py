@@ -73,6 +73,11 @@ _SIGS = [
     ("lb_state_load", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("lb_timing_begin", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     ("lb_timing_end", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    ("lb_adjoint_workspace_bytes", ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int32]),
+    ("lb_backward", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     ("lb_destroy", ctypes.c_int, [ctypes.c_void_p]),
     ("lb_last_error", ctypes.c_char_p, [ctypes.c_void_p]),
 ]
@@ -181,6 +186,20 @@ def lb_timing_end(ctx):
     out = (ctypes.c_double * 3)()
     _check(lib().lb_timing_end(ctx, out), ctx)
     return out[0], out[1], int(out[2])
+
+
+def lb_adjoint_workspace_bytes(ctx, k: int) -> int:
+    return int(lib().lb_adjoint_workspace_bytes(ctx, int(k)))
+
+
+def lb_backward(ctx, ckpts: int, n_steps: int, k: int, adj_ws: int, adj_ws_bytes: int, dL_dX: int,
+                dL_dv: int = 0, dL_db: int = 0, dL_dX0: int = 0, dL_dv0: int = 0):
+    """(dL/dgamma, dL/dtau); the device outputs are written in place."""
+    dg, dt = ctypes.c_double(), ctypes.c_double()
+    _check(lib().lb_backward(ctx, ckpts or None, int(n_steps), int(k), adj_ws or None, int(adj_ws_bytes),
+                             dL_dX or None, dL_dv or None, ctypes.byref(dg), ctypes.byref(dt),
+                             dL_db or None, dL_dX0 or None, dL_dv0 or None), ctx)
+    return dg.value, dt.value
 
 
 def lb_destroy(ctx):

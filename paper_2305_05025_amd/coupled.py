@@ -149,6 +149,44 @@ class CoupledLB:
     def load_state(self, snap):
         A.lb_state_load(self.ctx, snap[1])
 
+    # -- gradients (checkpoint-and-recompute adjoint) --------------------------------------
+    def run_checkpointed(self, n_steps: int, k: int) -> dict:
+        """Advance n_steps, saving the state before every segment of k steps (the last segment
+        may be shorter).  Returns the checkpoint record that backward() consumes."""
+        if n_steps < 1 or k < 1:
+            raise ValueError("n_steps and k must be >= 1")
+        sb = A.lb_state_bytes(self.ctx)
+        n_seg = -(-n_steps // k)
+        raw, base = _aligned_workspace(sb * n_seg, self.device)
+        for s in range(n_seg):
+            A.lb_state_save(self.ctx, base + s * sb)
+            A.lb_couple_step(self.ctx, min(k, n_steps - s * k))
+        return {"raw": raw, "ptr": base, "n_steps": int(n_steps), "k": int(k)}
+
+    def backward(self, ckpt: dict, dL_dX, dL_dv=None, want_body_force: bool = True,
+                 want_initial: bool = True) -> dict:
+        """Gradients of a loss L of the final atom state, given dL/dX and dL/dv [N, 3] there:
+        dL/dgamma, dL/dtau (floats), dL/dF_ext [3, nz, ny, nx] and dL/dX, dL/dv at the first
+        checkpoint (tensors, or None when not asked for)."""
+        k = ckpt["k"]
+        nb = A.lb_adjoint_workspace_bytes(self.ctx, k)
+        if nb == 0:
+            raise ValueError("backward needs atoms")
+        raw, adj = _aligned_workspace(nb, self.device)
+        f32 = lambda t: torch.as_tensor(t, dtype=torch.float32).reshape(self.N, 3).contiguous().to(self.device)
+        dX = f32(dL_dX)
+        dv = f32(dL_dv) if dL_dv is not None else None
+        nz, ny, nx = self.L[2], self.L[1], self.L[0]
+        db = torch.empty((3, nz, ny, nx), dtype=torch.float32, device=self.device) if want_body_force else None
+        dX0 = torch.empty((self.N, 3), dtype=torch.float32, device=self.device) if want_initial else None
+        dv0 = torch.empty((self.N, 3), dtype=torch.float32, device=self.device) if want_initial else None
+        ptr = lambda t: t.data_ptr() if t is not None else 0
+        torch.cuda.synchronize(self.device)   # inputs were staged on torch's current stream
+        dg, dt = A.lb_backward(self.ctx, ckpt["ptr"], ckpt["n_steps"], k, adj, nb, dX.data_ptr(),
+                               ptr(dv), ptr(db), ptr(dX0), ptr(dv0))
+        del raw
+        return {"gamma": dg, "tau": dt, "body_force": db, "x0": dX0, "v0": dv0}
+
     def close(self):
         if getattr(self, "ctx", None):
             self.stream.synchronize()

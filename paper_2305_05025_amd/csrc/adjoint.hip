@@ -1,0 +1,492 @@
+// Discrete adjoint of the coupled step (reverse mode), for gradients of a loss of the atoms'
+// final state with respect to the friction gamma, the relaxation time tau and the external
+// force-density field.
+//
+// The forward step n maps the stored post-collision buffer P^n, the atom positions X^n and
+// velocities v^n to P^{n+1}, X^{n+1}, v^{n+1} (Section 2.2, Eqs. 1-3 and the friction
+// coupling; see atoms.hip and lb_sweep.hip).  Its adjoint takes Lam^{n+1} = dL/dP^{n+1},
+// lx = dL/dX^{n+1}, lv = dL/dv^{n+1} back to step n, accumulating dL/dgamma, dL/domega and
+// dL/dF_ext on the way.  With h_i(x) = P^n_i(x - c_i) the pre-collision values at x and
+// mu(x) = Lam^{n+1}(x) the adjoint of the collision output at x:
+//   collision (BGK + Guo, u* = (j + F/2)/rho):
+//     a_i = (1 - omega) mu_i + l_rho + c_i . l_j        (l_j = l_u / rho,
+//     l_rho = omega sum_i mu_i dgeq_i/drho - u*.l_u/rho,  l_u = sum_i mu_i d(out_i)/du*)
+//     phi = dL/dF(x) = sum_i mu_i d(S_i)/dF + l_u / (2 rho)
+//     dL/domega += sum_i mu_i (-(h_i - geq_i) - s_i / 2),  S_i = (1 - omega/2) s_i
+//   atoms (F_c = gamma (U - v), U = sum_k W_k u_c(node_k), the fluid gets -W_k F_c):
+//     v'  = lv + lx                                       (X^{n+1} = X^n + v^{n+1})
+//     lF_c = v'/m - sum_k W_k phi(node_k)
+//     dL/dgamma += lF_c . (U - v);  l_U = gamma lF_c;  lv^n = v' - gamma lF_c
+//     lx^n = lx + H_ff(X^n) v'/m + sum_k grad W_k [u_c(node_k) . l_U - F_c . phi(node_k)]
+//   coupling velocity (u_c = (j + F_ext/2)/rho at nodes, from h):
+//     l_uc(x) = sum_a W(X_a, x) l_U,a;  a_i += -u_c.l_uc/rho + c_i . l_uc/rho
+//   and dL/dF_ext(x) += phi(x) + l_uc(x) / (2 rho)
+//   streaming (pull): Lam^n_i(x - c_i) = a_i(x), a push with one store per (i, x).
+// The state of each step is recomputed from checkpoints by the host (lb_backward).
+#include "atoms_common.h"
+
+namespace lbmd {
+namespace {
+
+struct AdjLatticeArgs {
+  const void* P;          // P^n (storage format)
+  const float* lam_in;    // Lam^{n+1}, FP32 [19][plane]
+  float* lam_out;         // Lam^n
+  long plane;
+  int nx, ny, nz, S;
+  float rho0, omega, pref;
+  int bf_kind;
+  const float* fext_tab;
+  const float* fext_field;
+  const uint32_t* tile_flag;
+  const float* fcoup;     // spread coupling force of step n on flagged tiles
+  float* fcoup_clear;     // the same buffer, cleared by the sweep (NULL in the tile pass)
+  int* base_count;        // cleared by the sweep on flagged tiles
+  const float* luc;       // dL/du_c on flagged tiles
+  float* phi;             // out (tile pass): dL/dF on flagged tiles
+  float* db;              // dL/dF_ext accumulated, [3][S], or NULL
+  double* dom_part;       // per workgroup: partial dL/domega
+  const int* hot_list;
+  const int* hot_count;
+};
+
+// Adjoint of the collision at one site: from mu (adjoint of the output) and the site's
+// pre-collision values g and force F, the adjoint of g (in place of mu), phi = dL/dF, and
+// this site's dL/domega term.  Also returns rho and the moments for the caller.
+__device__ __forceinline__ void collide_adjoint(float mu[19], const float g[19], float Fx, float Fy,
+                                                float Fz, float rho0, float omega, float pref,
+                                                float& phx, float& phy, float& phz, float& dom,
+                                                float& rho, float& jx, float& jy, float& jz) {
+  float drho;
+  moments(g, drho, jx, jy, jz);
+  rho = rho0 + drho;
+  const float inv = 1.0f / rho;
+  const float ux = (jx + 0.5f * Fx) * inv;
+  const float uy = (jy + 0.5f * Fy) * inv;
+  const float uz = (jz + 0.5f * Fz) * inv;
+  const float uu = ux * ux + uy * uy + uz * uz;
+  const float uF = ux * Fx + uy * Fy + uz * Fz;
+  float lrho_e = 0.f, lux = 0.f, luy = 0.f, luz = 0.f, lfx = 0.f, lfy = 0.f, lfz = 0.f;
+  dom = 0.f;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const float cu = cdot<0>(ux, uy, uz, CX[i], CY[i], CZ[i]);
+    const float cF = cdot<0>(Fx, Fy, Fz, CX[i], CY[i], CZ[i]);
+    const float A = mu[i] * WQ[i];
+    const float geq = WQ[i] * (drho + rho * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu));
+    const float si = WQ[i] * (3.0f * (cF - uF) + 9.0f * cu * cF);
+    dom += mu[i] * (-(g[i] - geq) - 0.5f * si);
+    lrho_e += A * (1.0f + 3.0f * cu + 4.5f * cu * cu - 1.5f * uu);
+    // d out_i / d u*: omega w rho (3 c + 9 cu c - 3 u) + pref w (9 cF c - 3 F)
+    const float kc = omega * rho * (3.0f + 9.0f * cu) + 9.0f * pref * cF;
+    const float ku = 3.0f * omega * rho;
+    const float kf = 3.0f * pref;
+    lux += A * (kc * (float)CX[i] - ku * ux - kf * Fx);
+    luy += A * (kc * (float)CY[i] - ku * uy - kf * Fy);
+    luz += A * (kc * (float)CZ[i] - ku * uz - kf * Fz);
+    // d S_i / d F (explicit): pref w (3 (c - u) + 9 cu c)
+    const float kfc = 3.0f + 9.0f * cu;
+    lfx += A * (kfc * (float)CX[i] - 3.0f * ux);
+    lfy += A * (kfc * (float)CY[i] - 3.0f * uy);
+    lfz += A * (kfc * (float)CZ[i] - 3.0f * uz);
+  }
+  const float ljx = lux * inv, ljy = luy * inv, ljz = luz * inv;
+  const float lrho = omega * lrho_e - (ux * lux + uy * luy + uz * luz) * inv;
+  phx = pref * lfx + 0.5f * ljx;
+  phy = pref * lfy + 0.5f * ljy;
+  phz = pref * lfz + 0.5f * ljz;
+#pragma unroll
+  for (int i = 0; i < 19; ++i)
+    mu[i] = (1.0f - omega) * mu[i] + lrho + cdot<0>(ljx, ljy, ljz, CX[i], CY[i], CZ[i]);
+}
+
+// per-site work shared by the tile pass and the sweep
+template <int ST>
+__device__ __forceinline__ void adj_site(const AdjLatticeArgs& a, int s, bool hot, bool sweep,
+                                         float& dom) {
+  using T = typename Store<ST>::T;
+  const int x = s % a.nx;
+  const int t = s / a.nx;
+  const int y = t % a.ny;
+  const int z = t / a.ny;
+  float g[19], mu[19];
+  gather<ST>(reinterpret_cast<const T*>(a.P), a.plane, x, y, z, a.nx, a.ny, a.nz, g);
+#pragma unroll
+  for (int i = 0; i < 19; ++i) mu[i] = a.lam_in[(size_t)i * a.plane + s];
+  float Ex, Ey, Ez;
+  external_force(a.bf_kind, a.fext_tab, a.fext_field, a.plane, s, y, Ex, Ey, Ez);
+  float Fx = Ex, Fy = Ey, Fz = Ez;
+  if (hot) {
+    Fx += a.fcoup[s];
+    Fy += a.fcoup[a.plane + s];
+    Fz += a.fcoup[2 * a.plane + s];
+  }
+  float phx, phy, phz, rho, jx, jy, jz;
+  collide_adjoint(mu, g, Fx, Fy, Fz, a.rho0, a.omega, a.pref, phx, phy, phz, dom, rho, jx, jy, jz);
+  if (!sweep) {
+    a.phi[s] = phx;
+    a.phi[a.plane + s] = phy;
+    a.phi[2 * a.plane + s] = phz;
+    return;
+  }
+  float dbx = phx, dby = phy, dbz = phz;
+  if (hot) {
+    // the coupling velocity u_c = (j + F_ext/2)/rho read at this node by the atoms
+    const float inv = 1.0f / rho;
+    const float lx = a.luc[s] * inv, ly = a.luc[a.plane + s] * inv, lz = a.luc[2 * a.plane + s] * inv;
+    const float ucx = (jx + 0.5f * Ex) * inv, ucy = (jy + 0.5f * Ey) * inv, ucz = (jz + 0.5f * Ez) * inv;
+    const float lr = -(ucx * lx + ucy * ly + ucz * lz);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) mu[i] += lr + cdot<0>(lx, ly, lz, CX[i], CY[i], CZ[i]);
+    dbx += 0.5f * lx;
+    dby += 0.5f * ly;
+    dbz += 0.5f * lz;
+    a.fcoup_clear[s] = 0.f;
+    a.fcoup_clear[a.plane + s] = 0.f;
+    a.fcoup_clear[2 * a.plane + s] = 0.f;
+    a.base_count[s] = 0;
+  }
+  if (a.db) {
+    a.db[s] += dbx;
+    a.db[a.S + s] += dby;
+    a.db[2 * a.S + s] += dbz;
+  }
+  // adjoint of the pull: the value read from (x - c_i) receives a_i
+  const int xm = x == 0 ? a.nx - 1 : x - 1, xp = x == a.nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? a.ny - 1 : y - 1, yp = y == a.ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? a.nz - 1 : z - 1, zp = z == a.nz - 1 ? 0 : z + 1;
+  const int nxy = a.nx * a.ny;
+  const int X3[3] = {xm, x, xp};
+  const int Y3[3] = {ym * a.nx, y * a.nx, yp * a.nx};
+  const int Z3[3] = {zm * nxy, z * nxy, zp * nxy};
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const int dst = X3[1 - CX[i]] + Y3[1 - CY[i]] + Z3[1 - CZ[i]];
+    a.lam_out[(size_t)i * a.plane + dst] = mu[i];
+  }
+}
+
+// FP64 sum of one value per thread over a 256-thread workgroup, in a fixed order
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double part[4];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double r = (part[0] + part[1]) + (part[2] + part[3]);
+  __syncthreads();
+  return r;
+}
+
+// dL/dF at every site of the flagged tiles (one wavefront per tile)
+template <int ST>
+__global__ __launch_bounds__(256) void k_adj_tiles(AdjLatticeArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6, nwave = gridDim.x * 4;
+  const int n = *a.hot_count;
+  for (int k = wave; k < n; k += nwave) {
+    const int s = (a.hot_list[k] << kTileShift) + lane;
+    float dom;
+    if (s < a.S) adj_site<ST>(a, s, true, false, dom);
+  }
+}
+
+// the adjoint sweep over all sites
+template <int ST>
+__global__ __launch_bounds__(kSweepBlock) void k_adj_sweep(AdjLatticeArgs a) {
+  const int s = blockIdx.x * kSweepBlock + threadIdx.x;
+  float dom = 0.f;
+  if (s < a.S) {
+    const bool hot = a.tile_flag != nullptr && a.tile_flag[s >> kTileShift] != 0u;
+    adj_site<ST>(a, s, hot, true, dom);
+  }
+  const double b = block_sum((double)dom);
+  if (threadIdx.x == 0) a.dom_part[blockIdx.x] = b;
+}
+
+// ---- atoms ------------------------------------------------------------------------------------
+struct AdjAtomArgs {
+  int N;
+  int n[3];
+  long plane;
+  float gamma, inv_mass;
+  const float* x0;
+  const float* d;
+  const float* v;
+  const float* fc;
+  const float* U;
+  const float* uc;
+  const float* phi;
+  const float* lx_in;
+  const float* lv_in;
+  float* lx_out;      // holds lx_in + H v'/m on entry
+  float* lv_out;
+  float* lU;
+  float4* lf;         // k_adj_dir: v'/m per atom
+  double* dg_part;    // per workgroup: partial dL/dgamma
+};
+
+__global__ __launch_bounds__(256) void k_adj_dir(AdjAtomArgs a) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.N) return;
+  a.lf[i] = make_float4((a.lv_in[3 * i] + a.lx_in[3 * i]) * a.inv_mass,
+                        (a.lv_in[3 * i + 1] + a.lx_in[3 * i + 1]) * a.inv_mass,
+                        (a.lv_in[3 * i + 2] + a.lx_in[3 * i + 2]) * a.inv_mass, 0.f);
+}
+
+__global__ __launch_bounds__(256) void k_adj_atoms(AdjAtomArgs a) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  double dg = 0.0;
+  if (i < a.N) {
+    int i0[3];
+    float fr[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) split(a.x0[3 * i + c], a.d[3 * i + c], a.n[c], i0[c], fr[c]);
+    const float fcx = a.fc[3 * i], fcy = a.fc[3 * i + 1], fcz = a.fc[3 * i + 2];
+    float wpx = 0.f, wpy = 0.f, wpz = 0.f;    // sum W phi
+    float gx = 0.f, gy = 0.f, gz = 0.f;       // -sum grad W (F_c . phi)
+    float M[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};  // sum grad W u_c^T
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int dx = k & 1, dy = (k >> 1) & 1, dz = (k >> 2) & 1;
+      const int x = dx ? (i0[0] + 1 == a.n[0] ? 0 : i0[0] + 1) : i0[0];
+      const int y = dy ? (i0[1] + 1 == a.n[1] ? 0 : i0[1] + 1) : i0[1];
+      const int z = dz ? (i0[2] + 1 == a.n[2] ? 0 : i0[2] + 1) : i0[2];
+      const int node = x + a.n[0] * (y + a.n[1] * z);
+      const float wx = dx ? fr[0] : 1.0f - fr[0];
+      const float wy = dy ? fr[1] : 1.0f - fr[1];
+      const float wz = dz ? fr[2] : 1.0f - fr[2];
+      const float w = wx * wy * wz;
+      const float gw[3] = {(dx ? 1.f : -1.f) * wy * wz, (dy ? 1.f : -1.f) * wx * wz,
+                           (dz ? 1.f : -1.f) * wx * wy};
+      const float px = a.phi[node], py = a.phi[a.plane + node], pz = a.phi[2 * a.plane + node];
+      const float ux = a.uc[node], uy = a.uc[a.plane + node], uz = a.uc[2 * a.plane + node];
+      wpx += w * px;
+      wpy += w * py;
+      wpz += w * pz;
+      const float fp = fcx * px + fcy * py + fcz * pz;
+      gx -= gw[0] * fp;
+      gy -= gw[1] * fp;
+      gz -= gw[2] * fp;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        M[r][0] += gw[r] * ux;
+        M[r][1] += gw[r] * uy;
+        M[r][2] += gw[r] * uz;
+      }
+    }
+    float vp[3], lfc[3], lu[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) vp[c] = a.lv_in[3 * i + c] + a.lx_in[3 * i + c];
+    lfc[0] = vp[0] * a.inv_mass - wpx;
+    lfc[1] = vp[1] * a.inv_mass - wpy;
+    lfc[2] = vp[2] * a.inv_mass - wpz;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      dg += (double)lfc[c] * (double)(a.U[3 * i + c] - a.v[3 * i + c]);
+      lu[c] = a.gamma * lfc[c];
+      a.lU[3 * i + c] = lu[c];
+      a.lv_out[3 * i + c] = vp[c] - lu[c];
+    }
+    a.lx_out[3 * i] += gx + M[0][0] * lu[0] + M[0][1] * lu[1] + M[0][2] * lu[2];
+    a.lx_out[3 * i + 1] += gy + M[1][0] * lu[0] + M[1][1] * lu[1] + M[1][2] * lu[2];
+    a.lx_out[3 * i + 2] += gz + M[2][0] * lu[0] + M[2][1] * lu[1] + M[2][2] * lu[2];
+  }
+  const double b = block_sum(dg);
+  if (threadIdx.x == 0) a.dg_part[blockIdx.x] = b;
+}
+
+// dL/du_c at every site of the flagged tiles: the transpose of the interpolation applied to
+// l_U, gathered over the base-node lists like the forward spread.  The entries of each list
+// are taken in atom-index order, so the FP32 sum does not depend on binning order.
+struct AdjSpreadArgs {
+  int S;
+  int n[3];
+  long plane;
+  const int* occ_tiles;
+  const int* occ_count;
+  const int* base_count;
+  const int* base_list;
+  const float4* atom_frac;
+  const float* lU;
+  float* luc;
+};
+
+__global__ __launch_bounds__(256) void k_adj_spread(AdjSpreadArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
+  const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6, nwave = gridDim.x * 4;
+  const int ntile = *a.occ_count;
+  for (int kt = wave; kt < ntile; kt += nwave) {
+    const int s = (a.occ_tiles[kt] << kTileShift) + lane;
+    if (s >= a.S) continue;
+    const int x = s % nx;
+    const int t = s / nx;
+    const int y = t % ny;
+    const int z = t / ny;
+    float sx = 0.f, sy = 0.f, sz = 0.f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int dx = k & 1, dy = (k >> 1) & 1, dz = (k >> 2) & 1;
+      const int bx = dx ? (x == 0 ? nx - 1 : x - 1) : x;
+      const int by = dy ? (y == 0 ? ny - 1 : y - 1) : y;
+      const int bz = dz ? (z == 0 ? nz - 1 : z - 1) : z;
+      const int base = bx + nx * (by + ny * bz);
+      int n = a.base_count[base];
+      n = n > kBaseCap ? kBaseCap : n;
+      int ids[kBaseCap];
+      for (int q = 0; q < n; ++q) {
+        // insertion into the sorted prefix
+        int v = a.base_list[(size_t)base * kBaseCap + q], r = q;
+        while (r > 0 && ids[r - 1] > v) {
+          ids[r] = ids[r - 1];
+          --r;
+        }
+        ids[r] = v;
+      }
+      for (int q = 0; q < n; ++q) {
+        const int at = ids[q];
+        const float4 fr = a.atom_frac[at];
+        const float w = (dx ? fr.x : 1.0f - fr.x) * (dy ? fr.y : 1.0f - fr.y) * (dz ? fr.z : 1.0f - fr.z);
+        sx += w * a.lU[3 * at];
+        sy += w * a.lU[3 * at + 1];
+        sz += w * a.lU[3 * at + 2];
+      }
+    }
+    a.luc[s] = sx;
+    a.luc[a.plane + s] = sy;
+    a.luc[2 * a.plane + s] = sz;
+  }
+}
+
+// acc[0] += sum of n0 partials, acc[1] += sum of n1 partials (fixed order, one workgroup)
+__global__ __launch_bounds__(256) void k_adj_reduce(const double* p0, int n0, const double* p1, int n1,
+                                                    double* acc) {
+  double s0 = 0.0, s1 = 0.0;
+  for (int k = threadIdx.x; k < n0; k += 256) s0 += p0[k];
+  for (int k = threadIdx.x; k < n1; k += 256) s1 += p1[k];
+  s0 = block_sum(s0);
+  s1 = block_sum(s1);
+  if (threadIdx.x == 0) {
+    acc[0] += s0;
+    acc[1] += s1;
+  }
+}
+
+}  // namespace
+
+// ---- launchers -------------------------------------------------------------------------------
+
+static AdjLatticeArgs lattice_args(lb_ctx* c, const AdjointBuffers& b) {
+  const Geometry& g = c->geo;
+  const int par = (int)(c->step & 1);
+  AdjLatticeArgs a;
+  a.P = c->popbuf[c->cur];
+  a.lam_in = b.lam_in;
+  a.lam_out = b.lam_out;
+  a.plane = g.plane;
+  a.nx = g.nx;
+  a.ny = g.ny;
+  a.nz = g.nz;
+  a.S = (int)g.S;
+  a.rho0 = c->p.rho0;
+  a.omega = c->omega;
+  a.pref = 1.0f - 0.5f * c->omega;
+  a.bf_kind = c->p.bf_kind;
+  a.fext_tab = (const float*)(c->ws + c->lay.fext_tab);
+  a.fext_field = (const float*)(c->ws + c->lay.fext_field);
+  a.tile_flag = (const uint32_t*)(c->ws + c->lay.tile_flag[par]);
+  a.fcoup = (const float*)(c->ws + c->lay.fcoup[par]);
+  a.fcoup_clear = (float*)(c->ws + c->lay.fcoup[par]);
+  a.base_count = (int*)(c->ws + c->lay.base_count[par]);
+  a.luc = b.luc;
+  a.phi = b.phi;
+  a.db = b.db;
+  a.dom_part = b.dom_part;
+  a.hot_list = (const int*)(c->ws + c->lay.occ_tiles[par]);
+  a.hot_count = (const int*)(c->ws + c->lay.occ_count[par]) + 1;
+  return a;
+}
+
+static AdjAtomArgs atom_args(lb_ctx* c, const AdjointBuffers& b) {
+  AdjAtomArgs a;
+  a.N = c->p.n_atoms;
+  a.n[0] = c->geo.nx;
+  a.n[1] = c->geo.ny;
+  a.n[2] = c->geo.nz;
+  a.plane = c->geo.plane;
+  a.gamma = c->p.gamma;
+  a.inv_mass = 1.0f / c->p.mass;
+  a.x0 = (const float*)(c->ws + c->lay.x0);
+  a.d = (const float*)(c->ws + c->lay.disp[c->dcur]);
+  a.v = (const float*)(c->ws + c->lay.vel);
+  a.fc = (const float*)(c->ws + c->lay.fc);
+  a.U = b.U;
+  a.uc = (const float*)(c->ws + c->lay.uc);
+  a.phi = b.phi;
+  a.lx_in = b.lx_in;
+  a.lv_in = b.lv_in;
+  a.lx_out = b.lx_out;
+  a.lv_out = b.lv_out;
+  a.lU = b.lU;
+  a.lf = b.lf;
+  a.dg_part = b.dg_part;
+  return a;
+}
+
+unsigned adjoint_atom_blocks(const lb_ctx* c) { return blocks(c->p.n_atoms, 256); }
+
+hipError_t launch_adjoint_step(lb_ctx* c, const AdjointBuffers& b) {
+  const Geometry& g = c->geo;
+  const hipStream_t st = c->stream;
+  const AdjAtomArgs aa = atom_args(c, b);
+  const unsigned nab = adjoint_atom_blocks(c);
+  // 1. direction v'/m and the force-field Hessian-vector product: lx_out = lx_in + H v'/m
+  hipLaunchKernelGGL(k_adj_dir, dim3(nab), dim3(256), 0, st, aa);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = launch_force_hvp(c, b.lf, b.lx_in, b.lx_out)) != hipSuccess) return e;
+  // 2. dL/dF on the flagged tiles
+  const AdjLatticeArgs la = lattice_args(c, b);
+  const dim3 tgrid(persistent_grid(g.ntiles)), blk(256);
+  switch (c->p.storage) {
+    case LB_STORE_F32: hipLaunchKernelGGL(k_adj_tiles<LB_STORE_F32>, tgrid, blk, 0, st, la); break;
+    case LB_STORE_F16: hipLaunchKernelGGL(k_adj_tiles<LB_STORE_F16>, tgrid, blk, 0, st, la); break;
+    default: hipLaunchKernelGGL(k_adj_tiles<LB_STORE_BF16>, tgrid, blk, 0, st, la); break;
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // 3. atoms
+  hipLaunchKernelGGL(k_adj_atoms, dim3(nab), dim3(256), 0, st, aa);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // 4. dL/du_c on the flagged tiles
+  AdjSpreadArgs sa;
+  const int par = (int)(c->step & 1);
+  sa.S = (int)g.S;
+  sa.n[0] = g.nx;
+  sa.n[1] = g.ny;
+  sa.n[2] = g.nz;
+  sa.plane = g.plane;
+  sa.occ_tiles = (const int*)(c->ws + c->lay.occ_tiles[par]);
+  sa.occ_count = (const int*)(c->ws + c->lay.occ_count[par]) + 1;
+  sa.base_count = (const int*)(c->ws + c->lay.base_count[par]);
+  sa.base_list = (const int*)(c->ws + c->lay.base_list[par]);
+  sa.atom_frac = (const float4*)(c->ws + c->lay.atom_frac);
+  sa.lU = b.lU;
+  sa.luc = b.luc;
+  hipLaunchKernelGGL(k_adj_spread, tgrid, blk, 0, st, sa);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // 5. the adjoint sweep
+  const dim3 sgrid(g.nblocks), sblk(kSweepBlock);
+  switch (c->p.storage) {
+    case LB_STORE_F32: hipLaunchKernelGGL(k_adj_sweep<LB_STORE_F32>, sgrid, sblk, 0, st, la); break;
+    case LB_STORE_F16: hipLaunchKernelGGL(k_adj_sweep<LB_STORE_F16>, sgrid, sblk, 0, st, la); break;
+    default: hipLaunchKernelGGL(k_adj_sweep<LB_STORE_BF16>, sgrid, sblk, 0, st, la); break;
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // 6. FP64 accumulators
+  hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(256), 0, st, (const double*)b.dg_part, (int)nab,
+                     (const double*)b.dom_part, g.nblocks, b.acc);
+  return hipGetLastError();
+}
+
+}  // namespace lbmd

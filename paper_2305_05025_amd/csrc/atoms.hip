@@ -7,11 +7,12 @@
 // eight trilinear weights.  The fluid velocity at a node is u_c = (j + F_ext/2)/rho of the
 // pre-collision state (Eqs. 2-3); the atoms' own force is not included.
 //
-// Per step, in stream order:
+// Per step:
 //   k_prep      clear the neighbour-list counts and the force-tile flags
 //   k_bin_mark  one thread per atom: flag its 8 stencil nodes (plain byte stores) and their
 //               64-site tiles, append the atom to the list of its stencil base node (lower
 //               corner), and append a record of it to its neighbour-list cell
+//   k_compact   lists of the occupied cells and of the flagged tiles
 //   k_node_u    u_c at every flagged node, pulled once per node (19 loads) rather than once
 //               per atom corner
 //   k_couple    eight lanes per atom: weighted u_c of its node, xor-shuffle sum -> U,
@@ -20,74 +21,18 @@
 //               whose stencil covers it, summed in 2^-40 fixed point (order-independent) and
 //               stored as a float; no atomics on the force
 //   (lattice sweep: adds the spread force on flagged tiles and clears the per-step buffers)
-//   k_forces_integrate  eight lanes per atom, the 27 neighbour cells split among them:
-//               tethers, bonds, Lennard-Jones summed in 2^-32 fixed point (order-independent,
-//               so the result does not depend on the order atoms landed in a cell), then the
-//               symplectic Euler update.
+//   k_cell_sort each occupied cell's records in atom-index order
+//   k_forces_cells  tethers, bonds and Lennard-Jones at X^n, one wavefront per occupied
+//               cell with the 27 neighbour cells staged in LDS, FP32 sums in a fixed order
+//   k_integrate symplectic Euler update
 //
 // Positions are kept as the caller's unwrapped anchors x0 plus a displacement d.  Stencil
 // fractions and pair vectors are formed from small numbers only (fractions in [0, 1) and
 // small integer offsets), so they keep full FP32 precision at any box size.
-#include "lattice_common.h"
+#include "atoms_common.h"
 
 namespace lbmd {
 namespace {
-
-__device__ __forceinline__ int wrapi(int a, int n) {
-  int r = a % n;
-  return r < 0 ? r + n : r;
-}
-
-// Integer node and fraction of (x0 + d) along one axis, the node wrapped into [0, n).
-// The clamp keeps a diverging displacement (reported by the velocity check) from
-// producing out-of-range integer conversions.
-__device__ __forceinline__ void split(float x0, float d, int n, int& i0, float& frac) {
-  const float ia = floorf(x0);
-  const float t = fminf(fmaxf((x0 - ia) + d, -1.0e6f), 1.0e6f);
-  const float fl = floorf(t);
-  frac = t - fl;
-  i0 = wrapi((int)ia + (int)fl, n);
-}
-
-// Neighbour-list cell of a wrapped position, and the integer origin of that cell.
-__device__ __forceinline__ int cell_of(int i0, float frac, float inv_cw, int nc) {
-  const int q = (int)(((float)i0 + frac) * inv_cw);
-  return q >= nc ? nc - 1 : q;
-}
-__device__ __forceinline__ int cell_origin(int q, int n, int nc) { return (q * n) / nc; }
-
-// Position of an atom inside its neighbour-list cell in 8.24 fixed point: (node offset from
-// the cell's integer origin, biased by 1) + fraction.  Differences of these integers are
-// exact, and one conversion turns a pair difference into a float.
-constexpr float kCellFix = 16777216.0f;      // 2^24
-constexpr float kCellFixInv = 1.0f / 16777216.0f;
-__device__ __forceinline__ int cell_fixed(int node_offset, float frac) {
-  return ((node_offset + 1) << 24) + (int)rintf(frac * kCellFix);
-}
-
-// value * scale rounded to an integer, clamped so a diverging state (which the velocity
-// check reports) cannot overflow the conversion
-__device__ __forceinline__ long long to_fixed(float v, float scale) {
-  float q = rintf(v * scale);
-  q = fminf(fmaxf(q, -4.0e18f), 4.0e18f);
-  return (long long)q;
-}
-
-// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.  Kernels whose
-// neighbouring work items share data (atoms of one globule, nodes of one region) renumber
-// their workgroups so that each XCD gets one contiguous eighth of the grid.  The grid must be
-// a multiple of 8 workgroups.
-__device__ __forceinline__ int xcd_block() {
-  const int per = (int)(gridDim.x >> 3);
-  return (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
-}
-
-
-struct AtomGeo {
-  int n[3];          // lattice extents
-  int nc[3];         // neighbour-list cells per axis (nc[0] == 0: no Lennard-Jones)
-  float inv_cw[3];
-};
 
 // ------------------------------------------------------------------------------------------
 struct PrepArgs {
@@ -284,6 +229,7 @@ struct CoupleArgs {
   const float* v;
   const float* uc;
   float* fc;              // out: friction force on each atom
+  float* U;               // out, optional: interpolated fluid velocity at each atom
 };
 
 __global__ __launch_bounds__(256) void k_couple(CoupleArgs a) {
@@ -314,6 +260,11 @@ __global__ __launch_bounds__(256) void k_couple(CoupleArgs a) {
     Uz += __shfl_xor(Uz, o, 64);
   }
   if (!valid || k != 0) return;
+  if (a.U) {
+    a.U[3 * atom] = Ux;
+    a.U[3 * atom + 1] = Uy;
+    a.U[3 * atom + 2] = Uz;
+  }
   a.fc[3 * atom] = a.gamma * (Ux - a.v[3 * atom]);
   a.fc[3 * atom + 1] = a.gamma * (Uy - a.v[3 * atom + 1]);
   a.fc[3 * atom + 2] = a.gamma * (Uz - a.v[3 * atom + 2]);
@@ -395,38 +346,33 @@ struct ForceArgs {
   const int* occ_cells;
   const int* occ_count;   // [1]: number of occupied cells
   uint32_t* err;
+  // Hessian-vector product (adjoint) only: direction per atom, and lx_out = lx_in + H lf
+  const float4* lf;
+  const float* lx_in;
+  float* lx_out;
 };
 
-__device__ __forceinline__ float min_image(float r, float L, float invL) {
-  return r - L * rintf(r * invL);
-}
-
-// per-axis neighbour-cell index after periodic wrap, and the integer shift (own cell origin
-// minus neighbour cell origin, across the periodic seam if it wrapped) that expresses the
-// neighbour's cell-relative positions in the own cell's frame
-__device__ __forceinline__ void nbr_cell(int q, int o, int n, int nc, int& cq, int& shift) {
-  int c = q + o, s = 0;
-  if (c < 0) {
-    c += nc;
-    s = n;
-  }
-  if (c >= nc) {
-    c -= nc;
-    s = -n;
-  }
-  cq = c;
-  shift = cell_origin(q, n, nc) - cell_origin(c, n, nc) + s;
-}
-
-// Tethers and bonds of atom i added to its Lennard-Jones force; the total stand-in force
-// field at X^n is stored for the integration.
+// Tethers and bonds of atom i added to its Lennard-Jones part.  Forward: the total stand-in
+// force field at X^n is stored for the integration.  Adjoint (kAdj): the same terms of the
+// force Jacobian applied to the direction lf (the Jacobian is symmetric), added to lx_in.
+// For a pair term f(r) = g(|r|^2) r with r = X_i - X_j, the Jacobian block is
+// J = g I + 2 g' r r^T, and atom i receives J (lf_i - lf_j).
+template <bool kAdj>
 __device__ __forceinline__ void bonded_and_store(const ForceArgs& a, int i, float Fx, float Fy,
                                                  float Fz) {
   const float xi = a.x0[3 * i], yi = a.x0[3 * i + 1], zi = a.x0[3 * i + 2];
   const float dxi = a.d[3 * i], dyi = a.d[3 * i + 1], dzi = a.d[3 * i + 2];
-  Fx -= a.k_tether * dxi;
-  Fy -= a.k_tether * dyi;
-  Fz -= a.k_tether * dzi;
+  float4 li = make_float4(0.f, 0.f, 0.f, 0.f);
+  if constexpr (kAdj) {
+    li = a.lf[i];
+    Fx -= a.k_tether * li.x;
+    Fy -= a.k_tether * li.y;
+    Fz -= a.k_tether * li.z;
+  } else {
+    Fx -= a.k_tether * dxi;
+    Fy -= a.k_tether * dyi;
+    Fz -= a.k_tether * dzi;
+  }
   const int b0 = a.bond_off[i], b1 = a.bond_off[i + 1];
   for (int b = b0; b < b1; ++b) {
     const int j = a.bond_nbr[b];
@@ -435,13 +381,29 @@ __device__ __forceinline__ void bonded_and_store(const ForceArgs& a, int i, floa
     const float rz = min_image((zi - a.x0[3 * j + 2]) + (dzi - a.d[3 * j + 2]), a.L[2], a.invL[2]);
     const float rl = sqrtf(rx * rx + ry * ry + rz * rz);
     const float f = -a.k_bond * (rl - a.r0_bond) / rl;
-    Fx += f * rx;
-    Fy += f * ry;
-    Fz += f * rz;
+    if constexpr (kAdj) {
+      // g = -k (1 - r0/|r|), 2 g' = -k r0 / |r|^3
+      const float4 lj = a.lf[j];
+      const float ex = li.x - lj.x, ey = li.y - lj.y, ez = li.z - lj.z;
+      const float t = -a.k_bond * a.r0_bond / (rl * rl * rl) * (rx * ex + ry * ey + rz * ez);
+      Fx += f * ex + t * rx;
+      Fy += f * ey + t * ry;
+      Fz += f * ez + t * rz;
+    } else {
+      Fx += f * rx;
+      Fy += f * ry;
+      Fz += f * rz;
+    }
   }
-  a.ff[3 * i] = Fx;
-  a.ff[3 * i + 1] = Fy;
-  a.ff[3 * i + 2] = Fz;
+  if constexpr (kAdj) {
+    a.lx_out[3 * i] = a.lx_in[3 * i] + Fx;
+    a.lx_out[3 * i + 1] = a.lx_in[3 * i + 1] + Fy;
+    a.lx_out[3 * i + 2] = a.lx_in[3 * i + 2] + Fz;
+  } else {
+    a.ff[3 * i] = Fx;
+    a.ff[3 * i + 1] = Fy;
+    a.ff[3 * i + 2] = Fz;
+  }
 }
 
 // Lennard-Jones, cell-centric, staged in LDS.  A wavefront takes one occupied cell at a time
@@ -461,12 +423,7 @@ __device__ __forceinline__ void bonded_and_store(const ForceArgs& a, int i, floa
 constexpr int kStage = 640;   // staged records per wavefront (27 cells of ~9.5 atoms need ~260)
 constexpr int kPasses = kCellCap / 16;
 
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
+template <bool kAdj>
 __global__ __launch_bounds__(256) void k_forces_cells(ForceArgs a) {
   __shared__ int4 stage_all[4][kStage];
   const int lane = threadIdx.x & 63;
@@ -485,12 +442,14 @@ __global__ __launch_bounds__(256) void k_forces_cells(ForceArgs a) {
     int pb[kPasses][4], b0s[kPasses], b1s[kPasses];
     bool hv[kPasses];
     float Fx[kPasses], Fy[kPasses], Fz[kPasses];
+    float4 lfi[kPasses];
 #pragma unroll
     for (int p = 0; p < kPasses; ++p) {
       const int h = 16 * p + hl;
       hv[p] = h < nh;
       me[p] = a.cell_rec[cell * kCellCap + (hv[p] ? h : 0)];
       const int i = me[p].w;
+      if constexpr (kAdj) lfi[p] = a.lf[i];
       b0s[p] = a.bond_off[i];
       b1s[p] = a.bond_off[i + 1];
       pb[p][0] = pb[p][1] = pb[p][2] = pb[p][3] = -1;
@@ -566,9 +525,20 @@ __global__ __launch_bounds__(256) void k_forces_cells(ForceArgs a) {
           const float sr2 = a.lj_sigma2 * inv2;
           const float sr6 = sr2 * sr2 * sr2;
           const float f = a.lj_eps24 * (2.0f * sr6 * sr6 - sr6) * inv2;
-          Fx[p] += f * rx;
-          Fy[p] += f * ry;
-          Fz[p] += f * rz;
+          if constexpr (kAdj) {
+            // g(s) = 24 eps (2 sigma^12 s^-7 - sigma^6 s^-4), s = r^2
+            const float gp2 = 2.0f * a.lj_eps24 * (4.0f * sr6 - 14.0f * sr6 * sr6) * inv2 * inv2;
+            const float4 lj = a.lf[j];
+            const float ex = lfi[p].x - lj.x, ey = lfi[p].y - lj.y, ez = lfi[p].z - lj.z;
+            const float t = gp2 * (rx * ex + ry * ey + rz * ez);
+            Fx[p] += f * ex + t * rx;
+            Fy[p] += f * ey + t * ry;
+            Fz[p] += f * ez + t * rz;
+          } else {
+            Fx[p] += f * rx;
+            Fy[p] += f * ry;
+            Fz[p] += f * rz;
+          }
         }
       }
       wave_lds_sync();
@@ -585,16 +555,17 @@ __global__ __launch_bounds__(256) void k_forces_cells(ForceArgs a) {
       fx += __shfl_xor(fx, 32, 64);
       fy += __shfl_xor(fy, 32, 64);
       fz += __shfl_xor(fz, 32, 64);
-      if (hv[p] && grp == 0) bonded_and_store(a, me[p].w, fx, fy, fz);
+      if (hv[p] && grp == 0) bonded_and_store<kAdj>(a, me[p].w, fx, fy, fz);
     }
   }
 }
 
 // Without Lennard-Jones: one thread per atom, tethers + bonds.
+template <bool kAdj>
 __global__ __launch_bounds__(256) void k_bonded_forces(ForceArgs a) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= a.N) return;
-  bonded_and_store(a, i, 0.f, 0.f, 0.f);
+  bonded_and_store<kAdj>(a, i, 0.f, 0.f, 0.f);
 }
 
 // Symplectic Euler with the force field at X^n and the friction of this step:
@@ -631,31 +602,6 @@ __global__ __launch_bounds__(256) void k_read_atoms(int N, const float* x0, cons
   if (t >= 3 * N) return;
   if (xo) xo[t] = x0[t] + d[t];
   if (vo) vo[t] = v[t];
-}
-
-AtomGeo atom_geo(const lb_ctx* c) {
-  AtomGeo g;
-  const int n3[3] = {c->geo.nx, c->geo.ny, c->geo.nz};
-  for (int k = 0; k < 3; ++k) {
-    g.n[k] = n3[k];
-    g.nc[k] = c->geo.nc[k];
-    g.inv_cw[k] = c->geo.inv_cw[k];
-  }
-  return g;
-}
-
-unsigned blocks(long n, int per) { return (unsigned)((n + per - 1) / per); }
-
-// grids of the XCD-mapped kernels are a multiple of 8 workgroups
-unsigned blocks8(long n, int per) { return (blocks(n, per) + 7u) & ~7u; }
-
-// persistent kernels: enough 4-wavefront workgroups for the items (one per wavefront), at
-// most 8 per CU
-unsigned persistent_grid(long nitems) {
-  long b = (nitems + 3) / 4;
-  if (b > 2048) b = 2048;
-  if (b < 8) b = 8;
-  return (unsigned)((b + 7) & ~7L);
 }
 
 }  // namespace
@@ -719,7 +665,7 @@ hipError_t launch_bin_mark(lb_ctx* c) {
 hipError_t launch_node_u(lb_ctx* c) {
   const Geometry& g = c->geo;
   NodeArgs a;
-  a.f = c->ws + c->lay.pop[c->cur];
+  a.f = c->popbuf[c->cur];
   a.plane = g.plane;
   a.nx = g.nx;
   a.ny = g.ny;
@@ -755,6 +701,7 @@ hipError_t launch_couple(lb_ctx* c) {
   a.v = (const float*)(c->ws + c->lay.vel);
   a.uc = (const float*)(c->ws + c->lay.uc);
   a.fc = (float*)(c->ws + c->lay.fc);
+  a.U = c->couple_u;
   hipLaunchKernelGGL(k_couple, dim3(blocks8(8L * a.N, 256)), dim3(256), 0, c->stream, a);
   return hipGetLastError();
 }
@@ -779,7 +726,7 @@ hipError_t launch_spread(lb_ctx* c) {
   return hipGetLastError();
 }
 
-hipError_t launch_forces(lb_ctx* c) {
+static ForceArgs force_args(lb_ctx* c) {
   ForceArgs a;
   a.N = c->p.n_atoms;
   a.g = atom_geo(c);
@@ -805,10 +752,32 @@ hipError_t launch_forces(lb_ctx* c) {
   a.occ_cells = (const int*)(c->ws + c->lay.occ_cells);
   a.occ_count = (const int*)(c->ws + c->lay.occ_count[c->step & 1]);
   a.err = (uint32_t*)(c->ws + c->lay.err);
+  a.lf = nullptr;
+  a.lx_in = nullptr;
+  a.lx_out = nullptr;
+  return a;
+}
+
+hipError_t launch_forces(lb_ctx* c) {
+  const ForceArgs a = force_args(c);
   if (a.ncell > 0)
-    hipLaunchKernelGGL(k_forces_cells, dim3(persistent_grid(std::min(a.ncell, (long)a.N))), dim3(256), 0, c->fstream, a);
+    hipLaunchKernelGGL(k_forces_cells<false>, dim3(persistent_grid(std::min(a.ncell, (long)a.N))), dim3(256), 0,
+                       c->fstream, a);
   else
-    hipLaunchKernelGGL(k_bonded_forces, dim3(blocks(a.N, 256)), dim3(256), 0, c->fstream, a);
+    hipLaunchKernelGGL(k_bonded_forces<false>, dim3(blocks(a.N, 256)), dim3(256), 0, c->fstream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_force_hvp(lb_ctx* c, const float4* lf, const float* lx_in, float* lx_out) {
+  ForceArgs a = force_args(c);
+  a.lf = lf;
+  a.lx_in = lx_in;
+  a.lx_out = lx_out;
+  if (a.ncell > 0)
+    hipLaunchKernelGGL(k_forces_cells<true>, dim3(persistent_grid(std::min(a.ncell, (long)a.N))), dim3(256), 0,
+                       c->stream, a);
+  else
+    hipLaunchKernelGGL(k_bonded_forces<true>, dim3(blocks(a.N, 256)), dim3(256), 0, c->stream, a);
   return hipGetLastError();
 }
 

@@ -1,0 +1,118 @@
+// Device and launch helpers shared by the atom-side kernels of the forward step and of its
+// adjoint: positions as anchor + displacement, stencil and neighbour-list cell geometry,
+// fixed-point conversions, XCD-aware workgroup numbering and grid sizes.
+#pragma once
+
+#include "lattice_common.h"
+
+namespace lbmd {
+
+__device__ __forceinline__ int wrapi(int a, int n) {
+  int r = a % n;
+  return r < 0 ? r + n : r;
+}
+
+// Integer node and fraction of (x0 + d) along one axis, the node wrapped into [0, n).
+// The clamp keeps a diverging displacement (reported by the velocity check) from
+// producing out-of-range integer conversions.
+__device__ __forceinline__ void split(float x0, float d, int n, int& i0, float& frac) {
+  const float ia = floorf(x0);
+  const float t = fminf(fmaxf((x0 - ia) + d, -1.0e6f), 1.0e6f);
+  const float fl = floorf(t);
+  frac = t - fl;
+  i0 = wrapi((int)ia + (int)fl, n);
+}
+
+// Neighbour-list cell of a wrapped position, and the integer origin of that cell.
+__device__ __forceinline__ int cell_of(int i0, float frac, float inv_cw, int nc) {
+  const int q = (int)(((float)i0 + frac) * inv_cw);
+  return q >= nc ? nc - 1 : q;
+}
+__device__ __forceinline__ int cell_origin(int q, int n, int nc) { return (q * n) / nc; }
+
+// Position of an atom inside its neighbour-list cell in 8.24 fixed point: (node offset from
+// the cell's integer origin, biased by 1) + fraction.  Differences of these integers are
+// exact, and one conversion turns a pair difference into a float.
+constexpr float kCellFix = 16777216.0f;      // 2^24
+constexpr float kCellFixInv = 1.0f / 16777216.0f;
+__device__ __forceinline__ int cell_fixed(int node_offset, float frac) {
+  return ((node_offset + 1) << 24) + (int)rintf(frac * kCellFix);
+}
+
+// value * scale rounded to an integer, clamped so a diverging state (which the velocity
+// check reports) cannot overflow the conversion
+__device__ __forceinline__ long long to_fixed(float v, float scale) {
+  float q = rintf(v * scale);
+  q = fminf(fmaxf(q, -4.0e18f), 4.0e18f);
+  return (long long)q;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.  Kernels whose
+// neighbouring work items share data (atoms of one globule, nodes of one region) renumber
+// their workgroups so that each XCD gets one contiguous eighth of the grid.  The grid must be
+// a multiple of 8 workgroups.
+__device__ __forceinline__ int xcd_block() {
+  const int per = (int)(gridDim.x >> 3);
+  return (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
+}
+
+
+struct AtomGeo {
+  int n[3];          // lattice extents
+  int nc[3];         // neighbour-list cells per axis (nc[0] == 0: no Lennard-Jones)
+  float inv_cw[3];
+};
+
+__device__ __forceinline__ float min_image(float r, float L, float invL) {
+  return r - L * rintf(r * invL);
+}
+
+// per-axis neighbour-cell index after periodic wrap, and the integer shift (own cell origin
+// minus neighbour cell origin, across the periodic seam if it wrapped) that expresses the
+// neighbour's cell-relative positions in the own cell's frame
+__device__ __forceinline__ void nbr_cell(int q, int o, int n, int nc, int& cq, int& shift) {
+  int c = q + o, s = 0;
+  if (c < 0) {
+    c += nc;
+    s = n;
+  }
+  if (c >= nc) {
+    c -= nc;
+    s = -n;
+  }
+  cq = c;
+  shift = cell_origin(q, n, nc) - cell_origin(c, n, nc) + s;
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+inline AtomGeo atom_geo(const lb_ctx* c) {
+  AtomGeo g;
+  const int n3[3] = {c->geo.nx, c->geo.ny, c->geo.nz};
+  for (int k = 0; k < 3; ++k) {
+    g.n[k] = n3[k];
+    g.nc[k] = c->geo.nc[k];
+    g.inv_cw[k] = c->geo.inv_cw[k];
+  }
+  return g;
+}
+
+inline unsigned blocks(long n, int per) { return (unsigned)((n + per - 1) / per); }
+
+// grids of the XCD-mapped kernels are a multiple of 8 workgroups
+inline unsigned blocks8(long n, int per) { return (blocks(n, per) + 7u) & ~7u; }
+
+// persistent kernels: enough 4-wavefront workgroups for the items (one per wavefront), at
+// most 8 per CU
+inline unsigned persistent_grid(long nitems) {
+  long b = (nitems + 3) / 4;
+  if (b > 2048) b = 2048;
+  if (b < 8) b = 8;
+  return (unsigned)((b + 7) & ~7L);
+}
+
+}  // namespace lbmd

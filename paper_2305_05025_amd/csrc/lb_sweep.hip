@@ -317,7 +317,7 @@ hipError_t launch_sweep(lb_ctx* c, const void* fin, void* fout, hipStream_t st) 
 static hipError_t launch_read(lb_ctx* c, float* rho, float* u, float* pops) {
   const Geometry& g = c->geo;
   ReadArgs a;
-  a.f = c->ws + c->lay.pop[c->cur];
+  a.f = c->popbuf[c->cur];
   a.plane = g.plane;
   a.nx = g.nx;
   a.ny = g.ny;
@@ -346,7 +346,7 @@ hipError_t launch_read_populations(lb_ctx* c, float* g) { return launch_read(c, 
 hipError_t launch_write_populations(lb_ctx* c, const float* g) {
   const Geometry& geo = c->geo;
   WriteArgs a;
-  a.f = c->ws + c->lay.pop[c->cur];
+  a.f = c->popbuf[c->cur];
   a.plane = geo.plane;
   a.nx = geo.nx;
   a.ny = geo.ny;
@@ -365,7 +365,7 @@ hipError_t launch_write_populations(lb_ctx* c, const float* g) {
 hipError_t launch_invariants(lb_ctx* c) {
   const Geometry& g = c->geo;
   RedArgs a;
-  a.f = c->ws + c->lay.pop[c->cur];
+  a.f = c->popbuf[c->cur];
   a.plane = g.plane;
   a.S = (int)g.S;
   a.partial = (double*)(c->ws + c->lay.red_partial);

@@ -254,6 +254,8 @@ lb_status lb_init(const lb_params* p, void* workspace, size_t workspace_bytes, c
   c->lay = lay;
   c->stream = st;
   c->ws = (char*)workspace;
+  c->popbuf[0] = c->ws + lay.pop[0];
+  c->popbuf[1] = c->ws + lay.pop[1];
   c->cur = 0;
   c->dcur = 0;
   c->step = 0;
@@ -364,8 +366,8 @@ lb_status lb_couple_step(lb_ctx* c, int32_t n_steps) {
   for (int n = 0; n < n_steps; ++n) {
     hipEvent_t* ev = slot();
     if (ev) c->timed++;
-    void* fin = c->ws + c->lay.pop[c->cur];
-    void* fout = c->ws + c->lay.pop[c->cur ^ 1];
+    void* fin = c->popbuf[c->cur];
+    void* fout = c->popbuf[c->cur ^ 1];
     if (atoms) {
       if ((n == 0 || !multi) && (st = binning(ev)) != LB_OK) return st;
       if (multi && ((e = hipStreamWaitEvent(c->stream, c->ev_bin, 0)) != hipSuccess ||
@@ -491,7 +493,7 @@ lb_status lb_state_save(lb_ctx* c, void* dst) {
   const size_t pb = round_up(state_pop_bytes(c), 256), ab = round_up(12 * (size_t)c->p.n_atoms, 256);
   hipError_t e = launch_store_i64(d, c->step, c->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(d + 256, c->ws + c->lay.pop[c->cur], state_pop_bytes(c), hipMemcpyDeviceToDevice, c->stream);
+    e = hipMemcpyAsync(d + 256, c->popbuf[c->cur], state_pop_bytes(c), hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess && c->p.n_atoms > 0) {
     e = hipMemcpyAsync(d + 256 + pb, c->ws + c->lay.disp[c->dcur], 12 * (size_t)c->p.n_atoms,
                        hipMemcpyDeviceToDevice, c->stream);
@@ -511,7 +513,7 @@ lb_status lb_state_load(lb_ctx* c, const void* src) {
   hipError_t e = hipMemcpyAsync(&step, s, 8, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(c->ws + c->lay.pop[c->cur], s + 256, state_pop_bytes(c), hipMemcpyDeviceToDevice, c->stream);
+    e = hipMemcpyAsync(c->popbuf[c->cur], s + 256, state_pop_bytes(c), hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess && c->p.n_atoms > 0) {
     e = hipMemcpyAsync(c->ws + c->lay.disp[c->dcur], s + 256 + pb, 12 * (size_t)c->p.n_atoms,
                        hipMemcpyDeviceToDevice, c->stream);
@@ -574,6 +576,200 @@ lb_status lb_timing_end(lb_ctx* c, double out_ms[3]) {
   out_ms[2] = c->timed;
   free_events(c);
   return LB_OK;
+}
+
+// ---- adjoint -------------------------------------------------------------------------------
+namespace {
+
+struct AdjLayout {
+  size_t final_state, slots, lam[2], phi, luc, U, lU, lf, lx[2], lv[2], dg_part, dom_part, acc, total;
+};
+
+AdjLayout plan_adjoint(const lb_ctx* c, int k) {
+  AdjLayout l;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = round_up(off + bytes, 256);
+    return o;
+  };
+  const size_t sb = lb_state_bytes(c), N = (size_t)c->p.n_atoms, plane = (size_t)c->geo.plane;
+  l.final_state = take(sb);
+  l.slots = take(sb * (size_t)k);
+  l.lam[0] = take(19 * plane * 4);
+  l.lam[1] = take(19 * plane * 4);
+  l.phi = take(3 * plane * 4);
+  l.luc = take(3 * plane * 4);
+  l.U = take(12 * N);
+  l.lU = take(12 * N);
+  l.lf = take(16 * N);
+  for (int q = 0; q < 2; ++q) {
+    l.lx[q] = take(12 * N);
+    l.lv[q] = take(12 * N);
+  }
+  l.dg_part = take(8 * (size_t)adjoint_atom_blocks(c));
+  l.dom_part = take(8 * (size_t)c->geo.nblocks);
+  l.acc = take(16);
+  l.total = off;
+  return l;
+}
+
+// the atom part of a state record: displacement and velocity
+size_t state_atom_offset(const lb_ctx* c) { return 256 + round_up(state_pop_bytes(c), 256); }
+
+hipError_t copy_atoms(lb_ctx* c, char* dst_disp, char* dst_vel, const char* src_disp, const char* src_vel) {
+  const size_t n = 12 * (size_t)c->p.n_atoms;
+  hipError_t e = hipMemcpyAsync(dst_disp, src_disp, n, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(dst_vel, src_vel, n, hipMemcpyDeviceToDevice, c->stream);
+  return e;
+}
+
+}  // namespace
+
+size_t lb_adjoint_workspace_bytes(const lb_ctx* c, int32_t k) {
+  if (!c || k < 1 || c->p.n_atoms <= 0) return 0;
+  return plan_adjoint(c, k).total;
+}
+
+lb_status lb_backward(lb_ctx* c, const void* ckpts, int32_t n_steps, int32_t k, void* adj_ws,
+                      size_t adj_ws_bytes, const float* dL_dX, const float* dL_dv, double* dL_dgamma,
+                      double* dL_dtau, float* dL_db, float* dL_dX0, float* dL_dv0) {
+  if (!c) return fail(nullptr, LB_EINVAL, "context is NULL");
+  if (c->p.n_atoms <= 0) return fail(c, LB_EINVAL, "lb_backward needs atoms (the loss is a function of them)");
+  if (n_steps < 1 || k < 1) return fail(c, LB_EINVAL, "n_steps and k must be >= 1");
+  if (!ckpts || (uintptr_t)ckpts % 256) return fail(c, LB_EINVAL, "ckpts must be a 256-byte aligned device buffer");
+  if (!adj_ws || (uintptr_t)adj_ws % 256) return fail(c, LB_EINVAL, "adj_ws must be a 256-byte aligned device buffer");
+  if (!dL_dX) return fail(c, LB_EINVAL, "dL_dX is NULL");
+  if (!dL_dgamma || !dL_dtau) return fail(c, LB_EINVAL, "dL_dgamma and dL_dtau are required (host)");
+  const AdjLayout L = plan_adjoint(c, k);
+  if (adj_ws_bytes < L.total) return fail(c, LB_ENOMEM, "adjoint workspace too small");
+  const size_t sb = lb_state_bytes(c);
+  const int n_seg = (n_steps + k - 1) / k;
+  const char* ck = (const char*)ckpts;
+  int64_t first = 0, last = 0;
+  hipError_t e = hipMemcpyAsync(&first, ck, 8, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&last, ck + (size_t)(n_seg - 1) * sb, 8, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "reading the checkpoints");
+  if (first + n_steps != c->step || last != first + (int64_t)(n_seg - 1) * k)
+    return fail(c, LB_ESTATE, "checkpoints do not match: ckpts[s] must hold the state at step "
+                              "(current step - n_steps) + s k");
+
+  char* A = (char*)adj_ws;
+  const size_t N3 = 3 * (size_t)c->p.n_atoms;
+  const size_t aoff = state_atom_offset(c), abytes = round_up(12 * (size_t)c->p.n_atoms, 256);
+  auto slot = [&](int q) { return A + L.slots + (size_t)q * sb; };
+  const hipStream_t as = c->astream, fs = c->fstream;
+  char* pb0 = c->popbuf[0];
+  char* pb1 = c->popbuf[1];
+  lb_status st = LB_OK;
+  // every kernel of the backward pass runs in order on the caller's stream
+  c->astream = c->fstream = c->stream;
+  if ((st = lb_state_save(c, A + L.final_state)) != LB_OK) goto restore;
+  if ((e = launch_zero(A + L.lam[0], 19 * (size_t)c->geo.plane * 4, c->stream)) != hipSuccess ||
+      (e = launch_zero(A + L.acc, 16, c->stream)) != hipSuccess ||
+      (dL_db && (e = launch_zero(dL_db, 12 * (size_t)c->geo.S, c->stream)) != hipSuccess) ||
+      (e = hipMemcpyAsync(A + L.lx[0], dL_dX, 4 * N3, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess ||
+      (e = dL_dv ? hipMemcpyAsync(A + L.lv[0], dL_dv, 4 * N3, hipMemcpyDeviceToDevice, c->stream)
+                 : launch_zero(A + L.lv[0], 4 * N3, c->stream)) != hipSuccess) {
+    st = hip_fail(c, e, "adjoint set-up");
+    goto restore;
+  }
+  {
+    int li = 0;
+    for (int seg = n_seg - 1; seg >= 0; --seg) {
+      const int t0 = seg * k, len = std::min(k, n_steps - t0);
+      if ((e = hipMemcpyAsync(slot(0), ck + (size_t)seg * sb, sb, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess) {
+        st = hip_fail(c, e, "checkpoint copy");
+        goto restore;
+      }
+      // recompute the segment, each step's output going straight into the next slot
+      for (int q = 0; q + 1 < len; ++q) {
+        char* disp = c->ws + c->lay.disp[c->dcur];
+        char* vel = c->ws + c->lay.vel;
+        if ((e = copy_atoms(c, disp, vel, slot(q) + aoff, slot(q) + aoff + abytes)) != hipSuccess) {
+          st = hip_fail(c, e, "recompute copy");
+          goto restore;
+        }
+        c->popbuf[c->cur] = slot(q) + 256;
+        c->popbuf[c->cur ^ 1] = slot(q + 1) + 256;
+        c->step = first + t0 + q;
+        if ((st = lb_couple_step(c, 1)) != LB_OK) goto restore;
+        if ((e = copy_atoms(c, slot(q + 1) + aoff, slot(q + 1) + aoff + abytes, c->ws + c->lay.disp[c->dcur],
+                            c->ws + c->lay.vel)) != hipSuccess) {
+          st = hip_fail(c, e, "recompute copy");
+          goto restore;
+        }
+      }
+      // the adjoint steps of the segment, last first
+      for (int q = len - 1; q >= 0; --q) {
+        if ((e = copy_atoms(c, c->ws + c->lay.disp[c->dcur], c->ws + c->lay.vel, slot(q) + aoff,
+                            slot(q) + aoff + abytes)) != hipSuccess) {
+          st = hip_fail(c, e, "adjoint copy");
+          goto restore;
+        }
+        c->popbuf[c->cur] = slot(q) + 256;
+        c->step = first + t0 + q;
+        c->couple_u = (float*)(A + L.U);
+        if ((e = launch_prep(c)) != hipSuccess || (e = launch_bin_mark(c)) != hipSuccess ||
+            (e = launch_compact(c)) != hipSuccess ||
+            (c->geo.ncell > 0 && (e = launch_cell_sort(c)) != hipSuccess) ||
+            (e = launch_node_u(c)) != hipSuccess || (e = launch_couple(c)) != hipSuccess ||
+            (e = launch_spread(c)) != hipSuccess) {
+          st = hip_fail(c, e, "adjoint recompute launch");
+          goto restore;
+        }
+        c->couple_u = nullptr;
+        AdjointBuffers b;
+        b.lam_in = (const float*)(A + L.lam[li]);
+        b.lam_out = (float*)(A + L.lam[li ^ 1]);
+        b.phi = (float*)(A + L.phi);
+        b.luc = (float*)(A + L.luc);
+        b.db = dL_db;
+        b.dom_part = (double*)(A + L.dom_part);
+        b.dg_part = (double*)(A + L.dg_part);
+        b.acc = (double*)(A + L.acc);
+        b.U = (const float*)(A + L.U);
+        b.lU = (float*)(A + L.lU);
+        b.lf = (float4*)(A + L.lf);
+        b.lx_in = (const float*)(A + L.lx[li]);
+        b.lv_in = (const float*)(A + L.lv[li]);
+        b.lx_out = (float*)(A + L.lx[li ^ 1]);
+        b.lv_out = (float*)(A + L.lv[li ^ 1]);
+        if ((e = launch_adjoint_step(c, b)) != hipSuccess) {
+          st = hip_fail(c, e, "adjoint step launch");
+          goto restore;
+        }
+        li ^= 1;
+      }
+    }
+    if ((dL_dX0 && (e = hipMemcpyAsync(dL_dX0, A + L.lx[li], 4 * N3, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess) ||
+        (dL_dv0 && (e = hipMemcpyAsync(dL_dv0, A + L.lv[li], 4 * N3, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)) {
+      st = hip_fail(c, e, "adjoint output");
+      goto restore;
+    }
+    double acc[2];
+    if ((e = hipMemcpyAsync(acc, A + L.acc, 16, hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(c->stream)) != hipSuccess) {
+      st = hip_fail(c, e, "adjoint result");
+      goto restore;
+    }
+    *dL_dgamma = acc[0];
+    // omega = 1/tau
+    *dL_dtau = -acc[1] / ((double)c->p.tau * (double)c->p.tau);
+  }
+restore:
+  c->couple_u = nullptr;
+  c->popbuf[0] = pb0;
+  c->popbuf[1] = pb1;
+  {
+    const lb_status s2 = lb_state_load(c, A + L.final_state);
+    c->astream = as;
+    c->fstream = fs;
+    if (st == LB_OK) st = s2;
+  }
+  if (st == LB_OK) st = lb_status_check(c);
+  return st;
 }
 
 lb_status lb_destroy(lb_ctx* c) {

@@ -89,6 +89,8 @@ struct lb_ctx {
   lbmd::Layout lay;
   hipStream_t stream;
   char* ws;
+  char* popbuf[2];  // population buffers A / B (inside ws; the adjoint points them at its slots)
+  float* couple_u = nullptr;  // when set, k_couple also stores U (the adjoint needs it)
   int cur;        // which population buffer holds the current state
   int dcur;       // which displacement buffer holds X^n - x0
   int64_t step;
@@ -125,7 +127,34 @@ hipError_t launch_node_u(lb_ctx* c);
 hipError_t launch_couple(lb_ctx* c);
 hipError_t launch_spread(lb_ctx* c);
 hipError_t launch_forces(lb_ctx* c);
+// adjoint: lx_out = lx_in + (d F_ff / d X)^T lf at the context's current positions
+hipError_t launch_force_hvp(lb_ctx* c, const float4* lf, const float* lx_in, float* lx_out);
 hipError_t launch_integrate(lb_ctx* c);
 hipError_t launch_read_atoms(lb_ctx* c, float* x, float* v);
+
+// ---- adjoint (adjoint.hip) ----
+// Buffers of one adjoint step: "in" holds the adjoints at step n + 1, "out" receives them at
+// step n.  U is the interpolated fluid velocity that k_couple stored for this step.
+struct AdjointBuffers {
+  const float* lam_in;   // dL/dP^{n+1}, FP32 [19][plane]
+  float* lam_out;        // dL/dP^n
+  float* phi;            // [3][plane] dL/dF on flagged tiles
+  float* luc;            // [3][plane] dL/du_c on flagged tiles
+  float* db;             // [3][S] dL/dF_ext accumulated, or NULL
+  double* dom_part;      // [nblocks]
+  double* dg_part;       // [adjoint_atom_blocks]
+  double* acc;           // [2]: dL/dgamma, dL/domega
+  const float* U;        // [N][3]
+  float* lU;             // [N][3]
+  float4* lf;            // [N]
+  const float* lx_in;    // [N][3] dL/dX^{n+1}
+  const float* lv_in;    // [N][3] dL/dv^{n+1}
+  float* lx_out;
+  float* lv_out;
+};
+unsigned adjoint_atom_blocks(const lb_ctx* c);
+// the adjoint of step c->step, with the context's forward buffers holding that step's
+// binning, coupling velocity, friction and spread force
+hipError_t launch_adjoint_step(lb_ctx* c, const AdjointBuffers& b);
 
 }  // namespace lbmd

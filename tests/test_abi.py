@@ -98,3 +98,12 @@ def test_null_context_calls():
     assert lib.lb_step_count(None) == -1
     assert lib.lb_state_bytes(None) == 0
     assert "NULL" in A.lb_last_error(None)
+
+
+def test_adjoint_entry_points_reject_null_context():
+    lib = A.lib()
+    assert lib.lb_adjoint_workspace_bytes(None, 20) == 0
+    dg, dt = ctypes.c_double(), ctypes.c_double()
+    st = lib.lb_backward(None, None, 10, 5, None, 0, None, None, ctypes.byref(dg), ctypes.byref(dt),
+                         None, None, None)
+    assert st == A.LB_EINVAL

@@ -1,0 +1,137 @@
+"""GPU adjoint (lb_backward, checkpoint-and-recompute) against the oracle's exact
+forward-mode derivatives of the same discrete scheme.
+
+Loss (the differentiation workload's): L = (1/N) sum_a |X_a(T) - (X_a(0) + D)|^2.  The GPU gets
+dL/dX(T) = 2 (X(T) - X(0) - D)/N from its own final displacement and returns dL/dgamma,
+dL/dtau and dL/dF_ext; the oracle gives dL/dgamma, dL/dtau and the directional derivative
+<dL/dF_ext, dF> along seeded directions, all in FP64.  Tolerance: 1e-3 relative (FP32
+adjoint against FP64 exact derivatives), tighter where the dynamics are linear.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_grads(w, field, D, steps, k, storage="f32", reps=1):
+    import torch
+    from paper_2305_05025_amd import _abi as A
+    from paper_2305_05025_amd.coupled import CoupledLB, params_from_workload
+    say("adjoint", w.name, w.L, "atoms", w.n_atoms, "steps", steps, "k", k, storage)
+    p = params_from_workload(w, storage)
+    p.bf_kind = A.LB_BF_FIELD
+    sim = CoupledLB(p, w.x0, w.v0, w.bonds, field.astype(np.float32))
+    ck = sim.run_checkpointed(steps, k)
+    d = sim.displacement().double().cpu().numpy()
+    g_before = sim.populations().cpu().numpy()
+    dLdX = 2.0 * (d - D[None, :]) / w.n_atoms
+    outs = [sim.backward(ck, torch.from_numpy(dLdX.astype(np.float32))) for _ in range(reps)]
+    g_after = sim.populations().cpu().numpy()
+    assert sim.step_count == steps
+    assert np.array_equal(g_before, g_after), "lb_backward must restore the context's state"
+    sim.close()
+    return outs, d
+
+
+def _oracle_grads(O, w, field, D, steps, dfields):
+    p = O.params_from_workload(w)
+    p.bf_kind = 3
+    g0 = np.zeros(O.pop_shape(p))
+    X0 = w.x0.astype(np.float64)
+    V0 = w.v0.astype(np.float64)
+    f64 = field.astype(np.float32).astype(np.float64)
+    _, dg = O.loss_derivative(p, g0, X0, V0, w.bonds, f64, D, steps, 0)
+    _, dt = O.loss_derivative(p, g0, X0, V0, w.bonds, f64, D, steps, 1)
+    dbs = [O.loss_derivative(p, g0, X0, V0, w.bonds, f64, D, steps, 2, df)[1] for df in dfields]
+    return dg, dt, dbs
+
+
+def _check(outs, orc, dfields, tol):
+    dg, dt, dbs = orc
+    out = outs[0]
+    db = out["body_force"].double().cpu().numpy()
+    errs = {"gamma": abs(out["gamma"] - dg) / abs(dg), "tau": abs(out["tau"] - dt) / abs(dt)}
+    for q, (df, ref) in enumerate(zip(dfields, dbs)):
+        errs["db%d" % q] = abs(float((db * df).sum()) - ref) / abs(ref)
+    say("adjoint rel errors", errs, "oracle", dg, dt, dbs)
+    for k, e in errs.items():
+        assert e < tol, (k, e, errs)
+    for o in outs[1:]:      # repeated backward passes are bitwise identical
+        assert o["gamma"] == out["gamma"] and o["tau"] == out["tau"]
+        assert bool((o["body_force"] == out["body_force"]).all())
+
+
+def _dfields(rng, shape, n=2):
+    return [rng.normal(0, 1.0, size=shape) for _ in range(n)]
+
+
+def test_adjoint_globule_with_lj_and_bonds(O):
+    """One 60-atom globule (bonds + LJ) in a 10^3 box with a random body-force field;
+    12 steps in segments of 5 (three segments, the last one shorter)."""
+    from workloads import globule_workload
+    L = 10
+    w = globule_workload(L, 1, 60, seed=21, tau=0.7, gamma=0.15)
+    rng = np.random.default_rng(3)
+    field = rng.normal(0, 1e-5, size=(3, L, L, L))
+    D = np.array([0.6, -0.48, 0.64])
+    dfields = _dfields(rng, field.shape)
+    outs, _ = _gpu_grads(w, field, D, 12, 5, reps=2)
+    _check(outs, _oracle_grads(O, w, field, D, 12, dfields), dfields, 1e-3)
+
+
+def test_adjoint_tethered_ball_without_lj(O):
+    """Linear dynamics (tethers + friction, no LJ) on a ragged 14 x 12 x 10 box: 20 steps in
+    segments of 7."""
+    from workloads import small_workload
+    w = small_workload((14, 12, 10), 40, seed=5, tau=0.8, gamma=0.1, k_tether=0.05, lj=False,
+                       mass=8.0)
+    rng = np.random.default_rng(9)
+    field = rng.normal(0, 1e-5, size=(3, 10, 12, 14))
+    D = np.array([0.0, 0.8, -0.6])
+    dfields = _dfields(rng, field.shape)
+    outs, _ = _gpu_grads(w, field, D, 20, 7)
+    _check(outs, _oracle_grads(O, w, field, D, 20, dfields), dfields, 2e-4)
+
+
+def test_adjoint_segment_length_does_not_matter(O):
+    """k = 1, 4 and n_steps give the same gradients (recompute is exact)."""
+    from workloads import globule_workload
+    L = 12
+    w = globule_workload(L, 1, 80, seed=4, tau=0.75, gamma=0.2)
+    rng = np.random.default_rng(1)
+    field = rng.normal(0, 1e-5, size=(3, L, L, L))
+    D = np.array([0.36, 0.48, 0.8])
+    res = [_gpu_grads(w, field, D, 9, k)[0][0] for k in (1, 4, 9)]
+    for r in res[1:]:
+        assert r["gamma"] == res[0]["gamma"] and r["tau"] == res[0]["tau"]
+        assert bool((r["body_force"] == res[0]["body_force"]).all())
+
+
+def test_autograd_function_matches_direct_call(O):
+    """torch.autograd through paper_2305_05025_amd.autograd.trajectory gives the gradients of
+    the direct lb_backward call, and they match the oracle."""
+    import torch
+    from paper_2305_05025_amd.autograd import trajectory
+    from workloads import globule_workload
+    L = 10
+    w = globule_workload(L, 1, 60, seed=21, tau=0.7, gamma=0.15)
+    rng = np.random.default_rng(3)
+    field = rng.normal(0, 1e-5, size=(3, L, L, L))
+    D = np.array([0.6, -0.48, 0.64])
+    dfields = _dfields(rng, field.shape)
+    gamma = torch.tensor(0.15, dtype=torch.float64, requires_grad=True)
+    tau = torch.tensor(0.7, dtype=torch.float64, requires_grad=True)
+    b = torch.tensor(field.astype(np.float32), device="cuda", requires_grad=True)
+    say("autograd trajectory", w.name)
+    disp, v = trajectory(w, gamma, tau, b, 12, k=5)
+    Dt = torch.tensor(D, dtype=torch.float32, device="cuda")
+    loss = ((disp - Dt) ** 2).sum(1).mean()
+    loss.backward()
+    dg, dt, dbs = _oracle_grads(O, w, field, D, 12, dfields)
+    assert abs(gamma.grad.item() - dg) < 1e-3 * abs(dg)
+    assert abs(tau.grad.item() - dt) < 1e-3 * abs(dt)
+    db = b.grad.double().cpu().numpy()
+    for df, ref in zip(dfields, dbs):
+        assert abs(float((db * df).sum()) - ref) < 1e-3 * abs(ref)
