@@ -94,6 +94,65 @@ def cpu_baseline(k: int):
                       % (steps, Ls[0], Ls[1], Ls[2], n_per, w.name, dt)}
 
 
+def time_steps(sim, steps: int, warmup: int):
+    """(ms per step, wall s) of `steps` coupled steps after `warmup` untimed ones, bracketed by
+    device synchronisation; no per-phase events are queued."""
+    import torch
+    sim.step(warmup)
+    sim.check()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    ev0.record(sim.stream)
+    sim.step(steps)
+    ev1.record(sim.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    sim.check()
+    return ev0.elapsed_time(ev1) / steps, wall
+
+
+def adjoint_ratio(dev):
+    """Forward and backward (adjoint with checkpoint-and-recompute) times on the
+    differentiation workload: 96^3 lattice, one 5,000-atom globule, body-force field, 200
+    steps, checkpoints every 20 steps."""
+    import numpy as np
+    import torch
+    from paper_2305_05025_amd.coupled import CoupledLB
+    from workloads import make_workload
+    w = make_workload(3)
+    n_steps, k = 200, 20
+    sim = CoupledLB.from_workload(w, device=dev)
+    fwd_ms, _ = time_steps(sim, n_steps, 0)
+    sim.close()
+    res = []
+    for rep in range(2):      # the first pass includes one-off allocation
+        sim = CoupledLB.from_workload(w, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ck = sim.run_checkpointed(n_steps, k)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        d = sim.displacement().double()
+        D = torch.tensor(w.target_shift, dtype=torch.float64, device=dev)
+        dLdX = (2.0 * (d - D) / w.n_atoms).float()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        g = sim.backward(ck, dLdX)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        sim.close()
+        res.append(((t1 - t0) * 1e3, (t3 - t2) * 1e3, g))
+    ck_ms, bwd_ms, g = res[-1]
+    return {"workload": w.name, "steps": n_steps, "k": k,
+            "forward_ms": round(fwd_ms * n_steps, 3),
+            "forward_with_checkpoints_ms": round(ck_ms, 3),
+            "backward_ms": round(bwd_ms, 3),
+            "ratio": round(bwd_ms / (fwd_ms * n_steps), 3),
+            "dL_dgamma": g["gamma"], "dL_dtau": g["tau"],
+            "dL_db_norm": float(torch.linalg.vector_norm(g["body_force"]).item())}
+
+
 def run(args):
     import torch
     from paper_2305_05025_amd import _abi as A
@@ -106,32 +165,32 @@ def run(args):
     log("workload %s: lattice %s, %d atoms, built in %.1f s" % (w.name, w.L, w.n_atoms, time.time() - t0))
     flags = A.LB_FLAG_SINGLE_STREAM if args.single_stream else 0
     sim = CoupledLB.from_workload(w, storage=args.storage, device=dev, flags=flags)
-    stream = sim.stream
-    sim.step(args.warmup)
-    sim.check()
-    torch.cuda.synchronize()
-    log("warmup done (%d steps)" % args.warmup)
-
     # the step: K steps with no per-phase events in the queue
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    ev0.record(stream)
-    sim.step(args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    sim.check()
-    step_ms = ev0.elapsed_time(ev1) / args.steps
+    step_ms, wall = time_steps(sim, args.steps, args.warmup)
     # the kernels: K more steps with HIP events around each phase, on the streams the
     # phases run on
     A.lb_timing_begin(sim.ctx, args.steps)
     sim.step(args.steps)
     sweep_ms, atom_ms, nsteps = A.lb_timing_end(sim.ctx)
     sim.check()
+    sim.close()
     log("timed %d steps: %.4f ms/step (events), wall %.3f s; per step in a second timed run: "
         "sweep kernel %.4f ms, atom kernel chains %.4f ms" %
         (args.steps, step_ms, wall, sweep_ms / nsteps, atom_ms / nsteps))
+    # the other storage formats, same workload and schedule
+    storage_ms = {args.storage: round(step_ms, 5)}
+    if args.formats:
+        for fmt in ("f32", "f16", "bf16"):
+            if fmt in storage_ms:
+                continue
+            s2 = CoupledLB.from_workload(w, storage=fmt, device=dev, flags=flags)
+            storage_ms[fmt] = round(time_steps(s2, args.steps, args.warmup)[0], 5)
+            s2.close()
+            log("storage %s: %.4f ms/step" % (fmt, storage_ms[fmt]))
+    adj = None
+    if args.adjoint:
+        adj = adjoint_ratio(dev)
+        log("adjoint: %s" % adj)
 
     S = w.n_sites
     field = w.bf_kind == 3
@@ -171,9 +230,12 @@ def run(args):
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "k_sweep<%s>" % args.storage,
                      "bytes_per_site": bps, "sweep_ms": round(sweep_ms / nsteps, 5)},
-        "adjoint_forward_ratio": None,
+        "storage_ms_per_step": storage_ms,
+        "f16_speedup": (round(storage_ms["f32"] / storage_ms["f16"], 4)
+                        if "f32" in storage_ms and "f16" in storage_ms else None),
+        "adjoint_forward_ratio": adj["ratio"] if adj else None,
+        "adjoint": adj,
     }
-    sim.close()
     if args.cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(args.config)
@@ -203,6 +265,10 @@ def main():
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--no-formats", dest="formats", action="store_false",
+                    help="skip the FP16/BF16 (or FP32) storage timings")
+    ap.add_argument("--no-adjoint", dest="adjoint", action="store_false",
+                    help="skip the adjoint/forward timing on the differentiation workload")
     ap.add_argument("--single-stream", action="store_true",
                     help="queue every kernel on one stream (no overlap of atom and lattice work)")
     args = ap.parse_args()
