@@ -413,21 +413,20 @@ __device__ __forceinline__ void bonded_and_store(const ForceArgs& a, int i, floa
 //   2. the records of those cells are copied into LDS (one coalesced load per cell, issued
 //      back to back), already shifted into the home cell's frame; if they exceed the stage,
 //      cells are staged in several rounds;
-//   3. lane = (home slot 0..15) + 16 * (group 0..3); group g takes staged records g, g+4,
-//      ...; all lanes of a group read the same LDS record (a broadcast).  Home cells with
-//      more than 16 atoms run up to 3 passes over the same staged records.
+//   3. the 64 lanes are split into groups of hs home slots, hs the smallest power of two
+//      >= max(home atoms, 8), so a cell of up to 8 atoms runs 8 groups, one of up to 16
+//      runs 4, and so on; group g takes staged records g, g + ngroups, ...; all lanes of a
+//      group read the same LDS record (a broadcast).
 // Each lane sums in FP32 in a fixed order (records in cell order, atom-index order inside a
-// cell); the 4 group partials meet through two xor-shuffles in a fixed order; group 0 then
-// adds tethers and bonds and updates the atom.  Pair vectors come from exact fixed-point
-// differences.  Each atom sits in exactly one cell slot, so every atom is updated once.
-constexpr int kStage = 640;   // staged records per wavefront (27 cells of ~9.5 atoms need ~260)
-constexpr int kPasses = kCellCap / 16;
+// cell); the group partials meet through xor-shuffles in a fixed order; group 0 then adds
+// tethers and bonds and stores.  Pair vectors come from exact fixed-point differences.
+// Each atom sits in exactly one cell slot, so every atom is written once.
+constexpr int kStage = 320;   // staged records per wavefront (27 cells of ~9 atoms need ~240)
 
 template <bool kAdj>
 __global__ __launch_bounds__(256) void k_forces_cells(ForceArgs a) {
   __shared__ int4 stage_all[4][kStage];
   const int lane = threadIdx.x & 63;
-  const int hl = lane & 15, grp = lane >> 4;
   int4* stage = stage_all[threadIdx.x >> 6];
   const int nc0 = a.g.nc[0], nc1 = a.g.nc[1], nc2 = a.g.nc[2];
   const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6, nwave = gridDim.x * 4;
@@ -436,32 +435,27 @@ __global__ __launch_bounds__(256) void k_forces_cells(ForceArgs a) {
     const long cell = a.occ_cells[k];
     int nh = a.cell_count[cell];
     nh = nh > kCellCap ? kCellCap : nh;
+    const int hs_log = nh <= 8 ? 3 : (nh <= 16 ? 4 : (nh <= 32 ? 5 : 6));
+    const int hs = 1 << hs_log;
+    const int hl = lane & (hs - 1), grp = lane >> hs_log, ngrp = 64 >> hs_log;
     const int q[3] = {(int)(cell % nc0), (int)((cell / nc0) % nc1), (int)(cell / ((long)nc0 * nc1))};
-    // home atoms of each pass
-    int4 me[kPasses];
-    int pb[kPasses][4], b0s[kPasses], b1s[kPasses];
-    bool hv[kPasses];
-    float Fx[kPasses], Fy[kPasses], Fz[kPasses];
-    float4 lfi[kPasses];
-#pragma unroll
-    for (int p = 0; p < kPasses; ++p) {
-      const int h = 16 * p + hl;
-      hv[p] = h < nh;
-      me[p] = a.cell_rec[cell * kCellCap + (hv[p] ? h : 0)];
-      const int i = me[p].w;
-      if constexpr (kAdj) lfi[p] = a.lf[i];
-      b0s[p] = a.bond_off[i];
-      b1s[p] = a.bond_off[i + 1];
-      pb[p][0] = pb[p][1] = pb[p][2] = pb[p][3] = -1;
-      if (a.lj_exclude_bonded) {
-        const int deg = b1s[p] - b0s[p];
-        if (deg > 0) pb[p][0] = a.bond_nbr[b0s[p]];
-        if (deg > 1) pb[p][1] = a.bond_nbr[b0s[p] + 1];
-        if (deg > 2) pb[p][2] = a.bond_nbr[b0s[p] + 2];
-        if (deg > 3) pb[p][3] = a.bond_nbr[b0s[p] + 3];
-      }
-      Fx[p] = Fy[p] = Fz[p] = 0.f;
+    // this lane's home atom
+    const bool hv = hl < nh;
+    const int4 me = a.cell_rec[cell * kCellCap + (hv ? hl : 0)];
+    const int i = me.w;
+    const int b0 = a.bond_off[i], b1 = a.bond_off[i + 1];
+    int pb[4] = {-1, -1, -1, -1};
+    if (a.lj_exclude_bonded) {
+      const int deg = b1 - b0;
+      if (deg > 0) pb[0] = a.bond_nbr[b0];
+      if (deg > 1) pb[1] = a.bond_nbr[b0 + 1];
+      if (deg > 2) pb[2] = a.bond_nbr[b0 + 2];
+      if (deg > 3) pb[3] = a.bond_nbr[b0 + 3];
     }
+    const bool excl = a.lj_exclude_bonded && b1 > b0;
+    float4 lfi = make_float4(0.f, 0.f, 0.f, 0.f);
+    if constexpr (kAdj) lfi = a.lf[i];
+    float Fx = 0.f, Fy = 0.f, Fz = 0.f;
     // neighbour cells: lane l < 27 holds cell l of the 3x3x3 block
     long nbc = 0;
     int nbn = 0, shx = 0, shy = 0, shz = 0;
@@ -501,24 +495,19 @@ __global__ __launch_bounds__(256) void k_forces_cells(ForceArgs a) {
       }
       wave_lds_sync();
       const int ntot = __shfl(pre, kend - 1, 64) - base;
-#pragma unroll
-      for (int p = 0; p < kPasses; ++p) {
-        if (16 * p >= nh) break;
-        if (!hv[p]) continue;
-        const int i = me[p].w;
-        const bool excl = a.lj_exclude_bonded && b1s[p] > b0s[p];
-        for (int c = grp; c < ntot; c += 4) {
+      if (hv) {
+        for (int c = grp; c < ntot; c += ngrp) {
           const int4 r4 = stage[c];
           // pair vector X_i - X_j: exact integer difference, one rounding
-          const float rx = (float)(me[p].x - r4.x) * kCellFixInv;
-          const float ry = (float)(me[p].y - r4.y) * kCellFixInv;
-          const float rz = (float)(me[p].z - r4.z) * kCellFixInv;
+          const float rx = (float)(me.x - r4.x) * kCellFixInv;
+          const float ry = (float)(me.y - r4.y) * kCellFixInv;
+          const float rz = (float)(me.z - r4.z) * kCellFixInv;
           const float r2 = rx * rx + ry * ry + rz * rz;
           const int j = r4.w;
           if (!(r2 < a.lj_rc2) || j == i) continue;
           if (excl) {
-            bool bonded = j == pb[p][0] || j == pb[p][1] || j == pb[p][2] || j == pb[p][3];
-            for (int bb = b0s[p] + 4; bb < b1s[p]; ++bb) bonded = bonded || (a.bond_nbr[bb] == j);
+            bool bonded = j == pb[0] || j == pb[1] || j == pb[2] || j == pb[3];
+            for (int bb = b0 + 4; bb < b1; ++bb) bonded = bonded || (a.bond_nbr[bb] == j);
             if (bonded) continue;
           }
           const float inv2 = __builtin_amdgcn_rcpf(r2);
@@ -529,34 +518,28 @@ __global__ __launch_bounds__(256) void k_forces_cells(ForceArgs a) {
             // g(s) = 24 eps (2 sigma^12 s^-7 - sigma^6 s^-4), s = r^2
             const float gp2 = 2.0f * a.lj_eps24 * (4.0f * sr6 - 14.0f * sr6 * sr6) * inv2 * inv2;
             const float4 lj = a.lf[j];
-            const float ex = lfi[p].x - lj.x, ey = lfi[p].y - lj.y, ez = lfi[p].z - lj.z;
+            const float ex = lfi.x - lj.x, ey = lfi.y - lj.y, ez = lfi.z - lj.z;
             const float t = gp2 * (rx * ex + ry * ey + rz * ez);
-            Fx[p] += f * ex + t * rx;
-            Fy[p] += f * ey + t * ry;
-            Fz[p] += f * ez + t * rz;
+            Fx += f * ex + t * rx;
+            Fy += f * ey + t * ry;
+            Fz += f * ez + t * rz;
           } else {
-            Fx[p] += f * rx;
-            Fy[p] += f * ry;
-            Fz[p] += f * rz;
+            Fx += f * rx;
+            Fy += f * ry;
+            Fz += f * rz;
           }
         }
       }
       wave_lds_sync();
       kc = kend;
     }
-#pragma unroll
-    for (int p = 0; p < kPasses; ++p) {
-      if (16 * p >= nh) break;
-      // groups 0+1 and 2+3, then the two pairs: a fixed summation order
-      float fx = Fx[p], fy = Fy[p], fz = Fz[p];
-      fx += __shfl_xor(fx, 16, 64);
-      fy += __shfl_xor(fy, 16, 64);
-      fz += __shfl_xor(fz, 16, 64);
-      fx += __shfl_xor(fx, 32, 64);
-      fy += __shfl_xor(fy, 32, 64);
-      fz += __shfl_xor(fz, 32, 64);
-      if (hv[p] && grp == 0) bonded_and_store<kAdj>(a, me[p].w, fx, fy, fz);
+    // group partials: pairs of groups, then pairs of pairs, ... (a fixed order per hs)
+    for (int o = hs; o < 64; o <<= 1) {
+      Fx += __shfl_xor(Fx, o, 64);
+      Fy += __shfl_xor(Fy, o, 64);
+      Fz += __shfl_xor(Fz, o, 64);
     }
+    if (hv && grp == 0) bonded_and_store<kAdj>(a, i, Fx, Fy, Fz);
   }
 }
 

@@ -313,8 +313,7 @@ lb_status lb_init(const lb_params* p, void* workspace, size_t workspace_bytes, c
         (e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&c->ev_bin, hipEventDisableTiming)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&c->ev_spread, hipEventDisableTiming)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&c->ev_couple, hipEventDisableTiming)) != hipSuccess) {
+        (e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming)) != hipSuccess) {
       lb_destroy(c);
       return hip_fail(nullptr, e, "creating the atom stream");
     }
@@ -330,12 +329,13 @@ lb_status lb_couple_step(lb_ctx* c, int32_t n_steps) {
   const bool atoms = c->p.n_atoms > 0;
   hipError_t e;
   // Three streams (the caller's "main" stream, "atoms" and "forces").  Step n:
-  //   main:   wait ev_bin(n); node u_c, couple -> ev_couple; spread -> ev_spread; sweep
+  //   main:   wait ev_bin(n); node u_c, couple, spread -> ev_spread; sweep
   //   forces: wait ev_bin(n); cell sort, force field at X^n -> ev_forces
-  //   atoms:  wait ev_couple, ev_forces; integration; then, for step n + 1:
-  //           wait ev_spread; prep, bin/mark, compaction -> ev_bin(n + 1)
-  // The coupling and the sweep run back to back on one stream; the force field, integration
-  // and the next step's binning overlap the sweep.  The atom stream first waits for
+  //   atoms:  wait ev_spread, ev_forces; integration; then, for step n + 1:
+  //           prep, bin/mark, compaction -> ev_bin(n + 1)
+  // The coupling and the sweep run back to back on one stream; the force field (which
+  // needs only X^n) overlaps both, and the integration and the next step's binning overlap
+  // the sweep.  The atom stream first waits for
   // everything already queued on the caller's stream, and the caller's stream finally waits
   // for the atom stream (which has waited for the force stream), so the call behaves as if
   // it had been queued on the caller's stream alone.  With LB_FLAG_SINGLE_STREAM every
@@ -373,15 +373,14 @@ lb_status lb_couple_step(lb_ctx* c, int32_t n_steps) {
       if (multi && ((e = hipStreamWaitEvent(c->stream, c->ev_bin, 0)) != hipSuccess ||
                     (e = hipStreamWaitEvent(c->fstream, c->ev_bin, 0)) != hipSuccess))
         return hip_fail(c, e, "binning wait");
-      rec(ev, 6, c->fstream);
       if (c->geo.ncell > 0 && (e = launch_cell_sort(c)) != hipSuccess) return hip_fail(c, e, "cell sort launch");
+      rec(ev, 6, c->fstream);
       if ((e = launch_forces(c)) != hipSuccess) return hip_fail(c, e, "force launch");
       rec(ev, 7, c->fstream);
       if (multi && (e = hipEventRecord(c->ev_forces, c->fstream)) != hipSuccess) return hip_fail(c, e, "force event");
       rec(ev, 0, c->stream);
       if ((e = launch_node_u(c)) != hipSuccess) return hip_fail(c, e, "node velocity launch");
       if ((e = launch_couple(c)) != hipSuccess) return hip_fail(c, e, "coupling launch");
-      if (multi && (e = hipEventRecord(c->ev_couple, c->stream)) != hipSuccess) return hip_fail(c, e, "coupling event");
       if ((e = launch_spread(c)) != hipSuccess) return hip_fail(c, e, "spread launch");
       rec(ev, 1, c->stream);
       if (multi && (e = hipEventRecord(c->ev_spread, c->stream)) != hipSuccess) return hip_fail(c, e, "spread event");
@@ -390,20 +389,17 @@ lb_status lb_couple_step(lb_ctx* c, int32_t n_steps) {
     if ((e = launch_sweep(c, fin, fout, c->stream)) != hipSuccess) return hip_fail(c, e, "sweep launch");
     rec(ev, 3, c->stream);
     if (atoms) {
-      if (multi && ((e = hipStreamWaitEvent(c->astream, c->ev_couple, 0)) != hipSuccess ||
+      if (multi && ((e = hipStreamWaitEvent(c->astream, c->ev_spread, 0)) != hipSuccess ||
                     (e = hipStreamWaitEvent(c->astream, c->ev_forces, 0)) != hipSuccess))
-        return hip_fail(c, e, "coupling/force wait");
+        return hip_fail(c, e, "spread/force wait");
       if ((e = launch_integrate(c)) != hipSuccess) return hip_fail(c, e, "integration launch");
     }
     c->cur ^= 1;
     if (atoms) c->dcur ^= 1;
     c->step++;
-    if (multi && n + 1 < n_steps) {
-      // the next binning rewrites the node flags and the atoms' stencil fractions, which the
-      // spread of this step reads
-      if ((e = hipStreamWaitEvent(c->astream, c->ev_spread, 0)) != hipSuccess) return hip_fail(c, e, "spread wait");
-      if ((st = binning(slot())) != LB_OK) return st;
-    }
+    // the next binning rewrites the node flags and the atoms' stencil fractions, which this
+    // step's spread reads: the atom stream has waited for ev_spread before the integration
+    if (multi && n + 1 < n_steps && (st = binning(slot())) != LB_OK) return st;
     if (c->p.flags & LB_FLAG_CHECK_FINITE) {
       if (multi && ((e = hipEventRecord(c->ev_join, c->astream)) != hipSuccess ||
                     (e = hipStreamWaitEvent(c->stream, c->ev_join, 0)) != hipSuccess))
@@ -559,7 +555,7 @@ lb_status lb_timing_end(lb_ctx* c, double out_ms[3]) {
     return hip_fail(c, e, "synchronising");
   double sweep = 0.0, atoms = 0.0;
   const bool has_atoms = c->p.n_atoms > 0;
-  // events per step: coupling 0-1, sweep 2-3, binning 4-5, sort + force field 6-7
+  // events per step: coupling 0-1, sweep 2-3, binning 4-5, force field 6-7
   for (int k = 0; k < c->timed; ++k) {
     float t[4] = {0.f, 0.f, 0.f, 0.f};
     hipEvent_t* ev = &c->ev[kTimedEvents * (size_t)k];
@@ -780,7 +776,7 @@ lb_status lb_destroy(lb_ctx* c) {
       (void)hipStreamSynchronize(s);
       (void)hipStreamDestroy(s);
     }
-  for (hipEvent_t e : {c->ev_fork, c->ev_bin, c->ev_couple, c->ev_spread, c->ev_join, c->ev_forces})
+  for (hipEvent_t e : {c->ev_fork, c->ev_bin, c->ev_spread, c->ev_join, c->ev_forces})
     if (e) (void)hipEventDestroy(e);
   delete c;
   return LB_OK;
