@@ -413,13 +413,13 @@ __device__ __forceinline__ void bonded_and_store(const ForceArgs& a, int i, floa
 //   2. the records of those cells are copied into LDS (one coalesced load per cell, issued
 //      back to back), already shifted into the home cell's frame; if they exceed the stage,
 //      cells are staged in several rounds;
-//   3. the 64 lanes are split into groups of hs home slots, hs the smallest power of two
-//      >= max(home atoms, 8), so a cell of up to 8 atoms runs 8 groups, one of up to 16
-//      runs 4, and so on; group g takes staged records g, g + ngroups, ...; all lanes of a
-//      group read the same LDS record (a broadcast).
+//   3. the 64 lanes are split into G = floor(64 / nh) groups of nh lanes, nh the number of
+//      home atoms (lane = group * nh + home slot; the remaining lanes idle); group g takes
+//      staged records g, g + G, ...; all lanes of a group read the same LDS record (a
+//      broadcast).
 // Each lane sums in FP32 in a fixed order (records in cell order, atom-index order inside a
-// cell); the group partials meet through xor-shuffles in a fixed order; group 0 then adds
-// tethers and bonds and stores.  Pair vectors come from exact fixed-point differences.
+// cell); the group partials meet in LDS and group 0 adds them in ascending group order,
+// then adds tethers and bonds and stores.  Pair vectors come from exact fixed-point differences.
 // Each atom sits in exactly one cell slot, so every atom is written once.
 constexpr int kStage = 320;   // staged records per wavefront (27 cells of ~9 atoms need ~240)
 
@@ -435,12 +435,12 @@ __global__ __launch_bounds__(256) void k_forces_cells(ForceArgs a) {
     const long cell = a.occ_cells[k];
     int nh = a.cell_count[cell];
     nh = nh > kCellCap ? kCellCap : nh;
-    const int hs_log = nh <= 8 ? 3 : (nh <= 16 ? 4 : (nh <= 32 ? 5 : 6));
-    const int hs = 1 << hs_log;
-    const int hl = lane & (hs - 1), grp = lane >> hs_log, ngrp = 64 >> hs_log;
+    nh = nh < 1 ? 1 : nh;   // listed cells are occupied; kept for the division below
+    const int ngrp = 64 / nh;
+    const int grp = lane / nh, hl = lane - grp * nh;
     const int q[3] = {(int)(cell % nc0), (int)((cell / nc0) % nc1), (int)(cell / ((long)nc0 * nc1))};
     // this lane's home atom
-    const bool hv = hl < nh;
+    const bool hv = grp < ngrp;
     const int4 me = a.cell_rec[cell * kCellCap + (hv ? hl : 0)];
     const int i = me.w;
     const int b0 = a.bond_off[i], b1 = a.bond_off[i + 1];
@@ -533,11 +533,20 @@ __global__ __launch_bounds__(256) void k_forces_cells(ForceArgs a) {
       wave_lds_sync();
       kc = kend;
     }
-    // group partials: pairs of groups, then pairs of pairs, ... (a fixed order per hs)
-    for (int o = hs; o < 64; o <<= 1) {
-      Fx += __shfl_xor(Fx, o, 64);
-      Fy += __shfl_xor(Fy, o, 64);
-      Fz += __shfl_xor(Fz, o, 64);
+    // group partials, through this wavefront's stage: group 0 adds groups 1 .. G-1 in order
+    float* part = reinterpret_cast<float*>(stage);
+    if (ngrp > 1) {
+      part[lane] = Fx;
+      part[64 + lane] = Fy;
+      part[128 + lane] = Fz;
+      wave_lds_sync();
+      if (grp == 0)
+        for (int g = 1; g < ngrp; ++g) {
+          Fx += part[g * nh + hl];
+          Fy += part[64 + g * nh + hl];
+          Fz += part[128 + g * nh + hl];
+        }
+      wave_lds_sync();
     }
     if (hv && grp == 0) bonded_and_store<kAdj>(a, i, Fx, Fy, Fz);
   }
