@@ -750,10 +750,15 @@ static ForceArgs force_args(lb_ctx* c) {
   return a;
 }
 
+// The force field runs beside the coupling kernels and the sweep: at most 1024 workgroups
+// (4 wavefronts per SIMD) leave those kernels room; fewer made it the critical path.
+constexpr unsigned kForceGridCap = 1024;
+
 hipError_t launch_forces(lb_ctx* c) {
   const ForceArgs a = force_args(c);
   if (a.ncell > 0)
-    hipLaunchKernelGGL(k_forces_cells<false>, dim3(persistent_grid(std::min(a.ncell, (long)a.N))), dim3(256), 0,
+    hipLaunchKernelGGL(k_forces_cells<false>,
+                       dim3(std::min(persistent_grid(std::min(a.ncell, (long)a.N)), kForceGridCap)), dim3(256), 0,
                        c->fstream, a);
   else
     hipLaunchKernelGGL(k_bonded_forces<false>, dim3(blocks(a.N, 256)), dim3(256), 0, c->fstream, a);
