@@ -15,7 +15,15 @@
 //     the non-equilibrium part grow by (1 + omega) per step).
 //   * Eqs. (2)-(3): rho = sum_i f_i, rho u = sum_i f_i c_i.
 //   * The forcing term S_i of Eq. (1), here the Guo-Zheng-Shi scheme (Phys. Rev. E 65,
-//     046308, 2002) because the paper leaves the scheme open; thermal noise xi_i = 0.
+//     046308, 2002) because the paper leaves the scheme open.
+//   * The thermal noise xi_i of the source term (fluctuating LB after Adhikari et al. 2005,
+//     which the paper cites), off when kT = 0: Gaussian noise on the 15 non-conserved modes
+//     of an orthogonal D3Q19 moment basis (Duenweg, Schiller & Ladd, Phys. Rev. E 76,
+//     036704, 2007), each with variance mu b_k (1 - (1 - omega)^2), mu = rho kT / c_s^2,
+//     rho the local density before the collision.  The normals come from the counter-based
+//     generator Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11) keyed by the seed and
+//     counted by (site, step), so that any implementation of the same definition draws the
+//     same noise.
 //   * The friction coupling paragraph: fluid velocity at an atom by linear interpolation
 //     over the nearest eight lattice nodes, friction force gamma (u - v), the equal and
 //     opposite force entering the lattice through S_i with the same (trilinear) weights,
@@ -95,6 +103,8 @@ struct Model {
   int L[3];
   long S;
   T tau, rho0, gamma, mass, k_tether, k_bond, r0_bond, lj_eps, lj_sigma, lj_rc;
+  double kT;                                 // thermal energy (0: no noise)
+  uint32_t seed[2];                          // Philox key
   int lj_exclude_bonded;
   int n_atoms, n_bonds;
   std::vector<int> bond_i, bond_j;           // bond list
@@ -105,6 +115,7 @@ struct Model {
 
 template <class T>
 struct State {
+  int64_t step = 0;   // step index (counts the noise)
   std::vector<T> g;   // pre-collision populations, deviation form, [19][S]
   std::vector<T> X;   // unwrapped positions [N][3]
   std::vector<T> V;   // velocities [N][3]
@@ -233,6 +244,114 @@ void spread(const int L[3], long S, int n, const T* X, const T* F, std::vector<T
     stencil(L, &X[3 * a], node, w);
     for (int k = 0; k < 8; ++k)
       for (int c = 0; c < 3; ++c) field[c * S + node[k]] += w[k] * F[3 * a + c];
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Thermal noise.
+// Philox4x32-10: ten rounds of (L0, R0, L1, R1) -> (hi(M1 R1) ^ L1 ^ k0, lo(M1 R1),
+// hi(M0 R0) ^ L0' ^ k1, lo(M0 R0)) on the counter (x0, x1, x2, x3), with the key bumped by
+// the Weyl constants between rounds.
+// ---------------------------------------------------------------------------------------
+void philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t x[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * x[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * x[2];
+    const uint32_t y0 = (uint32_t)(p1 >> 32) ^ x[1] ^ k0;
+    const uint32_t y1 = (uint32_t)p1;
+    const uint32_t y2 = (uint32_t)(p0 >> 32) ^ x[3] ^ k1;
+    const uint32_t y3 = (uint32_t)p0;
+    x[0] = y0;
+    x[1] = y1;
+    x[2] = y2;
+    x[3] = y3;
+  }
+  for (int q = 0; q < 4; ++q) out[q] = x[q];
+}
+
+// 16 standard normals for one site and step: Philox counters (site, step low word, step
+// high word, q) for q = 0..3 under the seed; each output word w gives the uniform
+// u = (floor(w / 2^8) + 1/2) / 2^24 in (0, 1), and consecutive pairs (u_a, u_b) give
+// sqrt(-2 ln u_a) (cos 2 pi u_b, sin 2 pi u_b) (Box-Muller).
+void site_normals(const uint32_t seed[2], int64_t step, long site, double z[16]) {
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t ctr[4] = {(uint32_t)site, (uint32_t)((uint64_t)step & 0xffffffffu),
+                             (uint32_t)((uint64_t)step >> 32), (uint32_t)q};
+    uint32_t w[4];
+    philox4x32_10(ctr, seed, w);
+    double u[4];
+    for (int t = 0; t < 4; ++t) u[t] = ((double)(w[t] >> 8) + 0.5) / 16777216.0;
+    for (int t = 0; t < 2; ++t) {
+      const double r = std::sqrt(-2.0 * std::log(u[2 * t]));
+      const double th = 2.0 * M_PI * u[2 * t + 1];
+      z[4 * q + 2 * t] = r * std::cos(th);
+      z[4 * q + 2 * t + 1] = r * std::sin(th);
+    }
+  }
+}
+
+// The moment basis: e_k(c) for k = 0..18, polynomials of the velocity c: density, momentum,
+// bulk and shear stresses, then nine kinetic ("ghost") modes.  Orthogonal under the weights:
+// sum_i w_i e_k(c_i) e_l(c_i) = b_k delta_kl.
+double mode_poly(int k, const int c[3]) {
+  const double x = c[0], y = c[1], z = c[2], c2 = x * x + y * y + z * z;
+  switch (k) {
+    case 0: return 1.0;
+    case 1: return x;
+    case 2: return y;
+    case 3: return z;
+    case 4: return c2 - 1.0;
+    case 5: return 3.0 * x * x - c2;
+    case 6: return y * y - z * z;
+    case 7: return x * y;
+    case 8: return y * z;
+    case 9: return z * x;
+    case 10: return (3.0 * c2 - 5.0) * x;
+    case 11: return (3.0 * c2 - 5.0) * y;
+    case 12: return (3.0 * c2 - 5.0) * z;
+    case 13: return (y * y - z * z) * x;
+    case 14: return (z * z - x * x) * y;
+    case 15: return (x * x - y * y) * z;
+    case 16: return 3.0 * c2 * c2 - 6.0 * c2 + 1.0;
+    case 17: return (2.0 * c2 - 3.0) * (3.0 * x * x - c2);
+    default: return (2.0 * c2 - 3.0) * (y * y - z * z);
+  }
+}
+
+double mode_norm(int k) {
+  static double b[19] = {-1.0};
+  if (b[0] < 0.0)
+    for (int q = 0; q < 19; ++q) {
+      double acc = 0.0;
+      for (int i = 0; i < 19; ++i) acc += WV[i] * mode_poly(q, CV[i]) * mode_poly(q, CV[i]);
+      b[q] = acc;
+    }
+  return b[k];
+}
+
+// Noise added to the post-collision populations at one site:
+//   xi_i = w_i sum_{k=4..18} e_k(c_i) phi_k z_{k-4} / b_k,
+//   phi_k = sqrt(mu b_k (1 - (1 - omega)^2)),  mu = 3 rho kT.
+template <class T>
+void site_noise(double kT, T tau, T rho, const uint32_t seed[2], int64_t step, long site, T xi[19]) {
+  double z[16];
+  site_normals(seed, step, site, z);
+  const T omega = T(1.0) / tau;
+  const T g = T(1.0) - omega;
+  const T amp2 = T(3.0 * kT) * rho * (T(1.0) - g * g);
+  for (int i = 0; i < 19; ++i) {
+    T acc = T(0.0);
+    for (int k = 4; k < 19; ++k) {
+      const double b = mode_norm(k);
+      acc += T(mode_poly(k, CV[i]) * z[k - 4]) * sqrtT(amp2 * T(b)) / T(b);
+    }
+    xi[i] = T(WV[i]) * acc;
   }
 }
 
@@ -395,6 +514,13 @@ void coupled_step(const Model<T>& m, State<T>& s, std::vector<T>& scratch_post) 
     for (int i = 0; i < 19; ++i) gin[i] = s.g[i * S + x];
     for (int c = 0; c < 3; ++c) F[c] = Ftot[c * S + x];
     collide_node(m.tau, m.rho0, gin, F, gout);
+    if (m.kT > 0.0) {
+      T rho = m.rho0;
+      for (int i = 0; i < 19; ++i) rho += gin[i];
+      T xi[19];
+      site_noise(m.kT, m.tau, rho, m.seed, s.step, x, xi);
+      for (int i = 0; i < 19; ++i) gout[i] += xi[i];
+    }
     for (int i = 0; i < 19; ++i) scratch_post[i * S + x] = gout[i];
   }
   stream(m, scratch_post, s.g);
@@ -404,6 +530,7 @@ void coupled_step(const Model<T>& m, State<T>& s, std::vector<T>& scratch_post) 
     s.V[k] = s.V[k] + (Fff[k] + Fc[k]) / m.mass;
     s.X[k] = s.X[k] + s.V[k];
   }
+  s.step++;
 }
 
 }  // namespace
@@ -422,6 +549,9 @@ struct or_params {
   int32_t bf_kind;   // 0 none, 1 Kolmogorov sin(2 pi y / ny), 2 sign(y + 1/2 - ny/2), 3 field
   int32_t pad;
   double tau, rho0, gamma, mass, k_tether, k_bond, r0_bond, lj_eps, lj_sigma, lj_rc, bf_amp;
+  double kT;          // thermal energy of the noise (0: none)
+  uint32_t seed[2];   // Philox key
+  int64_t step0;      // step index of the input state (counts the noise)
 };
 
 }  // extern "C"
@@ -466,6 +596,9 @@ void build_model(const or_params* p, const double* X0, const int32_t* bonds, con
   m.lj_sigma = T(p->lj_sigma);
   m.lj_rc = T(p->lj_rc);
   m.lj_exclude_bonded = p->lj_exclude_bonded;
+  m.kT = p->kT;
+  m.seed[0] = p->seed[0];
+  m.seed[1] = p->seed[1];
   m.n_atoms = p->n_atoms;
   m.n_bonds = p->n_bonds;
   m.bond_i.resize(p->n_bonds);
@@ -488,6 +621,7 @@ int run_impl(const or_params* p, double* g, double* X, double* V, const double* 
   Model<T> m;
   build_model<T>(p, X0, bonds, field, m);
   State<T> s;
+  s.step = p->step0;
   s.g.resize(19 * m.S);
   s.X.resize(3 * (size_t)m.n_atoms);
   s.V.resize(3 * (size_t)m.n_atoms);
@@ -509,6 +643,27 @@ int run_impl(const or_params* p, double* g, double* X, double* V, const double* 
 }  // namespace
 
 extern "C" {
+
+void or_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
+  philox4x32_10(ctr, key, out);
+}
+
+void or_site_normals(const uint32_t* seed, int64_t step, int64_t site, double* z) {
+  site_normals(seed, step, (long)site, z);
+}
+
+// e[k * 19 + i] = e_k(c_i), b[k] = sum_i w_i e_k(c_i)^2
+void or_mode_basis(double* e, double* b) {
+  for (int k = 0; k < 19; ++k) {
+    for (int i = 0; i < 19; ++i) e[k * 19 + i] = mode_poly(k, CV[i]);
+    b[k] = mode_norm(k);
+  }
+}
+
+void or_site_noise(double kT, double tau, double rho, const uint32_t* seed, int64_t step, int64_t site,
+                   double* xi) {
+  site_noise(kT, tau, rho, seed, step, (long)site, xi);
+}
 
 void or_velocity_set(int32_t* c, double* w) {
   for (int i = 0; i < 19; ++i) {
@@ -647,6 +802,7 @@ int or_loss_derivative(const or_params* p, const double* g, const double* X, con
     return 1;
   }
   State<Dual> s;
+  s.step = p->step0;
   s.g.resize(19 * m.S);
   s.X.resize(3 * (size_t)m.n_atoms);
   s.V.resize(3 * (size_t)m.n_atoms);
@@ -680,6 +836,7 @@ int or_step_sampled(const or_params* p, const double* g, const double* X, const 
   Model<double> m;
   build_model<double>(p, X0, bonds, field, m);
   State<double> s;
+  s.step = p->step0;
   s.g.assign(g, g + 19 * m.S);
   s.X.assign(X, X + 3 * (size_t)m.n_atoms);
   s.V.assign(V, V + 3 * (size_t)m.n_atoms);
@@ -695,6 +852,13 @@ int or_step_sampled(const or_params* p, const double* g, const double* X, const 
       for (int q = 0; q < 19; ++q) gin[q] = s.g[q * m.S + src];
       for (int c = 0; c < 3; ++c) F[c] = Ftot[c * m.S + src];
       collide_node(m.tau, m.rho0, gin, F, gout);
+      if (m.kT > 0.0) {
+        double rho = val(m.rho0);
+        for (int q = 0; q < 19; ++q) rho += gin[q];
+        double xi[19];
+        site_noise(m.kT, val(m.tau), rho, m.seed, s.step, src, xi);
+        gout[i] += xi[i];
+      }
       g_out[19 * k + i] = gout[i];
     }
   }

@@ -51,6 +51,9 @@ class OrParams(ctypes.Structure):
         ("lj_sigma", ctypes.c_double),
         ("lj_rc", ctypes.c_double),
         ("bf_amp", ctypes.c_double),
+        ("kT", ctypes.c_double),
+        ("seed", ctypes.c_uint32 * 2),
+        ("step0", ctypes.c_int64),
     ]
 
 
@@ -89,6 +92,12 @@ def lib():
         L.or_step_sampled.restype = ctypes.c_int
         L.or_loss.argtypes = [pp, dp, dp, dp, dp, ip, dp, dp, ctypes.c_int32, dp]
         L.or_loss.restype = ctypes.c_int
+        up = ctypes.POINTER(ctypes.c_uint32)
+        L.or_philox4x32_10.argtypes = [up, up, up]
+        L.or_site_normals.argtypes = [up, ctypes.c_int64, ctypes.c_int64, dp]
+        L.or_mode_basis.argtypes = [dp, dp]
+        L.or_site_noise.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, up,
+                                    ctypes.c_int64, ctypes.c_int64, dp]
         _lib = L
     return _lib
 
@@ -117,7 +126,7 @@ def i32(a):
 
 def make_params(L, tau, rho0=1.0, gamma=0.0, mass=1.0, k_tether=0.0, k_bond=0.0, r0_bond=1.0,
                 lj_eps=0.0, lj_sigma=1.0, lj_rc=2.5, lj_exclude_bonded=0, bf_kind=0, bf_amp=0.0,
-                n_atoms=0, n_bonds=0) -> OrParams:
+                n_atoms=0, n_bonds=0, kT=0.0, seed=0, step0=0) -> OrParams:
     p = OrParams()
     Ls = (L, L, L) if np.isscalar(L) else tuple(L)
     for a in range(3):
@@ -127,13 +136,17 @@ def make_params(L, tau, rho0=1.0, gamma=0.0, mass=1.0, k_tether=0.0, k_bond=0.0,
     p.tau, p.rho0, p.gamma, p.mass = float(tau), float(rho0), float(gamma), float(mass)
     p.k_tether, p.k_bond, p.r0_bond = float(k_tether), float(k_bond), float(r0_bond)
     p.lj_eps, p.lj_sigma, p.lj_rc, p.bf_amp = float(lj_eps), float(lj_sigma), float(lj_rc), float(bf_amp)
+    p.kT = float(kT)
+    p.seed[0], p.seed[1] = int(seed) & 0xffffffff, (int(seed) >> 32) & 0xffffffff
+    p.step0 = int(step0)
     return p
 
 
 def params_from_workload(w) -> OrParams:
     return make_params(w.L, w.tau, w.rho0, w.gamma, w.mass, w.k_tether, w.k_bond, w.r0_bond,
                        w.lj_eps, w.lj_sigma, w.lj_rc, w.lj_exclude_bonded, w.bf_kind, w.bf_amp,
-                       n_atoms=w.n_atoms, n_bonds=len(w.bonds))
+                       n_atoms=w.n_atoms, n_bonds=len(w.bonds), kT=getattr(w, "kT", 0.0),
+                       seed=getattr(w, "noise_seed", 0))
 
 
 def n_sites(p: OrParams) -> int:
@@ -273,6 +286,44 @@ def loss(p: OrParams, g, X, V, bonds, field, D, n_steps):
     if rc != 0:
         raise RuntimeError("oracle loss failed (%d)" % rc)
     return out.value
+
+
+def _u32(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.uint32))
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 of a 4-word counter under a 2-word key (four uint32)."""
+    c, cp = _u32(ctr)
+    k, kp = _u32(key)
+    out, op = _u32(np.zeros(4))
+    lib().or_philox4x32_10(cp, kp, op)
+    return out
+
+
+def site_normals(seed, step, site):
+    """The 16 standard normals of one site and step."""
+    k, kp = _u32([seed & 0xffffffff, (seed >> 32) & 0xffffffff])
+    z = np.zeros(16)
+    lib().or_site_normals(kp, int(step), int(site), _d(z))
+    return z
+
+
+def mode_basis():
+    """(e [19 modes, 19 velocities], b [19]) of the orthogonal moment basis."""
+    e = np.zeros((19, 19))
+    b = np.zeros(19)
+    lib().or_mode_basis(_d(e), _d(b))
+    return e, b
+
+
+def site_noise(kT, tau, rho, seed, step, site):
+    """The thermal noise xi [19] added after the collision at one site."""
+    k, kp = _u32([seed & 0xffffffff, (seed >> 32) & 0xffffffff])
+    xi = np.zeros(19)
+    lib().or_site_noise(float(kT), float(tau), float(rho), kp, int(step), int(site), _d(xi))
+    return xi
 
 
 def rest_state(p: OrParams):
