@@ -98,6 +98,9 @@ typedef struct {
   int32_t bf_kind;           /* lb_body_force */
   float bf_amp;
   uint32_t flags;            /* LB_FLAG_* */
+  float kT;                  /* thermal energy of the fluctuating-LB noise on the non-conserved
+                                modes (Section 2.2, the xi_i of Eq. 1's source term); 0 = off */
+  uint32_t seed[2];          /* key of the counter-based (Philox4x32-10) noise generator */
 } lb_params;
 
 /* The 19 lattice velocities c[i][0..2] and weights w[i] in the library's ordering:

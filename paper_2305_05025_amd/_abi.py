@@ -42,6 +42,8 @@ class lb_params(ctypes.Structure):
         ("bf_kind", ctypes.c_int32),
         ("bf_amp", ctypes.c_float),
         ("flags", ctypes.c_uint32),
+        ("kT", ctypes.c_float),
+        ("seed", ctypes.c_uint32 * 2),
     ]
 
 

@@ -18,7 +18,7 @@ STORAGE = {"f32": A.LB_STORE_F32, "f16": A.LB_STORE_F16, "bf16": A.LB_STORE_BF16
 
 def make_params(L, tau, rho0=1.0, storage="f32", n_atoms=0, mass=1.0, gamma=0.0, k_tether=0.0,
                 n_bonds=0, k_bond=0.0, r0_bond=1.0, lj_eps=0.0, lj_sigma=1.0, lj_rc=2.5,
-                lj_exclude_bonded=0, bf_kind=0, bf_amp=0.0, flags=0) -> A.lb_params:
+                lj_exclude_bonded=0, bf_kind=0, bf_amp=0.0, flags=0, kT=0.0, seed=0) -> A.lb_params:
     p = A.lb_params()
     Ls = (L, L, L) if isinstance(L, int) else tuple(L)
     for k in range(3):
@@ -30,13 +30,16 @@ def make_params(L, tau, rho0=1.0, storage="f32", n_atoms=0, mass=1.0, gamma=0.0,
     p.lj_eps, p.lj_sigma, p.lj_rc = float(lj_eps), float(lj_sigma), float(lj_rc)
     p.lj_exclude_bonded, p.bf_kind, p.bf_amp = int(lj_exclude_bonded), int(bf_kind), float(bf_amp)
     p.flags = int(flags)
+    p.kT = float(kT)
+    p.seed[0], p.seed[1] = int(seed) & 0xffffffff, (int(seed) >> 32) & 0xffffffff
     return p
 
 
 def params_from_workload(w, storage="f32", flags=0) -> A.lb_params:
     return make_params(w.L, w.tau, w.rho0, storage, w.n_atoms, w.mass, w.gamma, w.k_tether,
                        len(w.bonds), w.k_bond, w.r0_bond, w.lj_eps, w.lj_sigma, w.lj_rc,
-                       w.lj_exclude_bonded, w.bf_kind, w.bf_amp, flags)
+                       w.lj_exclude_bonded, w.bf_kind, w.bf_amp, flags,
+                       getattr(w, "kT", 0.0), getattr(w, "noise_seed", 0))
 
 
 def _aligned_workspace(nbytes: int, device) -> tuple:

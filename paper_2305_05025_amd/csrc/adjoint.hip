@@ -21,6 +21,9 @@
 //   coupling velocity (u_c = (j + F_ext/2)/rho at nodes, from h):
 //     l_uc(x) = sum_a W(X_a, x) l_U,a;  a_i += -u_c.l_uc/rho + c_i . l_uc/rho
 //   and dL/dF_ext(x) += phi(x) + l_uc(x) / (2 rho)
+//   thermal noise (kT > 0): out_i += A(rho, omega) p_i with A = sqrt(3 rho kT (2 omega -
+//     omega^2)) and p_i the step's fixed noise pattern, so a_i += (sum_j mu_j p_j) A/(2 rho)
+//     and dL/domega += (sum_j mu_j p_j) A (1 - omega)/(2 omega - omega^2)
 //   streaming (pull): Lam^n_i(x - c_i) = a_i(x), a push with one store per (i, x).
 // The state of each step is recomputed from checkpoints by the host (lb_backward).
 #include "atoms_common.h"
@@ -48,6 +51,9 @@ struct AdjLatticeArgs {
   double* dom_part;       // per workgroup: partial dL/domega
   const int* hot_list;
   const int* hot_count;
+  float kT;               // thermal noise of the forward step (0: none)
+  uint32_t seed0, seed1;
+  int64_t step;
 };
 
 // Adjoint of the collision at one site: from mu (adjoint of the output) and the site's
@@ -121,8 +127,24 @@ __device__ __forceinline__ void adj_site(const AdjLatticeArgs& a, int s, bool ho
     Fy += a.fcoup[a.plane + s];
     Fz += a.fcoup[2 * a.plane + s];
   }
+  // the noise does not depend on F, so only the sweep needs its terms
+  const bool noise = sweep && a.kT > 0.f;
+  float mp = 0.f;   // sum_i mu_i p_i of the noise pattern
+  if (noise) {
+    float pn[19];
+    noise_pattern(a.seed0, a.seed1, a.step, s, pn);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) mp += mu[i] * pn[i];
+  }
   float phx, phy, phz, rho, jx, jy, jz;
   collide_adjoint(mu, g, Fx, Fy, Fz, a.rho0, a.omega, a.pref, phx, phy, phz, dom, rho, jx, jy, jz);
+  if (noise) {
+    const float A = noise_amp(a.kT, rho, a.omega);
+    const float lr = mp * A / (2.0f * rho);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) mu[i] += lr;
+    dom += mp * A * (1.0f - a.omega) / (a.omega * (2.0f - a.omega));
+  }
   if (!sweep) {
     a.phi[s] = phx;
     a.phi[a.plane + s] = phy;
@@ -405,6 +427,10 @@ static AdjLatticeArgs lattice_args(lb_ctx* c, const AdjointBuffers& b) {
   a.dom_part = b.dom_part;
   a.hot_list = (const int*)(c->ws + c->lay.occ_tiles[par]);
   a.hot_count = (const int*)(c->ws + c->lay.occ_count[par]) + 1;
+  a.kT = c->p.kT;
+  a.seed0 = c->p.seed[0];
+  a.seed1 = c->p.seed[1];
+  a.step = c->step;
   return a;
 }
 

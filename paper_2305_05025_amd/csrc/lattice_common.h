@@ -119,6 +119,115 @@ __device__ __forceinline__ bool collide(float g[19], float Fx, float Fy, float F
   return __builtin_isfinite(drho + jx + jy + jz);
 }
 
+// ---- thermal noise (fluctuating LB) -------------------------------------------------------
+// The source term of Eq. 1 carries, besides the forces, Gaussian noise xi_i on the moments
+// the collision does not conserve (Section 2.2).  xi_i = w_i A sum_{k=4..18} e_k(c_i) z_k /
+// sqrt(b_k): e_k the orthogonal D3Q19 moment basis (density, momentum, stresses, kinetic
+// modes), b_k = sum_i w_i e_k(c_i)^2, A = sqrt(3 rho kT (1 - (1 - omega)^2)) with rho the
+// local density before the collision, z_k standard normals.  Each non-conserved mode then
+// receives variance 3 rho kT b_k (1 - (1 - omega)^2), which keeps it at its equilibrium
+// fluctuation under the relaxation factor 1 - omega; mass and momentum get none.
+//
+// Normals: Philox4x32-10 (a counter-based generator) keyed by the seed, counter (site, step
+// low word, step high word, q) for q = 0..3; each 32-bit output w gives the uniform
+// ((w >> 8) + 1/2) 2^-24, and pairs of uniforms give Box-Muller normals.
+
+__device__ __forceinline__ void philox4x32_10(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                              uint32_t k0, uint32_t k1, uint32_t out[4]) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t hi0 = __umulhi(0xD2511F53u, x0), lo0 = 0xD2511F53u * x0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, x2), lo1 = 0xCD9E8D57u * x2;
+    const uint32_t y0 = hi1 ^ x1 ^ k0, y2 = hi0 ^ x3 ^ k1;
+    x0 = y0;
+    x1 = lo1;
+    x2 = y2;
+    x3 = lo0;
+  }
+  out[0] = x0;
+  out[1] = x1;
+  out[2] = x2;
+  out[3] = x3;
+}
+
+// polynomial k of the moment basis at velocity (cx, cy, cz) (folded at compile time)
+constexpr float mode_poly(int k, int cx, int cy, int cz) {
+  const float x = (float)cx, y = (float)cy, z = (float)cz, c2 = x * x + y * y + z * z;
+  return k == 4    ? c2 - 1.f
+         : k == 5  ? 3.f * x * x - c2
+         : k == 6  ? y * y - z * z
+         : k == 7  ? x * y
+         : k == 8  ? y * z
+         : k == 9  ? z * x
+         : k == 10 ? (3.f * c2 - 5.f) * x
+         : k == 11 ? (3.f * c2 - 5.f) * y
+         : k == 12 ? (3.f * c2 - 5.f) * z
+         : k == 13 ? (y * y - z * z) * x
+         : k == 14 ? (z * z - x * x) * y
+         : k == 15 ? (x * x - y * y) * z
+         : k == 16 ? 3.f * c2 * c2 - 6.f * c2 + 1.f
+         : k == 17 ? (2.f * c2 - 3.f) * (3.f * x * x - c2)
+                   : (2.f * c2 - 3.f) * (y * y - z * z);
+}
+
+constexpr float mode_inv_sqrt_norm(int k) {
+  // 1 / sqrt(b_k), b_k = sum_i w_i e_k(c_i)^2 for k = 4 .. 18
+  return k == 4 || k == 10 || k == 11 || k == 12 ? 1.2247448713915890f     // b = 2/3
+         : k == 5 || k == 17                     ? 0.8660254037844386f     // b = 4/3
+         : k == 6 || k == 18                     ? 1.5f                    // b = 4/9
+         : k >= 7 && k <= 9                      ? 3.0f                    // b = 1/9
+         : k >= 13 && k <= 15                    ? 2.1213203435596424f     // b = 2/9
+                                                 : 0.7071067811865476f;    // b = 2 (k = 16)
+}
+
+// the 16 normals of one site and step
+__device__ __forceinline__ void site_normals(uint32_t seed0, uint32_t seed1, int64_t step, int site,
+                                             float z[16]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    uint32_t w[4];
+    philox4x32_10((uint32_t)site, (uint32_t)((uint64_t)step & 0xffffffffu), (uint32_t)((uint64_t)step >> 32),
+                  (uint32_t)q, seed0, seed1, w);
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const float ua = ((float)(w[2 * t] >> 8) + 0.5f) * (1.0f / 16777216.0f);
+      const float ub = ((float)(w[2 * t + 1] >> 8) + 0.5f) * (1.0f / 16777216.0f);
+      const float r = sqrtf(-2.0f * logf(ua));
+      float sn, cs;
+      sincospif(2.0f * ub, &sn, &cs);
+      z[4 * q + 2 * t] = r * cs;
+      z[4 * q + 2 * t + 1] = r * sn;
+    }
+  }
+}
+
+// xi_i / A: the unit-amplitude noise pattern of one site and step
+__device__ __forceinline__ void noise_pattern(uint32_t seed0, uint32_t seed1, int64_t step, int site,
+                                              float p[19]) {
+  float z[16];
+  site_normals(seed0, seed1, step, site, z);
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    float acc = 0.f;
+#pragma unroll
+    for (int k = 4; k < 19; ++k) {
+      const float e = mode_poly(k, CX[i], CY[i], CZ[i]) * mode_inv_sqrt_norm(k);
+      if (e != 0.f) acc += e * z[k - 4];
+    }
+    p[i] = WQ[i] * acc;
+  }
+}
+
+// noise amplitude A(rho, omega)
+__device__ __forceinline__ float noise_amp(float kT, float rho, float omega) {
+  const float g = 1.0f - omega;
+  return sqrtf(3.0f * rho * kT * (1.0f - g * g));
+}
+
 __device__ __forceinline__ void external_force(int bf_kind, const float* tab, const float* field,
                                                long plane, int s, int y, float& Fx, float& Fy,
                                                float& Fz) {

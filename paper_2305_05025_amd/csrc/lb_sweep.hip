@@ -34,9 +34,12 @@ struct SweepArgs {
   float* fcoup;                // [3][plane] spread coupling force (hot tiles only)
   int* base_count;             // [plane] cleared here for hot tiles
   uint32_t* err;
+  float kT;                    // thermal noise (NOISE instances only)
+  uint32_t seed0, seed1;
+  int64_t step;
 };
 
-template <int ST>
+template <int ST, bool NOISE>
 __device__ __forceinline__ void sweep_site(const SweepArgs& a, int s, bool hot) {
   using T = typename Store<ST>::T;
   const int x = s % a.nx;
@@ -59,19 +62,32 @@ __device__ __forceinline__ void sweep_site(const SweepArgs& a, int s, bool hot) 
     fc[2 * a.plane + s] = 0.f;
     a.base_count[s] = 0;
   }
+  float rho = 0.f;
+  if constexpr (NOISE) {
+    rho = a.rho0;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) rho += g[i];
+  }
   if (!collide(g, Fx, Fy, Fz, a.rho0, a.omega, a.pref)) atomicOr(a.err, kErrNonFinite);
+  if constexpr (NOISE) {
+    float xi[19];
+    noise_pattern(a.seed0, a.seed1, a.step, s, xi);
+    const float A = noise_amp(a.kT, rho, a.omega);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) g[i] += A * xi[i];
+  }
   T* out = reinterpret_cast<T*>(a.fout);
 #pragma unroll
   for (int i = 0; i < 19; ++i) Store<ST>::st(out + (size_t)i * a.plane + s, g[i]);
 }
 
 // One thread per site, in site order.
-template <int ST>
+template <int ST, bool NOISE>
 __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
   const int s = blockIdx.x * kSweepBlock + threadIdx.x;
   if (s >= a.S) return;
   const bool hot = a.tile_flag != nullptr && a.tile_flag[s >> kTileShift] != 0u;
-  sweep_site<ST>(a, s, hot);
+  sweep_site<ST, NOISE>(a, s, hot);
 }
 
 // ---- readback -------------------------------------------------------------------------------
@@ -305,11 +321,25 @@ hipError_t launch_sweep(lb_ctx* c, const void* fin, void* fout, hipStream_t st) 
   a.fcoup = (float*)(c->ws + c->lay.fcoup[par]);
   a.base_count = (int*)(c->ws + c->lay.base_count[par]);
   a.err = (uint32_t*)(c->ws + c->lay.err);
+  a.kT = c->p.kT;
+  a.seed0 = c->p.seed[0];
+  a.seed1 = c->p.seed[1];
+  a.step = c->step;
   const dim3 block(kSweepBlock), grid(g.nblocks);
+  const bool noise = c->p.kT > 0.0f;
   switch (c->p.storage) {
-    case LB_STORE_F32: hipLaunchKernelGGL(k_sweep<LB_STORE_F32>, grid, block, 0, st, a); break;
-    case LB_STORE_F16: hipLaunchKernelGGL(k_sweep<LB_STORE_F16>, grid, block, 0, st, a); break;
-    default: hipLaunchKernelGGL(k_sweep<LB_STORE_BF16>, grid, block, 0, st, a); break;
+    case LB_STORE_F32:
+      if (noise) hipLaunchKernelGGL((k_sweep<LB_STORE_F32, true>), grid, block, 0, st, a);
+      else hipLaunchKernelGGL((k_sweep<LB_STORE_F32, false>), grid, block, 0, st, a);
+      break;
+    case LB_STORE_F16:
+      if (noise) hipLaunchKernelGGL((k_sweep<LB_STORE_F16, true>), grid, block, 0, st, a);
+      else hipLaunchKernelGGL((k_sweep<LB_STORE_F16, false>), grid, block, 0, st, a);
+      break;
+    default:
+      if (noise) hipLaunchKernelGGL((k_sweep<LB_STORE_BF16, true>), grid, block, 0, st, a);
+      else hipLaunchKernelGGL((k_sweep<LB_STORE_BF16, false>), grid, block, 0, st, a);
+      break;
   }
   return hipGetLastError();
 }

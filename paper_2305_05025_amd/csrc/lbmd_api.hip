@@ -104,6 +104,7 @@ static std::string validate(const lb_params* p) {
   if (!finite(p->tau) || !(p->tau > 0.5f)) return "tau must be finite and > 0.5 (nu = (tau - 1/2)/3 > 0)";
   if (p->flags & ~(LB_FLAG_CHECK_FINITE | LB_FLAG_SINGLE_STREAM))
     return "flags holds an unknown bit";
+  if (!finite(p->kT) || p->kT < 0.0f) return "kT must be finite and >= 0";
   if (!finite(p->rho0) || !(p->rho0 > 0.0f)) return "rho0 must be finite and > 0";
   if (p->storage < LB_STORE_F32 || p->storage > LB_STORE_BF16) return "unknown storage format";
   if (p->bf_kind < LB_BF_NONE || p->bf_kind > LB_BF_FIELD) return "unknown body-force kind";

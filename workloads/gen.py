@@ -66,6 +66,8 @@ class Workload:
     body_force: Optional[np.ndarray]    # [3, nz, ny, nx] float32 (BF_FIELD only)
     target_shift: Optional[np.ndarray]  # [3] float32: loss target displacement D
     seed: int
+    kT: float = 0.0                     # thermal energy of the lattice noise (0: athermal)
+    noise_seed: int = 0                 # key of the counter-based noise generator
 
     @property
     def n_atoms(self) -> int:
@@ -79,7 +81,8 @@ class Workload:
         """Scalar parameters as a plain dict (no arrays)."""
         return {k: getattr(self, k) for k in (
             "L", "tau", "rho0", "gamma", "mass", "k_tether", "k_bond", "r0_bond",
-            "lj_eps", "lj_sigma", "lj_rc", "lj_exclude_bonded", "bf_kind", "bf_amp")}
+            "lj_eps", "lj_sigma", "lj_rc", "lj_exclude_bonded", "bf_kind", "bf_amp", "kT",
+            "noise_seed")}
 
 
 # ---------------------------------------------------------------------------------------
