@@ -187,6 +187,16 @@ def run(args):
             storage_ms[fmt] = round(time_steps(s2, args.steps, args.warmup)[0], 5)
             s2.close()
             log("storage %s: %.4f ms/step" % (fmt, storage_ms[fmt]))
+    # the thermal (fluctuating) lattice: the same workload with noise on the non-conserved
+    # modes at kT = 1e-4 (thermal velocity 0.01 per component)
+    thermal = None
+    if args.formats:
+        import dataclasses
+        wt = dataclasses.replace(w, kT=1e-4, noise_seed=7)
+        s3 = CoupledLB.from_workload(wt, storage=args.storage, device=dev, flags=flags)
+        thermal = {"kT": 1e-4, "ms_per_step": round(time_steps(s3, args.steps, args.warmup)[0], 5)}
+        s3.close()
+        log("thermal: %s" % thermal)
     adj = None
     if args.adjoint:
         adj = adjoint_ratio(dev)
@@ -233,6 +243,7 @@ def run(args):
         "storage_ms_per_step": storage_ms,
         "f16_speedup": (round(storage_ms["f32"] / storage_ms["f16"], 4)
                         if "f32" in storage_ms and "f16" in storage_ms else None),
+        "thermal": thermal,
         "adjoint_forward_ratio": adj["ratio"] if adj else None,
         "adjoint": adj,
     }
@@ -266,7 +277,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--no-formats", dest="formats", action="store_false",
-                    help="skip the FP16/BF16 (or FP32) storage timings")
+                    help="skip the FP16/BF16 (or FP32) storage and thermal-noise timings")
     ap.add_argument("--no-adjoint", dest="adjoint", action="store_false",
                     help="skip the adjoint/forward timing on the differentiation workload")
     ap.add_argument("--single-stream", action="store_true",
