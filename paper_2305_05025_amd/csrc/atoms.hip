@@ -47,7 +47,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
   const long t = blockIdx.x * 256L + threadIdx.x;
   if (t < a.ncell) a.cell_count[t] = 0;
   if (t < a.ntiles) a.tile_flag[t] = 0u;
-  if (t < 2) a.occ_count[t] = 0;
+  if (t < 3) a.occ_count[t] = 0;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -80,6 +80,50 @@ __device__ __forceinline__ void compact_block(bool keep, int item, int* list, in
   int off = block_base;
   for (int w = 0; w < wid; ++w) off += wave_n[w];
   if (keep) list[off + __popcll(m & ((1ull << lane) - 1ull))] = item;
+}
+
+// The flagged nodes inside the flagged tiles.  Each workgroup takes a contiguous range of the
+// tile list and each of its wavefronts a contiguous quarter of that, so the list keeps the
+// tiles' order within a workgroup; the workgroup counts its flagged nodes, reserves room with
+// a single counter atomic, then writes them in a second pass over the same tiles.
+struct NodeCompactArgs {
+  int S;
+  const int* occ_tiles;
+  const uint8_t* node_flag;
+  int* node_list;
+  int* occ_count;    // [1] tiles (in), [2] nodes (out)
+};
+
+__global__ __launch_bounds__(256) void k_node_compact(NodeCompactArgs a) {
+  __shared__ int wave_n[4];
+  __shared__ int block_base;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int ntile = a.occ_count[1];
+  const int chunk = (ntile + (int)gridDim.x - 1) / (int)gridDim.x;
+  const int q = (chunk + 3) / 4;
+  const int t0 = min((int)blockIdx.x * chunk + wid * q, ntile);
+  const int t1 = min(min(t0 + q, (int)(blockIdx.x + 1) * chunk), ntile);
+  int n = 0;
+  for (int k = t0; k < t1; ++k) {
+    const int s = (a.occ_tiles[k] << kTileShift) + lane;
+    n += __popcll(__ballot(s < a.S && a.node_flag[s] != 0));
+  }
+  if (lane == 0) wave_n[wid] = n;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int tot = wave_n[0] + wave_n[1] + wave_n[2] + wave_n[3];
+    block_base = tot ? atomicAdd(a.occ_count + 2, tot) : 0;
+  }
+  __syncthreads();
+  int off = block_base;
+  for (int w = 0; w < wid; ++w) off += wave_n[w];
+  for (int k = t0; k < t1; ++k) {
+    const int s = (a.occ_tiles[k] << kTileShift) + lane;
+    const bool keep = s < a.S && a.node_flag[s] != 0;
+    const unsigned long long m = __ballot(keep);
+    if (keep) a.node_list[off + __popcll(m & ((1ull << lane) - 1ull))] = s;
+    off += __popcll(m);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_compact(CompactArgs a) {
@@ -186,22 +230,18 @@ struct NodeArgs {
   int bf_kind;
   const float* fext_tab;
   const float* fext_field;
-  const int* occ_tiles;
-  const int* occ_count;   // [1]: number of flagged tiles
-  const uint8_t* node_flag;
+  const int* node_list;
+  const int* node_count;
   float* uc;   // [3][plane]
 };
 
-// one wavefront per flagged 64-site tile (persistent over the tile list), lane = site
+// one thread per flagged node (persistent over the node list)
 template <int ST>
 __global__ __launch_bounds__(256) void k_node_u(NodeArgs a) {
   using T = typename Store<ST>::T;
-  const int lane = threadIdx.x & 63;
-  const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6, nwave = gridDim.x * 4;
-  const int ntile = *a.occ_count;
-  for (int k = wave; k < ntile; k += nwave) {
-    const int s = (a.occ_tiles[k] << kTileShift) + lane;
-    if (s >= a.S || a.node_flag[s] == 0) continue;
+  const int n = *a.node_count;
+  for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+    const int s = a.node_list[k];
     const int x = s % a.nx;
     const int t = s / a.nx;
     const int y = t % a.ny;
@@ -275,8 +315,8 @@ struct SpreadArgs {
   int S;
   int n[3];
   long plane;
-  const int* occ_tiles;
-  const int* occ_count;
+  const int* node_list;
+  const int* node_count;
   uint8_t* node_flag;        // cleared here
   const int* base_count;
   const int* base_list;
@@ -286,16 +326,13 @@ struct SpreadArgs {
 };
 
 // The transpose of the interpolation: node x is corner delta of every atom whose base node
-// is x - delta; its share of that atom's -F_c is the same trilinear weight.  One wavefront
-// per flagged 64-site tile (persistent over the tile list), lane = site.
+// is x - delta; its share of that atom's -F_c is the same trilinear weight.  One thread per
+// flagged node (persistent over the node list).
 __global__ __launch_bounds__(256) void k_spread(SpreadArgs a) {
-  const int lane = threadIdx.x & 63;
   const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
-  const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6, nwave = gridDim.x * 4;
-  const int ntile = *a.occ_count;
-  for (int kt = wave; kt < ntile; kt += nwave) {
-    const int s = (a.occ_tiles[kt] << kTileShift) + lane;
-    if (s >= a.S || a.node_flag[s] == 0) continue;
+  const int n = *a.node_count;
+  for (int kn = blockIdx.x * 256 + threadIdx.x; kn < n; kn += gridDim.x * 256) {
+    const int s = a.node_list[kn];
     const int x = s % nx;
     const int t = s / nx;
     const int y = t % ny;
@@ -621,6 +658,15 @@ hipError_t launch_compact(lb_ctx* c) {
   a.occ_count = (int*)(c->ws + c->lay.occ_count[c->step & 1]);
   const long nb = (a.ncell + 255) / 256 + (a.ntiles + 255) / 256;
   hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(256), 0, c->astream, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  NodeCompactArgs b;
+  b.S = (int)c->geo.S;
+  b.occ_tiles = a.occ_tiles;
+  b.node_flag = (const uint8_t*)(c->ws + c->lay.node_flag);
+  b.node_list = (int*)(c->ws + c->lay.node_list[c->step & 1]);
+  b.occ_count = a.occ_count;
+  hipLaunchKernelGGL(k_node_compact, dim3(256), dim3(256), 0, c->astream, b);
   return hipGetLastError();
 }
 
@@ -667,11 +713,10 @@ hipError_t launch_node_u(lb_ctx* c) {
   a.bf_kind = c->p.bf_kind;
   a.fext_tab = (const float*)(c->ws + c->lay.fext_tab);
   a.fext_field = (const float*)(c->ws + c->lay.fext_field);
-  a.occ_tiles = (const int*)(c->ws + c->lay.occ_tiles[c->step & 1]);
-  a.occ_count = (const int*)(c->ws + c->lay.occ_count[c->step & 1]) + 1;
-  a.node_flag = (const uint8_t*)(c->ws + c->lay.node_flag);
+  a.node_list = (const int*)(c->ws + c->lay.node_list[c->step & 1]);
+  a.node_count = (const int*)(c->ws + c->lay.occ_count[c->step & 1]) + 2;
   a.uc = (float*)(c->ws + c->lay.uc);
-  const dim3 grid(persistent_grid(g.ntiles)), block(256);
+  const dim3 grid(node_grid(c)), block(256);
   switch (c->p.storage) {
     case LB_STORE_F32: hipLaunchKernelGGL(k_node_u<LB_STORE_F32>, grid, block, 0, c->stream, a); break;
     case LB_STORE_F16: hipLaunchKernelGGL(k_node_u<LB_STORE_F16>, grid, block, 0, c->stream, a); break;
@@ -706,15 +751,15 @@ hipError_t launch_spread(lb_ctx* c) {
   a.n[2] = c->geo.nz;
   a.plane = c->geo.plane;
   const int par = (int)(c->step & 1);
-  a.occ_tiles = (const int*)(c->ws + c->lay.occ_tiles[par]);
-  a.occ_count = (const int*)(c->ws + c->lay.occ_count[par]) + 1;
+  a.node_list = (const int*)(c->ws + c->lay.node_list[par]);
+  a.node_count = (const int*)(c->ws + c->lay.occ_count[par]) + 2;
   a.node_flag = (uint8_t*)(c->ws + c->lay.node_flag);
   a.base_count = (const int*)(c->ws + c->lay.base_count[par]);
   a.base_list = (const int*)(c->ws + c->lay.base_list[par]);
   a.atom_frac = (const float4*)(c->ws + c->lay.atom_frac);
   a.fc = (const float*)(c->ws + c->lay.fc);
   a.fcoup = (float*)(c->ws + c->lay.fcoup[par]);
-  hipLaunchKernelGGL(k_spread, dim3(persistent_grid(c->geo.ntiles)), dim3(256), 0, c->stream, a);
+  hipLaunchKernelGGL(k_spread, dim3(node_grid(c)), dim3(256), 0, c->stream, a);
   return hipGetLastError();
 }
 

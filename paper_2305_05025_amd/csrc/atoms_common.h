@@ -108,6 +108,14 @@ inline unsigned blocks8(long n, int per) { return (blocks(n, per) + 7u) & ~7u; }
 
 // persistent kernels: enough 4-wavefront workgroups for the items (one per wavefront), at
 // most 8 per CU
+// one thread per flagged node: enough workgroups for the most nodes there can be (8 per atom,
+// at most one per site), at most 2048
+inline unsigned node_grid(const lb_ctx* c) {
+  const long n = std::min(8L * c->p.n_atoms, (long)c->geo.S);
+  const long b = (n + 255) / 256;
+  return (unsigned)(b < 1 ? 1 : (b > 2048 ? 2048 : b));
+}
+
 inline unsigned persistent_grid(long nitems) {
   long b = (nitems + 3) / 4;
   if (b > 2048) b = 2048;

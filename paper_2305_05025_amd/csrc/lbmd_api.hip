@@ -67,6 +67,7 @@ Layout plan(const lb_params* p, const Geometry& g) {
   l.occ_cells = take(std::min((size_t)g.ncell, N) * 4);
   for (int k = 0; k < 2; ++k) {
     l.occ_tiles[k] = take(N ? (size_t)g.ntiles * 4 : 0);
+    l.node_list[k] = take(std::min(8 * N, (size_t)g.S) * 4);
     l.occ_count[k] = take(N ? 16 : 0);
   }
   l.fext_tab = take((size_t)g.ny * 4);

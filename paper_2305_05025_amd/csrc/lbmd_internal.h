@@ -45,7 +45,8 @@ struct Layout {
   size_t atom_frac;    // float4 [N]: stencil fractions of each atom
   size_t occ_cells;    // int32 [min(ncell, N)]: neighbour-list cells holding atoms this step
   size_t occ_tiles[2]; // int32 [ntiles]: flagged force tiles, by step parity
-  size_t occ_count[2]; // int32 [2] by step parity: lengths of the cell and tile lists
+  size_t node_list[2]; // int32 [min(8 N, S)]: flagged nodes (atom stencil nodes), by step parity
+  size_t occ_count[2]; // int32 [4] by step parity: lengths of the cell, tile and node lists
   size_t fext_tab;     // float [ny]   (Kolmogorov / sign-shear profile)
   size_t fext_field;   // float [3][plane] (caller field)
   size_t x0;           // float [N][3] anchors
@@ -121,7 +122,7 @@ hipError_t launch_store_i64(void* dst, int64_t v, hipStream_t s);
 // ---- kernel launchers (atoms.hip) ----
 hipError_t launch_prep(lb_ctx* c);
 hipError_t launch_bin_mark(lb_ctx* c);
-hipError_t launch_compact(lb_ctx* c);
+hipError_t launch_compact(lb_ctx* c);   // occupied cells, flagged tiles, then flagged nodes
 hipError_t launch_cell_sort(lb_ctx* c);
 hipError_t launch_node_u(lb_ctx* c);
 hipError_t launch_couple(lb_ctx* c);
