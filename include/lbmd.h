@@ -101,6 +101,10 @@ typedef struct {
   float kT;                  /* thermal energy of the fluctuating-LB noise on the non-conserved
                                 modes (Section 2.2, the xi_i of Eq. 1's source term); 0 = off */
   uint32_t seed[2];          /* key of the counter-based (Philox4x32-10) noise generator */
+  float coul_k;              /* implicit-solvent Coulomb between atoms (Section 2.2: direct sum,
+                                permittivity growing with r): U = coul_k q_i q_j / r^2 under the
+                                Lennard-Jones cut-off and exclusions; charges from
+                                lb_set_charges (zero until set); 0 = off */
 } lb_params;
 
 /* The 19 lattice velocities c[i][0..2] and weights w[i] in the library's ordering:
@@ -147,6 +151,11 @@ lb_status lb_read_fields(lb_ctx* c, float* rho, float* u, float* x_unwrapped, fl
  * at full FP32 precision (an unwrapped position x0 + d rounded to FP32 loses the low bits
  * of small displacements).  Asynchronous. */
 lb_status lb_read_displacement(lb_ctx* c, float* d);
+
+/* Atom charges q [N] (device, FP32) for the Coulomb term, copied into the context
+ * (asynchronous on its stream; the caller's buffer may be reused once the stream has passed
+ * this call).  Charges start at zero. */
+lb_status lb_set_charges(lb_ctx* c, const float* q);
 
 /* Raw populations of the current pre-collision state as float32 deviations g_i
  * [19][S] (device pointer), in the lb_velocity_set ordering.  Asynchronous. */

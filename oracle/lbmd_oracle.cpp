@@ -30,9 +30,11 @@
 //     one lattice step per atom step.
 //
 // The atom force field of the paper (CHARMM36 + implicit-solvent Coulomb) is replaced by
-// a stand-in: harmonic tethers to the initial positions, harmonic chain bonds and a
+// a stand-in: harmonic tethers to the initial positions, harmonic chain bonds, a
 // Lennard-Jones pair term truncated (not shifted) at r_c with minimum image, bonded pairs
-// optionally excluded.  Atom update: symplectic Euler, v += F/m then x += v (dt = 1).
+// optionally excluded, and the paper's implicit-solvent Coulomb term (direct summation with
+// a distance-dependent permittivity, i.e. one more 1/r: U = k_C q_i q_j / r^2) under the same
+// cut-off and exclusions.  Atom update: symplectic Euler, v += F/m then x += v (dt = 1).
 //
 // Populations are kept as deviations g_i = f_i - w_i rho0 (exactly the same scheme,
 // written around the rest state).  All arithmetic is in the template scalar T:
@@ -103,6 +105,8 @@ struct Model {
   int L[3];
   long S;
   T tau, rho0, gamma, mass, k_tether, k_bond, r0_bond, lj_eps, lj_sigma, lj_rc;
+  T coul_k;                                  // implicit-solvent Coulomb prefactor (0: off)
+  std::vector<T> charge;                     // per atom
   double kT;                                 // thermal energy (0: no noise)
   uint32_t seed[2];                          // Philox key
   int lj_exclude_bonded;
@@ -367,7 +371,37 @@ bool bonded(const Model<T>& m, int i, int j) {
   return false;
 }
 
-// Stand-in force field at positions X (unwrapped): tethers, bonds, truncated LJ.
+template <class T>
+bool pair_terms_on(const Model<T>& m) {
+  return val(m.lj_eps) != 0.0 || val(m.coul_k) != 0.0;
+}
+
+// |F_i| / |r| of the pair terms at squared distance r2 (force on i along r = X_i - X_j):
+//   LJ: 24 eps / r^2 [2 (s/r)^12 - (s/r)^6];  Coulomb with permittivity ~ r: 2 k_C q_i q_j / r^4
+template <class T>
+T pair_force_over_r(const Model<T>& m, int i, int j, T r2) {
+  T f = T(0.0);
+  if (val(m.lj_eps) != 0.0) {
+    T sr2 = m.lj_sigma * m.lj_sigma / r2;
+    T sr6 = sr2 * sr2 * sr2;
+    f += T(24.0) * m.lj_eps * (T(2.0) * sr6 * sr6 - sr6) / r2;
+  }
+  if (val(m.coul_k) != 0.0) f += T(2.0) * m.coul_k * m.charge[i] * m.charge[j] / (r2 * r2);
+  return f;
+}
+
+template <class T>
+T pair_energy(const Model<T>& m, int i, int j, T r2) {
+  T e = T(0.0);
+  if (val(m.lj_eps) != 0.0) {
+    T sr6 = (m.lj_sigma * m.lj_sigma / r2) * (m.lj_sigma * m.lj_sigma / r2) * (m.lj_sigma * m.lj_sigma / r2);
+    e += T(4.0) * m.lj_eps * (sr6 * sr6 - sr6);
+  }
+  if (val(m.coul_k) != 0.0) e += m.coul_k * m.charge[i] * m.charge[j] / r2;
+  return e;
+}
+
+// Stand-in force field at positions X (unwrapped): tethers, bonds, truncated pair terms.
 template <class T>
 void atom_forces(const Model<T>& m, const std::vector<T>& X, std::vector<T>& F) {
   const int N = m.n_atoms;
@@ -388,10 +422,10 @@ void atom_forces(const Model<T>& m, const std::vector<T>& X, std::vector<T>& F) 
       F[3 * j + c] -= fmag * r[c];
     }
   }
-  // Lennard-Jones: U = 4 eps [(s/r)^12 - (s/r)^6] for r < r_c, all pairs (brute force)
-  if (val(m.lj_eps) != 0.0) {
+  // Pair terms for r < r_c, all pairs (brute force): Lennard-Jones
+  // U = 4 eps [(s/r)^12 - (s/r)^6] and implicit-solvent Coulomb U = k_C q_i q_j / r^2
+  if (pair_terms_on(m)) {
     T rc2 = m.lj_rc * m.lj_rc;
-    T s2 = m.lj_sigma * m.lj_sigma;
     for (int i = 0; i < N; ++i)
       for (int j = i + 1; j < N; ++j) {
         T r[3];
@@ -399,10 +433,7 @@ void atom_forces(const Model<T>& m, const std::vector<T>& X, std::vector<T>& F) 
         T r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
         if (!(val(r2) < val(rc2))) continue;
         if (m.lj_exclude_bonded && bonded(m, i, j)) continue;
-        T sr2 = s2 / r2;
-        T sr6 = sr2 * sr2 * sr2;
-        // F_i = 24 eps / r^2 [2 (s/r)^12 - (s/r)^6] r_vec
-        T fmag = T(24.0) * m.lj_eps * (T(2.0) * sr6 * sr6 - sr6) / r2;
+        T fmag = pair_force_over_r(m, i, j, r2);
         for (int c = 0; c < 3; ++c) {
           F[3 * i + c] += fmag * r[c];
           F[3 * j + c] -= fmag * r[c];
@@ -426,7 +457,7 @@ void atom_force_one(const Model<T>& m, const std::vector<T>& X, int i, T F[3]) {
     T fmag = -m.k_bond * (rl - m.r0_bond) / rl;
     for (int c = 0; c < 3; ++c) F[c] += fmag * r[c];
   }
-  if (val(m.lj_eps) != 0.0)
+  if (pair_terms_on(m))
     for (int j = 0; j < m.n_atoms; ++j) {
       if (j == i) continue;
       T r[3];
@@ -434,9 +465,7 @@ void atom_force_one(const Model<T>& m, const std::vector<T>& X, int i, T F[3]) {
       T r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
       if (!(val(r2) < val(m.lj_rc * m.lj_rc))) continue;
       if (m.lj_exclude_bonded && bonded(m, i, j)) continue;
-      T sr2 = m.lj_sigma * m.lj_sigma / r2;
-      T sr6 = sr2 * sr2 * sr2;
-      T fmag = T(24.0) * m.lj_eps * (T(2.0) * sr6 * sr6 - sr6) / r2;
+      T fmag = pair_force_over_r(m, i, j, r2);
       for (int c = 0; c < 3; ++c) F[c] += fmag * r[c];
     }
 }
@@ -457,7 +486,7 @@ T atom_energy(const Model<T>& m, const std::vector<T>& X) {
     T rl = sqrtT(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
     E += T(0.5) * m.k_bond * (rl - m.r0_bond) * (rl - m.r0_bond);
   }
-  if (val(m.lj_eps) != 0.0)
+  if (pair_terms_on(m))
     for (int i = 0; i < N; ++i)
       for (int j = i + 1; j < N; ++j) {
         T r[3];
@@ -465,8 +494,7 @@ T atom_energy(const Model<T>& m, const std::vector<T>& X) {
         T r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
         if (!(val(r2) < val(m.lj_rc * m.lj_rc))) continue;
         if (m.lj_exclude_bonded && bonded(m, i, j)) continue;
-        T sr6 = (m.lj_sigma * m.lj_sigma / r2) * (m.lj_sigma * m.lj_sigma / r2) * (m.lj_sigma * m.lj_sigma / r2);
-        E += T(4.0) * m.lj_eps * (sr6 * sr6 - sr6);
+        E += pair_energy(m, i, j, r2);
       }
   return E;
 }
@@ -552,6 +580,8 @@ struct or_params {
   double kT;          // thermal energy of the noise (0: none)
   uint32_t seed[2];   // Philox key
   int64_t step0;      // step index of the input state (counts the noise)
+  double coul_k;      // implicit-solvent Coulomb prefactor k_C (0: off)
+  const double* charge;   // [n_atoms] charges, or NULL (all zero)
 };
 
 }  // extern "C"
@@ -597,6 +627,10 @@ void build_model(const or_params* p, const double* X0, const int32_t* bonds, con
   m.lj_rc = T(p->lj_rc);
   m.lj_exclude_bonded = p->lj_exclude_bonded;
   m.kT = p->kT;
+  m.coul_k = T(p->coul_k);
+  m.charge.assign((size_t)p->n_atoms, T(0.0));
+  if (p->charge)
+    for (int a = 0; a < p->n_atoms; ++a) m.charge[a] = T(p->charge[a]);
   m.seed[0] = p->seed[0];
   m.seed[1] = p->seed[1];
   m.n_atoms = p->n_atoms;

@@ -54,6 +54,8 @@ class OrParams(ctypes.Structure):
         ("kT", ctypes.c_double),
         ("seed", ctypes.c_uint32 * 2),
         ("step0", ctypes.c_int64),
+        ("coul_k", ctypes.c_double),
+        ("charge", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -126,7 +128,7 @@ def i32(a):
 
 def make_params(L, tau, rho0=1.0, gamma=0.0, mass=1.0, k_tether=0.0, k_bond=0.0, r0_bond=1.0,
                 lj_eps=0.0, lj_sigma=1.0, lj_rc=2.5, lj_exclude_bonded=0, bf_kind=0, bf_amp=0.0,
-                n_atoms=0, n_bonds=0, kT=0.0, seed=0, step0=0) -> OrParams:
+                n_atoms=0, n_bonds=0, kT=0.0, seed=0, step0=0, coul_k=0.0, charges=None) -> OrParams:
     p = OrParams()
     Ls = (L, L, L) if np.isscalar(L) else tuple(L)
     for a in range(3):
@@ -139,6 +141,12 @@ def make_params(L, tau, rho0=1.0, gamma=0.0, mass=1.0, k_tether=0.0, k_bond=0.0,
     p.kT = float(kT)
     p.seed[0], p.seed[1] = int(seed) & 0xffffffff, (int(seed) >> 32) & 0xffffffff
     p.step0 = int(step0)
+    p.coul_k = float(coul_k)
+    if charges is not None:
+        q = f64(charges).reshape(-1)
+        assert q.size == p.n_atoms
+        p._charges = q           # kept alive with the parameters
+        p.charge = _d(q)
     return p
 
 
@@ -146,7 +154,8 @@ def params_from_workload(w) -> OrParams:
     return make_params(w.L, w.tau, w.rho0, w.gamma, w.mass, w.k_tether, w.k_bond, w.r0_bond,
                        w.lj_eps, w.lj_sigma, w.lj_rc, w.lj_exclude_bonded, w.bf_kind, w.bf_amp,
                        n_atoms=w.n_atoms, n_bonds=len(w.bonds), kT=getattr(w, "kT", 0.0),
-                       seed=getattr(w, "noise_seed", 0))
+                       seed=getattr(w, "noise_seed", 0), coul_k=getattr(w, "coul_k", 0.0),
+                       charges=getattr(w, "charges", None))
 
 
 def n_sites(p: OrParams) -> int:

@@ -44,6 +44,7 @@ class lb_params(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("kT", ctypes.c_float),
         ("seed", ctypes.c_uint32 * 2),
+        ("coul_k", ctypes.c_float),
     ]
 
 
@@ -67,6 +68,7 @@ _SIGS = [
     ("lb_read_displacement", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("lb_read_populations", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("lb_set_populations", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("lb_set_charges", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("lb_invariants", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
     ("lb_status_check", ctypes.c_int, [ctypes.c_void_p]),
     ("lb_step_count", ctypes.c_int64, [ctypes.c_void_p]),
@@ -151,6 +153,10 @@ def lb_read_populations(ctx, g: int):
 
 def lb_set_populations(ctx, g: int):
     _check(lib().lb_set_populations(ctx, g or None), ctx)
+
+
+def lb_set_charges(ctx, q: int):
+    _check(lib().lb_set_charges(ctx, q or None), ctx)
 
 
 def lb_invariants(ctx):

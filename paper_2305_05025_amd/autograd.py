@@ -25,8 +25,9 @@ class CoupledTrajectory(torch.autograd.Function):
         p.tau = float(tau)
         p.bf_kind = A.LB_BF_FIELD
         field = body_force.detach().to(torch.float32).contiguous()
-        sim = CoupledLB(p, w.x0, w.v0, w.bonds, field.cpu().numpy(), device=field.device
-                        if field.is_cuda else "cuda")
+        sim = CoupledLB(p, w.x0, w.v0, w.bonds, field.cpu().numpy(),
+                        device=field.device if field.is_cuda else "cuda",
+                        charges=getattr(w, "charges", None))
         ckpt = sim.run_checkpointed(int(n_steps), int(k))
         disp = sim.displacement()
         _, _, _, v = sim.read_fields()

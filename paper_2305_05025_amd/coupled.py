@@ -18,7 +18,8 @@ STORAGE = {"f32": A.LB_STORE_F32, "f16": A.LB_STORE_F16, "bf16": A.LB_STORE_BF16
 
 def make_params(L, tau, rho0=1.0, storage="f32", n_atoms=0, mass=1.0, gamma=0.0, k_tether=0.0,
                 n_bonds=0, k_bond=0.0, r0_bond=1.0, lj_eps=0.0, lj_sigma=1.0, lj_rc=2.5,
-                lj_exclude_bonded=0, bf_kind=0, bf_amp=0.0, flags=0, kT=0.0, seed=0) -> A.lb_params:
+                lj_exclude_bonded=0, bf_kind=0, bf_amp=0.0, flags=0, kT=0.0, seed=0,
+                coul_k=0.0) -> A.lb_params:
     p = A.lb_params()
     Ls = (L, L, L) if isinstance(L, int) else tuple(L)
     for k in range(3):
@@ -32,6 +33,7 @@ def make_params(L, tau, rho0=1.0, storage="f32", n_atoms=0, mass=1.0, gamma=0.0,
     p.flags = int(flags)
     p.kT = float(kT)
     p.seed[0], p.seed[1] = int(seed) & 0xffffffff, (int(seed) >> 32) & 0xffffffff
+    p.coul_k = float(coul_k)
     return p
 
 
@@ -39,7 +41,7 @@ def params_from_workload(w, storage="f32", flags=0) -> A.lb_params:
     return make_params(w.L, w.tau, w.rho0, storage, w.n_atoms, w.mass, w.gamma, w.k_tether,
                        len(w.bonds), w.k_bond, w.r0_bond, w.lj_eps, w.lj_sigma, w.lj_rc,
                        w.lj_exclude_bonded, w.bf_kind, w.bf_amp, flags,
-                       getattr(w, "kT", 0.0), getattr(w, "noise_seed", 0))
+                       getattr(w, "kT", 0.0), getattr(w, "noise_seed", 0), getattr(w, "coul_k", 0.0))
 
 
 def _aligned_workspace(nbytes: int, device) -> tuple:
@@ -53,11 +55,12 @@ class CoupledLB:
     """One coupled lattice + atom system living on one GPU.
 
     x0, v0: [N, 3] float32 (unwrapped positions, velocities); bonds: [n_bonds, 2] int32;
-    body_force: [3, nz, ny, nx] float32 when bf_kind is LB_BF_FIELD.
+    body_force: [3, nz, ny, nx] float32 when bf_kind is LB_BF_FIELD; charges: [N] float32 for
+    the Coulomb term (zero when not given).
     """
 
     def __init__(self, params: A.lb_params, x0=None, v0=None, bonds=None, body_force=None,
-                 device="cuda", stream: Optional[torch.cuda.Stream] = None):
+                 device="cuda", stream: Optional[torch.cuda.Stream] = None, charges=None):
         self.device = torch.device(device)
         self.params = params
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -87,12 +90,17 @@ class CoupledLB:
         with torch.cuda.stream(self.stream):
             self.ctx = A.lb_init(params, ws_ptr, nbytes, ptr(x0t), ptr(v0t), ptr(bt), ptr(bft),
                                  self.stream.cuda_stream)
-        self._inputs = (x0t, v0t, bt, bft)   # kept alive until set-up copies are done
+        qt = None
+        if charges is not None and self.N:
+            qt = t32(charges, (self.N,))
+            A.lb_set_charges(self.ctx, qt.data_ptr())
+            self.stream.synchronize()
+        self._inputs = (x0t, v0t, bt, bft, qt)   # kept alive until set-up copies are done
 
     @classmethod
     def from_workload(cls, w, storage="f32", device="cuda", flags=0, stream=None):
         return cls(params_from_workload(w, storage, flags), w.x0, w.v0, w.bonds, w.body_force,
-                   device=device, stream=stream)
+                   device=device, stream=stream, charges=getattr(w, "charges", None))
 
     # -- stepping / observables ------------------------------------------------------------
     def step(self, n: int = 1):

@@ -378,6 +378,8 @@ struct ForceArgs {
   float k_bond, r0_bond;
   float lj_eps24, lj_sigma2, lj_rc2;
   int lj_exclude_bonded;
+  float coul2;            // 2 k_C (0: no Coulomb term)
+  const float* charge;
   const int* cell_count;
   const int4* cell_rec;
   const int* occ_cells;
@@ -492,6 +494,7 @@ __global__ __launch_bounds__(256) void k_forces_cells(ForceArgs a) {
     const bool excl = a.lj_exclude_bonded && b1 > b0;
     float4 lfi = make_float4(0.f, 0.f, 0.f, 0.f);
     if constexpr (kAdj) lfi = a.lf[i];
+    const float qi = a.coul2 != 0.f ? a.charge[i] : 0.f;
     float Fx = 0.f, Fy = 0.f, Fz = 0.f;
     // neighbour cells: lane l < 27 holds cell l of the 3x3x3 block
     long nbc = 0;
@@ -550,10 +553,18 @@ __global__ __launch_bounds__(256) void k_forces_cells(ForceArgs a) {
           const float inv2 = __builtin_amdgcn_rcpf(r2);
           const float sr2 = a.lj_sigma2 * inv2;
           const float sr6 = sr2 * sr2 * sr2;
-          const float f = a.lj_eps24 * (2.0f * sr6 * sr6 - sr6) * inv2;
+          // force on i = g(s) r with s = r^2; LJ: g = 24 eps (2 sigma^12 s^-7 - sigma^6 s^-4)
+          float f = a.lj_eps24 * (2.0f * sr6 * sr6 - sr6) * inv2;
+          // the Jacobian uses 2 g'(s)
+          float gp2 = 0.f;
+          if constexpr (kAdj) gp2 = 2.0f * a.lj_eps24 * (4.0f * sr6 - 14.0f * sr6 * sr6) * inv2 * inv2;
+          if (a.coul2 != 0.f) {
+            // implicit-solvent Coulomb: g = 2 k_C q_i q_j s^-2, 2 g' = -4 g / s
+            const float gc = a.coul2 * qi * a.charge[j] * inv2 * inv2;
+            f += gc;
+            if constexpr (kAdj) gp2 -= 4.0f * gc * inv2;
+          }
           if constexpr (kAdj) {
-            // g(s) = 24 eps (2 sigma^12 s^-7 - sigma^6 s^-4), s = r^2
-            const float gp2 = 2.0f * a.lj_eps24 * (4.0f * sr6 - 14.0f * sr6 * sr6) * inv2 * inv2;
             const float4 lj = a.lf[j];
             const float ex = lfi.x - lj.x, ey = lfi.y - lj.y, ez = lfi.z - lj.z;
             const float t = gp2 * (rx * ex + ry * ey + rz * ez);
@@ -781,7 +792,9 @@ static ForceArgs force_args(lb_ctx* c) {
   a.k_bond = c->p.k_bond;
   a.r0_bond = c->p.r0_bond;
   a.lj_eps24 = 24.0f * c->p.lj_eps;
-  a.lj_sigma2 = c->p.lj_sigma * c->p.lj_sigma;
+  a.lj_sigma2 = c->p.lj_eps != 0.0f ? c->p.lj_sigma * c->p.lj_sigma : 0.0f;
+  a.coul2 = 2.0f * c->p.coul_k;
+  a.charge = (const float*)(c->ws + c->lay.charge);
   a.lj_rc2 = c->p.lj_rc * c->p.lj_rc;
   a.lj_exclude_bonded = c->p.lj_exclude_bonded;
   a.cell_count = (const int*)(c->ws + c->lay.cell_count);

@@ -30,7 +30,7 @@ bool geometry(const lb_params* p, Geometry* g) {
     g->nc[k] = 0;
     g->inv_cw[k] = 0.f;
   }
-  if (p->n_atoms > 0 && p->lj_eps != 0.0f) {
+  if (p->n_atoms > 0 && (p->lj_eps != 0.0f || p->coul_k != 0.0f)) {
     g->ncell = 1;
     for (int k = 0; k < 3; ++k) {
       // cells at least r_c (plus a 0.1% margin against rounding of wrapped positions) wide
@@ -78,6 +78,7 @@ Layout plan(const lb_params* p, const Geometry& g) {
   l.vel = take(3 * N * 4);
   l.fc = take(3 * N * 4);
   l.ff = take(3 * N * 4);
+  l.charge = take(N * 4);
   l.bond_off = take((N + 1) * 4);
   l.bond_nbr = take(2 * (size_t)p->n_bonds * 4);
   l.cell_count = take((size_t)g.ncell * 4);
@@ -118,8 +119,9 @@ static std::string validate(const lb_params* p) {
     if (!finite(p->k_tether)) return "k_tether must be finite";
     if (!finite(p->k_bond) || !finite(p->r0_bond)) return "bond parameters must be finite";
     if (!finite(p->lj_eps) || p->lj_eps < 0.0f) return "lj_eps must be finite and >= 0";
-    if (p->lj_eps != 0.0f) {
-      if (!finite(p->lj_sigma) || !(p->lj_sigma > 0.0f)) return "lj_sigma must be > 0";
+    if (!finite(p->coul_k)) return "coul_k must be finite";
+    if (p->lj_eps != 0.0f && (!finite(p->lj_sigma) || !(p->lj_sigma > 0.0f))) return "lj_sigma must be > 0";
+    if (p->lj_eps != 0.0f || p->coul_k != 0.0f) {
       // cell-relative fixed-point positions (8.24) need cells narrower than ~60 lattice units
       if (!finite(p->lj_rc) || !(p->lj_rc > 0.0f) || p->lj_rc > 40.0f) return "lj_rc must be in (0, 40]";
       for (int k = 0; k < 3; ++k)
@@ -440,6 +442,15 @@ lb_status lb_read_populations(lb_ctx* c, float* g) {
   if (!g) return fail(c, LB_EINVAL, "output is NULL");
   hipError_t e = launch_read_populations(c, g);
   return e == hipSuccess ? LB_OK : hip_fail(c, e, "population readback launch");
+}
+
+lb_status lb_set_charges(lb_ctx* c, const float* q) {
+  if (!c) return fail(nullptr, LB_EINVAL, "context is NULL");
+  if (c->p.n_atoms == 0) return LB_OK;
+  if (!q) return fail(c, LB_EINVAL, "charges are NULL");
+  hipError_t e = hipMemcpyAsync(c->ws + c->lay.charge, q, 4 * (size_t)c->p.n_atoms, hipMemcpyDeviceToDevice,
+                                c->stream);
+  return e == hipSuccess ? LB_OK : hip_fail(c, e, "charge copy");
 }
 
 lb_status lb_set_populations(lb_ctx* c, const float* g) {

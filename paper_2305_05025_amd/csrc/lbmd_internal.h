@@ -54,6 +54,7 @@ struct Layout {
   size_t vel;          // float [N][3]
   size_t fc;           // float [N][3] friction force of the current step
   size_t ff;           // float [N][3] stand-in force field at X^n
+  size_t charge;       // float [N] atom charges (Coulomb term)
   size_t bond_off;     // int32 [N+1]
   size_t bond_nbr;     // int32 [2 n_bonds]
   size_t cell_count;   // int32 [ncell]

@@ -22,7 +22,7 @@ def _gpu_grads(w, field, D, steps, k, storage="f32", reps=1):
     say("adjoint", w.name, w.L, "atoms", w.n_atoms, "steps", steps, "k", k, storage)
     p = params_from_workload(w, storage)
     p.bf_kind = A.LB_BF_FIELD
-    sim = CoupledLB(p, w.x0, w.v0, w.bonds, field.astype(np.float32))
+    sim = CoupledLB(p, w.x0, w.v0, w.bonds, field.astype(np.float32), charges=w.charges)
     ck = sim.run_checkpointed(steps, k)
     d = sim.displacement().double().cpu().numpy()
     g_before = sim.populations().cpu().numpy()

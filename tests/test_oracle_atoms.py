@@ -135,3 +135,46 @@ def test_symplectic_euler_tethered_atom(O, k, m):
         want = Mn @ np.array([x[0, c] - X0[0, c], v[0, c]])
         assert abs(Xn[0, c] - X0[0, c] - want[0]) < 1e-12
         assert abs(Vn[0, c] - want[1]) < 1e-12
+
+
+# ---- implicit-solvent Coulomb (permittivity proportional to r): U = k_C q_i q_j / r^2 ----------
+
+def test_coulomb_implicit_pair_closed_form(O):
+    """Two charges: U = k q1 q2 / r^2 and F_1 = 2 k q1 q2 (X_1 - X_2) / r^4, off at r >= r_c."""
+    q = np.array([0.7, -0.4])
+    p = O.make_params(20, 0.8, n_atoms=2, coul_k=0.3, charges=q, lj_rc=2.5)
+    for r in (0.9, 1.7, 2.4):
+        X = np.array([[5.0, 5.0, 5.0], [5.0, 5.0 + r, 5.0]])
+        U = O.energy(p, X, X, E0)
+        assert abs(U - 0.3 * 0.7 * -0.4 / r ** 2) < 1e-15
+        F = O.forces(p, X, X, E0)
+        want = 2 * 0.3 * 0.7 * -0.4 / r ** 4 * np.array([0.0, -r, 0.0])
+        np.testing.assert_allclose(F[0], want, rtol=1e-14, atol=1e-18)
+        np.testing.assert_allclose(F[1], -want, rtol=1e-14, atol=1e-18)
+    X = np.array([[5.0, 5.0, 5.0], [5.0, 5.0 + 2.6, 5.0]])
+    assert O.energy(p, X, X, E0) == 0.0 and np.abs(O.forces(p, X, X, E0)).max() == 0.0
+
+
+def test_coulomb_newton_third_law_and_gradient(O, cluster):
+    """With charges on the globule (bonded pairs excluded like LJ): forces sum to zero and
+    equal -grad U by central differences."""
+    from workloads import seeded_charges
+    w, X = cluster
+    q = seeded_charges(w.n_atoms, 3).astype(np.float64)
+    p = O.make_params(w.L, w.tau, k_bond=w.k_bond, r0_bond=w.r0_bond, lj_eps=w.lj_eps,
+                      lj_exclude_bonded=1, n_atoms=w.n_atoms, n_bonds=len(w.bonds),
+                      coul_k=0.02, charges=q)
+    F = O.forces(p, X, w.x0, w.bonds)
+    p0 = O.make_params(w.L, w.tau, k_bond=w.k_bond, r0_bond=w.r0_bond, lj_eps=w.lj_eps,
+                       lj_exclude_bonded=1, n_atoms=w.n_atoms, n_bonds=len(w.bonds))
+    assert np.abs(F - O.forces(p0, X, w.x0, w.bonds)).max() > 1e-4   # the term is active
+    np.testing.assert_allclose(F.sum(0), 0.0, atol=1e-14)
+    h = 1e-6
+    rng = np.random.default_rng(2)
+    for a in rng.choice(w.n_atoms, 8, replace=False):
+        for c in range(3):
+            Xp, Xm = X.copy(), X.copy()
+            Xp[a, c] += h
+            Xm[a, c] -= h
+            fd = -(O.energy(p, Xp, w.x0, w.bonds) - O.energy(p, Xm, w.x0, w.bonds)) / (2 * h)
+            assert abs(fd - F[a, c]) < 1e-7 * max(1.0, abs(F[a, c])), (a, c, fd, F[a, c])

@@ -68,6 +68,8 @@ class Workload:
     seed: int
     kT: float = 0.0                     # thermal energy of the lattice noise (0: athermal)
     noise_seed: int = 0                 # key of the counter-based noise generator
+    coul_k: float = 0.0                 # implicit-solvent Coulomb prefactor (0: off)
+    charges: Optional[np.ndarray] = None  # [N] float32 atom charges
 
     @property
     def n_atoms(self) -> int:
@@ -82,7 +84,7 @@ class Workload:
         return {k: getattr(self, k) for k in (
             "L", "tau", "rho0", "gamma", "mass", "k_tether", "k_bond", "r0_bond",
             "lj_eps", "lj_sigma", "lj_rc", "lj_exclude_bonded", "bf_kind", "bf_amp", "kT",
-            "noise_seed")}
+            "noise_seed", "coul_k")}
 
 
 # ---------------------------------------------------------------------------------------
@@ -257,6 +259,13 @@ CONFIGS = {
 def globule_radius(n_per: int) -> float:
     """R = 20 for a 20k-atom globule, scaled as n^(1/3) otherwise."""
     return 20.0 * (n_per / 20000.0) ** (1.0 / 3.0)
+
+
+def seeded_charges(n: int, seed: int, q0: float = 0.5) -> np.ndarray:
+    """A neutral (for even n) set of charges +-q0 in seeded random order, float32."""
+    q = np.where(np.arange(n) % 2 == 0, q0, -q0)
+    np.random.default_rng(seed).shuffle(q)
+    return q.astype(np.float32)
 
 
 def make_workload(k: int, seed: Optional[int] = None) -> Workload:
