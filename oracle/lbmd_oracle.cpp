@@ -106,6 +106,7 @@ struct Model {
   long S;
   T tau, rho0, gamma, mass, k_tether, k_bond, r0_bond, lj_eps, lj_sigma, lj_rc;
   T coul_k;                                  // implicit-solvent Coulomb prefactor (0: off)
+  T trt_magic;                               // two-relaxation-time magic parameter (0: BGK)
   std::vector<T> charge;                     // per atom
   double kT;                                 // thermal energy (0: no noise)
   uint32_t seed[2];                          // Philox key
@@ -157,12 +158,26 @@ void equilibrium_dev(T drho, T rho, const T u[3], T out[19]) {
   }
 }
 
-// Eq. (1) at one node, BGK with Guo forcing:
-//   u* = (j + F/2) / rho
-//   S_i = (1 - 1/(2 tau)) w_i [ 3 (c_i - u*) + 9 (c_i . u*) c_i ] . F
-//   g*_i = g_i - (g_i - g_eq_i(rho, u*)) / tau + S_i
+// Opposite velocity: c_opp(i) = -c_i.
+inline int opposite(int i) { return i == 0 ? 0 : (i % 2 ? i + 1 : i - 1); }
+
+// Relaxation rate of the antisymmetric part (two-relaxation-time collision) from the
+// "magic" parameter Lambda = (1/omega+ - 1/2)(1/omega- - 1/2), omega+ = 1/tau.
 template <class T>
-void collide_node(T tau, T rho0, const T g[19], const T F[3], T out[19]) {
+T omega_minus(T tau, T magic) {
+  return T(1.0) / (T(0.5) + magic / (tau - T(0.5)));
+}
+
+// Eq. (1) at one node with Guo forcing:
+//   u* = (j + F/2) / rho
+//   s_i = w_i [ 3 (c_i - u*) + 9 (c_i . u*) c_i ] . F
+//   BGK (magic = 0): g*_i = g_i - (g_i - g_eq_i(rho, u*)) / tau + (1 - 1/(2 tau)) s_i
+//   two relaxation times (magic > 0; the collision-variant extension): with
+//     d_i = g_i - g_eq_i + s_i / 2 split into its parts even and odd under c -> -c,
+//     g*_i = g_i + s_i - omega+ d+_i - omega- d-_i,  omega+ = 1/tau, omega- from magic,
+//   which is the BGK form above when omega- = omega+.
+template <class T>
+void collide_node(T tau, T rho0, const T g[19], const T F[3], T out[19], T magic = T(0.0)) {
   T drho = T(0.0), j[3] = {T(0.0), T(0.0), T(0.0)};
   for (int i = 0; i < 19; ++i) {
     drho += g[i];
@@ -174,6 +189,7 @@ void collide_node(T tau, T rho0, const T g[19], const T F[3], T out[19]) {
   T geq[19];
   equilibrium_dev(drho, rho, u, geq);
   T pref = T(1.0) - T(1.0) / (T(2.0) * tau);
+  T sraw[19];
   for (int i = 0; i < 19; ++i) {
     T cu = T((double)CV[i][0]) * u[0] + T((double)CV[i][1]) * u[1] + T((double)CV[i][2]) * u[2];
     T src = T(0.0);
@@ -183,6 +199,17 @@ void collide_node(T tau, T rho0, const T g[19], const T F[3], T out[19]) {
     }
     T Si = pref * T(WV[i]) * src;
     out[i] = g[i] - (g[i] - geq[i]) / tau + Si;
+    sraw[i] = T(WV[i]) * src;
+  }
+  if (val(magic) > 0.0) {
+    const T om_p = T(1.0) / tau, om_m = omega_minus(tau, magic);
+    T d[19];
+    for (int i = 0; i < 19; ++i) d[i] = g[i] - geq[i] + T(0.5) * sraw[i];
+    for (int i = 0; i < 19; ++i) {
+      const T dp = T(0.5) * (d[i] + d[opposite(i)]);
+      const T dm = T(0.5) * (d[i] - d[opposite(i)]);
+      out[i] = g[i] + sraw[i] - om_p * dp - om_m * dm;
+    }
   }
 }
 
@@ -341,18 +368,24 @@ double mode_norm(int k) {
 
 // Noise added to the post-collision populations at one site:
 //   xi_i = w_i sum_{k=4..18} e_k(c_i) phi_k z_{k-4} / b_k,
-//   phi_k = sqrt(mu b_k (1 - (1 - omega)^2)),  mu = 3 rho kT.
+//   phi_k = sqrt(mu b_k (1 - (1 - omega_k)^2)),  mu = 3 rho kT,
+// omega_k the rate that relaxes mode k: 1/tau, except the modes odd under c -> -c (k = 10..15)
+// under the two-relaxation-time collision, which relax at omega-.
 template <class T>
-void site_noise(double kT, T tau, T rho, const uint32_t seed[2], int64_t step, long site, T xi[19]) {
+void site_noise(double kT, T tau, T rho, const uint32_t seed[2], int64_t step, long site, T xi[19],
+                T magic = T(0.0)) {
   double z[16];
   site_normals(seed, step, site, z);
-  const T omega = T(1.0) / tau;
-  const T g = T(1.0) - omega;
-  const T amp2 = T(3.0 * kT) * rho * (T(1.0) - g * g);
+  const T om_p = T(1.0) / tau;
+  const T om_m = val(magic) > 0.0 ? omega_minus(tau, magic) : om_p;
+  const T gp = T(1.0) - om_p, gm = T(1.0) - om_m;
+  const T amp2_p = T(3.0 * kT) * rho * (T(1.0) - gp * gp);
+  const T amp2_m = T(3.0 * kT) * rho * (T(1.0) - gm * gm);
   for (int i = 0; i < 19; ++i) {
     T acc = T(0.0);
     for (int k = 4; k < 19; ++k) {
       const double b = mode_norm(k);
+      const T amp2 = (k >= 10 && k <= 15) ? amp2_m : amp2_p;
       acc += T(mode_poly(k, CV[i]) * z[k - 4]) * sqrtT(amp2 * T(b)) / T(b);
     }
     xi[i] = T(WV[i]) * acc;
@@ -541,12 +574,12 @@ void coupled_step(const Model<T>& m, State<T>& s, std::vector<T>& scratch_post) 
     T gin[19], gout[19], F[3];
     for (int i = 0; i < 19; ++i) gin[i] = s.g[i * S + x];
     for (int c = 0; c < 3; ++c) F[c] = Ftot[c * S + x];
-    collide_node(m.tau, m.rho0, gin, F, gout);
+    collide_node(m.tau, m.rho0, gin, F, gout, m.trt_magic);
     if (m.kT > 0.0) {
       T rho = m.rho0;
       for (int i = 0; i < 19; ++i) rho += gin[i];
       T xi[19];
-      site_noise(m.kT, m.tau, rho, m.seed, s.step, x, xi);
+      site_noise(m.kT, m.tau, rho, m.seed, s.step, x, xi, m.trt_magic);
       for (int i = 0; i < 19; ++i) gout[i] += xi[i];
     }
     for (int i = 0; i < 19; ++i) scratch_post[i * S + x] = gout[i];
@@ -582,6 +615,7 @@ struct or_params {
   int64_t step0;      // step index of the input state (counts the noise)
   double coul_k;      // implicit-solvent Coulomb prefactor k_C (0: off)
   const double* charge;   // [n_atoms] charges, or NULL (all zero)
+  double trt_magic;   // two-relaxation-time collision: Lambda (0: BGK)
 };
 
 }  // extern "C"
@@ -628,6 +662,7 @@ void build_model(const or_params* p, const double* X0, const int32_t* bonds, con
   m.lj_exclude_bonded = p->lj_exclude_bonded;
   m.kT = p->kT;
   m.coul_k = T(p->coul_k);
+  m.trt_magic = T(p->trt_magic);
   m.charge.assign((size_t)p->n_atoms, T(0.0));
   if (p->charge)
     for (int a = 0; a < p->n_atoms; ++a) m.charge[a] = T(p->charge[a]);
@@ -695,8 +730,8 @@ void or_mode_basis(double* e, double* b) {
 }
 
 void or_site_noise(double kT, double tau, double rho, const uint32_t* seed, int64_t step, int64_t site,
-                   double* xi) {
-  site_noise(kT, tau, rho, seed, step, (long)site, xi);
+                   double* xi, double magic) {
+  site_noise(kT, tau, rho, seed, step, (long)site, xi, magic);
 }
 
 void or_velocity_set(int32_t* c, double* w) {
@@ -714,6 +749,11 @@ void or_equilibrium(double rho0, double drho, const double* u, double* out) {
 // One BGK + Guo collision at a single node.
 void or_collide_node(double tau, double rho0, const double* g, const double* F, double* out) {
   collide_node<double>(tau, rho0, g, F, out);
+}
+
+void or_collide_node_trt(double tau, double magic, double rho0, const double* g, const double* F,
+                         double* out) {
+  collide_node<double>(tau, rho0, g, F, out, magic);
 }
 
 // Streaming of a [19][S] population array (post-collision in, pre-collision out).
@@ -885,12 +925,12 @@ int or_step_sampled(const or_params* p, const double* g, const double* X, const 
       double gin[19], gout[19], F[3];
       for (int q = 0; q < 19; ++q) gin[q] = s.g[q * m.S + src];
       for (int c = 0; c < 3; ++c) F[c] = Ftot[c * m.S + src];
-      collide_node(m.tau, m.rho0, gin, F, gout);
+      collide_node(m.tau, m.rho0, gin, F, gout, m.trt_magic);
       if (m.kT > 0.0) {
         double rho = val(m.rho0);
         for (int q = 0; q < 19; ++q) rho += gin[q];
         double xi[19];
-        site_noise(m.kT, val(m.tau), rho, m.seed, s.step, src, xi);
+        site_noise(m.kT, val(m.tau), rho, m.seed, s.step, src, xi, m.trt_magic);
         gout[i] += xi[i];
       }
       g_out[19 * k + i] = gout[i];

@@ -56,6 +56,7 @@ class OrParams(ctypes.Structure):
         ("step0", ctypes.c_int64),
         ("coul_k", ctypes.c_double),
         ("charge", ctypes.POINTER(ctypes.c_double)),
+        ("trt_magic", ctypes.c_double),
     ]
 
 
@@ -99,7 +100,8 @@ def lib():
         L.or_site_normals.argtypes = [up, ctypes.c_int64, ctypes.c_int64, dp]
         L.or_mode_basis.argtypes = [dp, dp]
         L.or_site_noise.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, up,
-                                    ctypes.c_int64, ctypes.c_int64, dp]
+                                    ctypes.c_int64, ctypes.c_int64, dp, ctypes.c_double]
+        L.or_collide_node_trt.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -128,7 +130,8 @@ def i32(a):
 
 def make_params(L, tau, rho0=1.0, gamma=0.0, mass=1.0, k_tether=0.0, k_bond=0.0, r0_bond=1.0,
                 lj_eps=0.0, lj_sigma=1.0, lj_rc=2.5, lj_exclude_bonded=0, bf_kind=0, bf_amp=0.0,
-                n_atoms=0, n_bonds=0, kT=0.0, seed=0, step0=0, coul_k=0.0, charges=None) -> OrParams:
+                n_atoms=0, n_bonds=0, kT=0.0, seed=0, step0=0, coul_k=0.0, charges=None,
+                trt_magic=0.0) -> OrParams:
     p = OrParams()
     Ls = (L, L, L) if np.isscalar(L) else tuple(L)
     for a in range(3):
@@ -142,6 +145,7 @@ def make_params(L, tau, rho0=1.0, gamma=0.0, mass=1.0, k_tether=0.0, k_bond=0.0,
     p.seed[0], p.seed[1] = int(seed) & 0xffffffff, (int(seed) >> 32) & 0xffffffff
     p.step0 = int(step0)
     p.coul_k = float(coul_k)
+    p.trt_magic = float(trt_magic)
     if charges is not None:
         q = f64(charges).reshape(-1)
         assert q.size == p.n_atoms
@@ -155,7 +159,7 @@ def params_from_workload(w) -> OrParams:
                        w.lj_eps, w.lj_sigma, w.lj_rc, w.lj_exclude_bonded, w.bf_kind, w.bf_amp,
                        n_atoms=w.n_atoms, n_bonds=len(w.bonds), kT=getattr(w, "kT", 0.0),
                        seed=getattr(w, "noise_seed", 0), coul_k=getattr(w, "coul_k", 0.0),
-                       charges=getattr(w, "charges", None))
+                       charges=getattr(w, "charges", None), trt_magic=getattr(w, "trt_magic", 0.0))
 
 
 def n_sites(p: OrParams) -> int:
@@ -327,12 +331,20 @@ def mode_basis():
     return e, b
 
 
-def site_noise(kT, tau, rho, seed, step, site):
+def site_noise(kT, tau, rho, seed, step, site, trt_magic=0.0):
     """The thermal noise xi [19] added after the collision at one site."""
     k, kp = _u32([seed & 0xffffffff, (seed >> 32) & 0xffffffff])
     xi = np.zeros(19)
-    lib().or_site_noise(float(kT), float(tau), float(rho), kp, int(step), int(site), _d(xi))
+    lib().or_site_noise(float(kT), float(tau), float(rho), kp, int(step), int(site), _d(xi),
+                        float(trt_magic))
     return xi
+
+
+def collide_node_trt(tau, magic, rho0, g, F):
+    """The two-relaxation-time collision at one node (magic = 0: BGK)."""
+    out = np.zeros(19)
+    lib().or_collide_node_trt(float(tau), float(magic), float(rho0), _d(f64(g)), _d(f64(F)), _d(out))
+    return out
 
 
 def rest_state(p: OrParams):
