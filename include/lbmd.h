@@ -105,6 +105,10 @@ typedef struct {
                                 permittivity growing with r): U = coul_k q_i q_j / r^2 under the
                                 Lennard-Jones cut-off and exclusions; charges from
                                 lb_set_charges (zero until set); 0 = off */
+  float trt_magic;           /* collision variant: 0 = BGK (Eq. 1); > 0 = two relaxation times,
+                                the part of f - f_eq odd under c -> -c relaxing at omega- with
+                                (tau - 1/2)(1/omega- - 1/2) = trt_magic (tau sets the viscosity
+                                as before; trt_magic = (tau - 1/2)^2 is BGK again) */
 } lb_params;
 
 /* The 19 lattice velocities c[i][0..2] and weights w[i] in the library's ordering:

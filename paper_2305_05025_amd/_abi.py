@@ -45,6 +45,7 @@ class lb_params(ctypes.Structure):
         ("kT", ctypes.c_float),
         ("seed", ctypes.c_uint32 * 2),
         ("coul_k", ctypes.c_float),
+        ("trt_magic", ctypes.c_float),
     ]
 
 

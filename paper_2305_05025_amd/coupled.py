@@ -19,7 +19,7 @@ STORAGE = {"f32": A.LB_STORE_F32, "f16": A.LB_STORE_F16, "bf16": A.LB_STORE_BF16
 def make_params(L, tau, rho0=1.0, storage="f32", n_atoms=0, mass=1.0, gamma=0.0, k_tether=0.0,
                 n_bonds=0, k_bond=0.0, r0_bond=1.0, lj_eps=0.0, lj_sigma=1.0, lj_rc=2.5,
                 lj_exclude_bonded=0, bf_kind=0, bf_amp=0.0, flags=0, kT=0.0, seed=0,
-                coul_k=0.0) -> A.lb_params:
+                coul_k=0.0, trt_magic=0.0) -> A.lb_params:
     p = A.lb_params()
     Ls = (L, L, L) if isinstance(L, int) else tuple(L)
     for k in range(3):
@@ -34,6 +34,7 @@ def make_params(L, tau, rho0=1.0, storage="f32", n_atoms=0, mass=1.0, gamma=0.0,
     p.kT = float(kT)
     p.seed[0], p.seed[1] = int(seed) & 0xffffffff, (int(seed) >> 32) & 0xffffffff
     p.coul_k = float(coul_k)
+    p.trt_magic = float(trt_magic)
     return p
 
 
@@ -41,7 +42,8 @@ def params_from_workload(w, storage="f32", flags=0) -> A.lb_params:
     return make_params(w.L, w.tau, w.rho0, storage, w.n_atoms, w.mass, w.gamma, w.k_tether,
                        len(w.bonds), w.k_bond, w.r0_bond, w.lj_eps, w.lj_sigma, w.lj_rc,
                        w.lj_exclude_bonded, w.bf_kind, w.bf_amp, flags,
-                       getattr(w, "kT", 0.0), getattr(w, "noise_seed", 0), getattr(w, "coul_k", 0.0))
+                       getattr(w, "kT", 0.0), getattr(w, "noise_seed", 0), getattr(w, "coul_k", 0.0),
+                       getattr(w, "trt_magic", 0.0))
 
 
 def _aligned_workspace(nbytes: int, device) -> tuple:

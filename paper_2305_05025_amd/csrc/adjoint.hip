@@ -8,11 +8,15 @@
 // lx = dL/dX^{n+1}, lv = dL/dv^{n+1} back to step n, accumulating dL/dgamma, dL/domega and
 // dL/dF_ext on the way.  With h_i(x) = P^n_i(x - c_i) the pre-collision values at x and
 // mu(x) = Lam^{n+1}(x) the adjoint of the collision output at x:
-//   collision (BGK + Guo, u* = (j + F/2)/rho):
-//     a_i = (1 - omega) mu_i + l_rho + c_i . l_j        (l_j = l_u / rho,
-//     l_rho = omega sum_i mu_i dgeq_i/drho - u*.l_u/rho,  l_u = sum_i mu_i d(out_i)/du*)
-//     phi = dL/dF(x) = sum_i mu_i d(S_i)/dF + l_u / (2 rho)
-//     dL/domega += sum_i mu_i (-(h_i - geq_i) - s_i / 2),  S_i = (1 - omega/2) s_i
+//   collision with Guo forcing, written as out = h + s - omega+ d+ - omega- d- with
+//     d = h - geq(rho, u*) + s/2, u* = (j + F/2)/rho, s the Guo source before its prefactor
+//     (BGK: omega- = omega+ = omega).  With nu_i = omega+ mu+_i + omega- mu-_i (mu+- the parts
+//     of mu even and odd under c -> -c) and kappa = mu - nu/2:
+//     a_i = mu_i - nu_i + l_rho + c_i . l_j      (l_j = l_u / rho,
+//       l_rho = sum_i nu_i dgeq_i/drho - u*.l_u/rho,
+//       l_u = sum_i [nu_i dgeq_i/du* + kappa_i ds_i/du*])
+//     phi = dL/dF(x) = sum_i kappa_i ds_i/dF + l_u / (2 rho)
+//     dL/domega+ += -sum_i mu+_i d_i,  dL/domega- += -sum_i mu-_i d_i
 //   atoms (F_c = gamma (U - v), U = sum_k W_k u_c(node_k), the fluid gets -W_k F_c):
 //     v'  = lv + lx                                       (X^{n+1} = X^n + v^{n+1})
 //     lF_c = v'/m - sum_k W_k phi(node_k)
@@ -21,9 +25,10 @@
 //   coupling velocity (u_c = (j + F_ext/2)/rho at nodes, from h):
 //     l_uc(x) = sum_a W(X_a, x) l_U,a;  a_i += -u_c.l_uc/rho + c_i . l_uc/rho
 //   and dL/dF_ext(x) += phi(x) + l_uc(x) / (2 rho)
-//   thermal noise (kT > 0): out_i += A(rho, omega) p_i with A = sqrt(3 rho kT (2 omega -
-//     omega^2)) and p_i the step's fixed noise pattern, so a_i += (sum_j mu_j p_j) A/(2 rho)
-//     and dL/domega += (sum_j mu_j p_j) A (1 - omega)/(2 omega - omega^2)
+//   thermal noise (kT > 0): out_i += A+ pe_i + A- po_i with A+- = sqrt(3 rho kT (2 omega+- -
+//     omega+-^2)) and pe, po the step's fixed even and odd patterns, so
+//     a_i += (sum mu pe A+ + sum mu po A-)/(2 rho) and
+//     dL/domega+- += (sum mu p+-) A+- (1 - omega+-)/(2 omega+- - omega+-^2)
 //   streaming (pull): Lam^n_i(x - c_i) = a_i(x), a push with one store per (i, x).
 // The state of each step is recomputed from checkpoints by the host (lb_backward).
 #include "atoms_common.h"
@@ -37,7 +42,7 @@ struct AdjLatticeArgs {
   float* lam_out;         // Lam^n
   long plane;
   int nx, ny, nz, S;
-  float rho0, omega, pref;
+  float rho0, omega, omega_m;
   int bf_kind;
   const float* fext_tab;
   const float* fext_field;
@@ -48,7 +53,7 @@ struct AdjLatticeArgs {
   const float* luc;       // dL/du_c on flagged tiles
   float* phi;             // out (tile pass): dL/dF on flagged tiles
   float* db;              // dL/dF_ext accumulated, [3][S], or NULL
-  double* dom_part;       // per workgroup: partial dL/domega
+  double* dom_part;       // per workgroup: partial dL/domega+ and dL/domega- [2][nblocks]
   const int* hot_list;
   const int* hot_count;
   float kT;               // thermal noise of the forward step (0: none)
@@ -57,12 +62,13 @@ struct AdjLatticeArgs {
 };
 
 // Adjoint of the collision at one site: from mu (adjoint of the output) and the site's
-// pre-collision values g and force F, the adjoint of g (in place of mu), phi = dL/dF, and
-// this site's dL/domega term.  Also returns rho and the moments for the caller.
+// pre-collision values g and force F, the adjoint of g (in place of mu), phi = dL/dF, and this
+// site's dL/domega+ and dL/domega- terms.  Also returns rho and the moments for the caller.
 __device__ __forceinline__ void collide_adjoint(float mu[19], const float g[19], float Fx, float Fy,
-                                                float Fz, float rho0, float omega, float pref,
-                                                float& phx, float& phy, float& phz, float& dom,
-                                                float& rho, float& jx, float& jy, float& jz) {
+                                                float Fz, float rho0, float omega_p, float omega_m,
+                                                float& phx, float& phy, float& phz, float& dom_p,
+                                                float& dom_m, float& rho, float& jx, float& jy,
+                                                float& jz) {
   float drho;
   moments(g, drho, jx, jy, jz);
   rho = rho0 + drho;
@@ -72,44 +78,49 @@ __device__ __forceinline__ void collide_adjoint(float mu[19], const float g[19],
   const float uz = (jz + 0.5f * Fz) * inv;
   const float uu = ux * ux + uy * uy + uz * uz;
   const float uF = ux * Fx + uy * Fy + uz * Fz;
+  const float ca = 0.5f * (omega_p + omega_m), cb = 0.5f * (omega_p - omega_m);
   float lrho_e = 0.f, lux = 0.f, luy = 0.f, luz = 0.f, lfx = 0.f, lfy = 0.f, lfz = 0.f;
-  dom = 0.f;
+  float nu[19];
+  dom_p = dom_m = 0.f;
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
     const float cu = cdot<0>(ux, uy, uz, CX[i], CY[i], CZ[i]);
     const float cF = cdot<0>(Fx, Fy, Fz, CX[i], CY[i], CZ[i]);
-    const float A = mu[i] * WQ[i];
+    const float n = ca * mu[i] + cb * mu[OPP(i)];
+    const float k = mu[i] - 0.5f * n;
+    nu[i] = n;
     const float geq = WQ[i] * (drho + rho * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu));
     const float si = WQ[i] * (3.0f * (cF - uF) + 9.0f * cu * cF);
-    dom += mu[i] * (-(g[i] - geq) - 0.5f * si);
-    lrho_e += A * (1.0f + 3.0f * cu + 4.5f * cu * cu - 1.5f * uu);
-    // d out_i / d u*: omega w rho (3 c + 9 cu c - 3 u) + pref w (9 cF c - 3 F)
-    const float kc = omega * rho * (3.0f + 9.0f * cu) + 9.0f * pref * cF;
-    const float ku = 3.0f * omega * rho;
-    const float kf = 3.0f * pref;
-    lux += A * (kc * (float)CX[i] - ku * ux - kf * Fx);
-    luy += A * (kc * (float)CY[i] - ku * uy - kf * Fy);
-    luz += A * (kc * (float)CZ[i] - ku * uz - kf * Fz);
-    // d S_i / d F (explicit): pref w (3 (c - u) + 9 cu c)
+    const float d = g[i] - geq + 0.5f * si;
+    dom_p -= 0.5f * (mu[i] + mu[OPP(i)]) * d;
+    dom_m -= 0.5f * (mu[i] - mu[OPP(i)]) * d;
+    const float An = n * WQ[i], Ak = k * WQ[i];
+    lrho_e += An * (1.0f + 3.0f * cu + 4.5f * cu * cu - 1.5f * uu);
+    // d geq_i / d u*: w rho (3 c + 9 cu c - 3 u);  d s_i / d u*: w (9 cF c - 3 F)
+    const float kc = rho * (3.0f + 9.0f * cu);
+    lux += An * (kc * (float)CX[i] - 3.0f * rho * ux) + Ak * (9.0f * cF * (float)CX[i] - 3.0f * Fx);
+    luy += An * (kc * (float)CY[i] - 3.0f * rho * uy) + Ak * (9.0f * cF * (float)CY[i] - 3.0f * Fy);
+    luz += An * (kc * (float)CZ[i] - 3.0f * rho * uz) + Ak * (9.0f * cF * (float)CZ[i] - 3.0f * Fz);
+    // d s_i / d F (explicit): w (3 (c - u) + 9 cu c)
     const float kfc = 3.0f + 9.0f * cu;
-    lfx += A * (kfc * (float)CX[i] - 3.0f * ux);
-    lfy += A * (kfc * (float)CY[i] - 3.0f * uy);
-    lfz += A * (kfc * (float)CZ[i] - 3.0f * uz);
+    lfx += Ak * (kfc * (float)CX[i] - 3.0f * ux);
+    lfy += Ak * (kfc * (float)CY[i] - 3.0f * uy);
+    lfz += Ak * (kfc * (float)CZ[i] - 3.0f * uz);
   }
   const float ljx = lux * inv, ljy = luy * inv, ljz = luz * inv;
-  const float lrho = omega * lrho_e - (ux * lux + uy * luy + uz * luz) * inv;
-  phx = pref * lfx + 0.5f * ljx;
-  phy = pref * lfy + 0.5f * ljy;
-  phz = pref * lfz + 0.5f * ljz;
+  const float lrho = lrho_e - (ux * lux + uy * luy + uz * luz) * inv;
+  phx = lfx + 0.5f * ljx;
+  phy = lfy + 0.5f * ljy;
+  phz = lfz + 0.5f * ljz;
 #pragma unroll
   for (int i = 0; i < 19; ++i)
-    mu[i] = (1.0f - omega) * mu[i] + lrho + cdot<0>(ljx, ljy, ljz, CX[i], CY[i], CZ[i]);
+    mu[i] = mu[i] - nu[i] + lrho + cdot<0>(ljx, ljy, ljz, CX[i], CY[i], CZ[i]);
 }
 
 // per-site work shared by the tile pass and the sweep
 template <int ST>
 __device__ __forceinline__ void adj_site(const AdjLatticeArgs& a, int s, bool hot, bool sweep,
-                                         float& dom) {
+                                         float& dom_p, float& dom_m) {
   using T = typename Store<ST>::T;
   const int x = s % a.nx;
   const int t = s / a.nx;
@@ -129,21 +140,26 @@ __device__ __forceinline__ void adj_site(const AdjLatticeArgs& a, int s, bool ho
   }
   // the noise does not depend on F, so only the sweep needs its terms
   const bool noise = sweep && a.kT > 0.f;
-  float mp = 0.f;   // sum_i mu_i p_i of the noise pattern
+  float mpe = 0.f, mpo = 0.f;   // sum_i mu_i pe_i, sum_i mu_i po_i of the noise patterns
   if (noise) {
-    float pn[19];
-    noise_pattern(a.seed0, a.seed1, a.step, s, pn);
+    float pe[19], po[19];
+    noise_patterns(a.seed0, a.seed1, a.step, s, pe, po);
 #pragma unroll
-    for (int i = 0; i < 19; ++i) mp += mu[i] * pn[i];
+    for (int i = 0; i < 19; ++i) {
+      mpe += mu[i] * pe[i];
+      mpo += mu[i] * po[i];
+    }
   }
   float phx, phy, phz, rho, jx, jy, jz;
-  collide_adjoint(mu, g, Fx, Fy, Fz, a.rho0, a.omega, a.pref, phx, phy, phz, dom, rho, jx, jy, jz);
+  collide_adjoint(mu, g, Fx, Fy, Fz, a.rho0, a.omega, a.omega_m, phx, phy, phz, dom_p, dom_m, rho,
+                  jx, jy, jz);
   if (noise) {
-    const float A = noise_amp(a.kT, rho, a.omega);
-    const float lr = mp * A / (2.0f * rho);
+    const float Ap = noise_amp(a.kT, rho, a.omega), Am = noise_amp(a.kT, rho, a.omega_m);
+    const float lr = (mpe * Ap + mpo * Am) / (2.0f * rho);
 #pragma unroll
     for (int i = 0; i < 19; ++i) mu[i] += lr;
-    dom += mp * A * (1.0f - a.omega) / (a.omega * (2.0f - a.omega));
+    dom_p += mpe * Ap * (1.0f - a.omega) / (a.omega * (2.0f - a.omega));
+    dom_m += mpo * Am * (1.0f - a.omega_m) / (a.omega_m * (2.0f - a.omega_m));
   }
   if (!sweep) {
     a.phi[s] = phx;
@@ -208,8 +224,8 @@ __global__ __launch_bounds__(256) void k_adj_tiles(AdjLatticeArgs a) {
   const int n = *a.hot_count;
   for (int k = wave; k < n; k += nwave) {
     const int s = (a.hot_list[k] << kTileShift) + lane;
-    float dom;
-    if (s < a.S) adj_site<ST>(a, s, true, false, dom);
+    float dp, dm;
+    if (s < a.S) adj_site<ST>(a, s, true, false, dp, dm);
   }
 }
 
@@ -217,13 +233,17 @@ __global__ __launch_bounds__(256) void k_adj_tiles(AdjLatticeArgs a) {
 template <int ST>
 __global__ __launch_bounds__(kSweepBlock) void k_adj_sweep(AdjLatticeArgs a) {
   const int s = blockIdx.x * kSweepBlock + threadIdx.x;
-  float dom = 0.f;
+  float dp = 0.f, dm = 0.f;
   if (s < a.S) {
     const bool hot = a.tile_flag != nullptr && a.tile_flag[s >> kTileShift] != 0u;
-    adj_site<ST>(a, s, hot, true, dom);
+    adj_site<ST>(a, s, hot, true, dp, dm);
   }
-  const double b = block_sum((double)dom);
-  if (threadIdx.x == 0) a.dom_part[blockIdx.x] = b;
+  const double bp = block_sum((double)dp);
+  const double bm = block_sum((double)dm);
+  if (threadIdx.x == 0) {
+    a.dom_part[blockIdx.x] = bp;
+    a.dom_part[gridDim.x + blockIdx.x] = bm;
+  }
 }
 
 // ---- atoms ------------------------------------------------------------------------------------
@@ -381,17 +401,23 @@ __global__ __launch_bounds__(256) void k_adj_spread(AdjSpreadArgs a) {
   }
 }
 
-// acc[0] += sum of n0 partials, acc[1] += sum of n1 partials (fixed order, one workgroup)
+// acc[0] += sum of the n0 partials p0; acc[1], acc[2] += sums of the two rows of n1 partials
+// p1 (fixed order, one workgroup)
 __global__ __launch_bounds__(256) void k_adj_reduce(const double* p0, int n0, const double* p1, int n1,
                                                     double* acc) {
-  double s0 = 0.0, s1 = 0.0;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
   for (int k = threadIdx.x; k < n0; k += 256) s0 += p0[k];
-  for (int k = threadIdx.x; k < n1; k += 256) s1 += p1[k];
+  for (int k = threadIdx.x; k < n1; k += 256) {
+    s1 += p1[k];
+    s2 += p1[n1 + k];
+  }
   s0 = block_sum(s0);
   s1 = block_sum(s1);
+  s2 = block_sum(s2);
   if (threadIdx.x == 0) {
     acc[0] += s0;
     acc[1] += s1;
+    acc[2] += s2;
   }
 }
 
@@ -413,7 +439,7 @@ static AdjLatticeArgs lattice_args(lb_ctx* c, const AdjointBuffers& b) {
   a.S = (int)g.S;
   a.rho0 = c->p.rho0;
   a.omega = c->omega;
-  a.pref = 1.0f - 0.5f * c->omega;
+  a.omega_m = c->omega_m;
   a.bf_kind = c->p.bf_kind;
   a.fext_tab = (const float*)(c->ws + c->lay.fext_tab);
   a.fext_field = (const float*)(c->ws + c->lay.fext_field);

@@ -205,20 +205,26 @@ __device__ __forceinline__ void site_normals(uint32_t seed0, uint32_t seed1, int
   }
 }
 
-// xi_i / A: the unit-amplitude noise pattern of one site and step
-__device__ __forceinline__ void noise_pattern(uint32_t seed0, uint32_t seed1, int64_t step, int site,
-                                              float p[19]) {
+// The unit-amplitude noise patterns of one site and step: pe from the modes even under
+// c -> -c, po from the odd ones (k = 10..15); the noise is A+ pe + A- po, with A- = A+ unless
+// the two-relaxation-time collision relaxes the odd modes at omega-.
+__device__ __forceinline__ void noise_patterns(uint32_t seed0, uint32_t seed1, int64_t step, int site,
+                                               float pe[19], float po[19]) {
   float z[16];
   site_normals(seed0, seed1, step, site, z);
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
-    float acc = 0.f;
+    float ae = 0.f, ao = 0.f;
 #pragma unroll
     for (int k = 4; k < 19; ++k) {
       const float e = mode_poly(k, CX[i], CY[i], CZ[i]) * mode_inv_sqrt_norm(k);
-      if (e != 0.f) acc += e * z[k - 4];
+      if (e != 0.f) {
+        if (k >= 10 && k <= 15) ao += e * z[k - 4];
+        else ae += e * z[k - 4];
+      }
     }
-    p[i] = WQ[i] * acc;
+    pe[i] = WQ[i] * ae;
+    po[i] = WQ[i] * ao;
   }
 }
 
@@ -226,6 +232,41 @@ __device__ __forceinline__ void noise_pattern(uint32_t seed0, uint32_t seed1, in
 __device__ __forceinline__ float noise_amp(float kT, float rho, float omega) {
   const float g = 1.0f - omega;
   return sqrtf(3.0f * rho * kT * (1.0f - g * g));
+}
+
+// opposite velocity index: c_opp(i) = -c_i
+constexpr int OPP(int i) { return i == 0 ? 0 : (i % 2 ? i + 1 : i - 1); }
+
+// The two-relaxation-time variant: with d_i = g_i - g_eq_i + s_i/2 (s_i the Guo source before
+// its prefactor) split into parts even and odd under c -> -c,
+//   g*_i = g_i + s_i - omega+ d+_i - omega- d-_i = g_i + s_i - a d_i - b d_opp(i),
+// a = (omega+ + omega-)/2, b = (omega+ - omega-)/2; omega- = omega+ is the BGK collision.
+__device__ __forceinline__ bool collide_trt(float g[19], float Fx, float Fy, float Fz, float rho0,
+                                            float omega_p, float omega_m) {
+  float drho, jx, jy, jz;
+  moments(g, drho, jx, jy, jz);
+  const float rho = rho0 + drho;
+  const float inv = 1.0f / rho;
+  const float ux = (jx + 0.5f * Fx) * inv;
+  const float uy = (jy + 0.5f * Fy) * inv;
+  const float uz = (jz + 0.5f * Fz) * inv;
+  const float uu = ux * ux + uy * uy + uz * uz;
+  const float uF = ux * Fx + uy * Fy + uz * Fz;
+  const float base = drho - 1.5f * rho * uu;
+  float d[19];
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const float cu = cdot<0>(ux, uy, uz, CX[i], CY[i], CZ[i]);
+    const float cF = cdot<0>(Fx, Fy, Fz, CX[i], CY[i], CZ[i]);
+    const float geq = WQ[i] * (base + rho * (3.0f * cu + 4.5f * cu * cu));
+    const float si = WQ[i] * (3.0f * (cF - uF) + 9.0f * cu * cF);
+    d[i] = g[i] - geq + 0.5f * si;
+    g[i] += si;
+  }
+  const float a = 0.5f * (omega_p + omega_m), b = 0.5f * (omega_p - omega_m);
+#pragma unroll
+  for (int i = 0; i < 19; ++i) g[i] -= a * d[i] + b * d[OPP(i)];
+  return __builtin_isfinite(drho + jx + jy + jz);
 }
 
 __device__ __forceinline__ void external_force(int bf_kind, const float* tab, const float* field,

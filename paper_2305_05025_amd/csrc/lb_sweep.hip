@@ -37,9 +37,10 @@ struct SweepArgs {
   float kT;                    // thermal noise (NOISE instances only)
   uint32_t seed0, seed1;
   int64_t step;
+  float omega_m;               // rate of the odd part (TRT instances only)
 };
 
-template <int ST, bool NOISE>
+template <int ST, bool NOISE, bool TRT>
 __device__ __forceinline__ void sweep_site(const SweepArgs& a, int s, bool hot) {
   using T = typename Store<ST>::T;
   const int x = s % a.nx;
@@ -68,13 +69,17 @@ __device__ __forceinline__ void sweep_site(const SweepArgs& a, int s, bool hot) 
 #pragma unroll
     for (int i = 0; i < 19; ++i) rho += g[i];
   }
-  if (!collide(g, Fx, Fy, Fz, a.rho0, a.omega, a.pref)) atomicOr(a.err, kErrNonFinite);
+  bool ok;
+  if constexpr (TRT) ok = collide_trt(g, Fx, Fy, Fz, a.rho0, a.omega, a.omega_m);
+  else ok = collide(g, Fx, Fy, Fz, a.rho0, a.omega, a.pref);
+  if (!ok) atomicOr(a.err, kErrNonFinite);
   if constexpr (NOISE) {
-    float xi[19];
-    noise_pattern(a.seed0, a.seed1, a.step, s, xi);
-    const float A = noise_amp(a.kT, rho, a.omega);
+    float pe[19], po[19];
+    noise_patterns(a.seed0, a.seed1, a.step, s, pe, po);
+    const float Ap = noise_amp(a.kT, rho, a.omega);
+    const float Am = TRT ? noise_amp(a.kT, rho, a.omega_m) : Ap;
 #pragma unroll
-    for (int i = 0; i < 19; ++i) g[i] += A * xi[i];
+    for (int i = 0; i < 19; ++i) g[i] += Ap * pe[i] + Am * po[i];
   }
   T* out = reinterpret_cast<T*>(a.fout);
 #pragma unroll
@@ -82,12 +87,20 @@ __device__ __forceinline__ void sweep_site(const SweepArgs& a, int s, bool hot) 
 }
 
 // One thread per site, in site order.
-template <int ST, bool NOISE>
+template <int ST, bool NOISE, bool TRT>
 __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
   const int s = blockIdx.x * kSweepBlock + threadIdx.x;
   if (s >= a.S) return;
   const bool hot = a.tile_flag != nullptr && a.tile_flag[s >> kTileShift] != 0u;
-  sweep_site<ST, NOISE>(a, s, hot);
+  sweep_site<ST, NOISE, TRT>(a, s, hot);
+}
+
+template <int ST>
+void launch_sweep_st(bool noise, bool trt, dim3 grid, dim3 block, hipStream_t st, const SweepArgs& a) {
+  if (noise && trt) hipLaunchKernelGGL((k_sweep<ST, true, true>), grid, block, 0, st, a);
+  else if (noise) hipLaunchKernelGGL((k_sweep<ST, true, false>), grid, block, 0, st, a);
+  else if (trt) hipLaunchKernelGGL((k_sweep<ST, false, true>), grid, block, 0, st, a);
+  else hipLaunchKernelGGL((k_sweep<ST, false, false>), grid, block, 0, st, a);
 }
 
 // ---- readback -------------------------------------------------------------------------------
@@ -325,21 +338,13 @@ hipError_t launch_sweep(lb_ctx* c, const void* fin, void* fout, hipStream_t st) 
   a.seed0 = c->p.seed[0];
   a.seed1 = c->p.seed[1];
   a.step = c->step;
+  a.omega_m = c->omega_m;
   const dim3 block(kSweepBlock), grid(g.nblocks);
-  const bool noise = c->p.kT > 0.0f;
+  const bool noise = c->p.kT > 0.0f, trt = c->p.trt_magic > 0.0f;
   switch (c->p.storage) {
-    case LB_STORE_F32:
-      if (noise) hipLaunchKernelGGL((k_sweep<LB_STORE_F32, true>), grid, block, 0, st, a);
-      else hipLaunchKernelGGL((k_sweep<LB_STORE_F32, false>), grid, block, 0, st, a);
-      break;
-    case LB_STORE_F16:
-      if (noise) hipLaunchKernelGGL((k_sweep<LB_STORE_F16, true>), grid, block, 0, st, a);
-      else hipLaunchKernelGGL((k_sweep<LB_STORE_F16, false>), grid, block, 0, st, a);
-      break;
-    default:
-      if (noise) hipLaunchKernelGGL((k_sweep<LB_STORE_BF16, true>), grid, block, 0, st, a);
-      else hipLaunchKernelGGL((k_sweep<LB_STORE_BF16, false>), grid, block, 0, st, a);
-      break;
+    case LB_STORE_F32: launch_sweep_st<LB_STORE_F32>(noise, trt, grid, block, st, a); break;
+    case LB_STORE_F16: launch_sweep_st<LB_STORE_F16>(noise, trt, grid, block, st, a); break;
+    default: launch_sweep_st<LB_STORE_BF16>(noise, trt, grid, block, st, a); break;
   }
   return hipGetLastError();
 }

@@ -107,6 +107,7 @@ static std::string validate(const lb_params* p) {
   if (p->flags & ~(LB_FLAG_CHECK_FINITE | LB_FLAG_SINGLE_STREAM))
     return "flags holds an unknown bit";
   if (!finite(p->kT) || p->kT < 0.0f) return "kT must be finite and >= 0";
+  if (!finite(p->trt_magic) || p->trt_magic < 0.0f) return "trt_magic must be finite and >= 0";
   if (!finite(p->rho0) || !(p->rho0 > 0.0f)) return "rho0 must be finite and > 0";
   if (p->storage < LB_STORE_F32 || p->storage > LB_STORE_BF16) return "unknown storage format";
   if (p->bf_kind < LB_BF_NONE || p->bf_kind > LB_BF_FIELD) return "unknown body-force kind";
@@ -264,6 +265,9 @@ lb_status lb_init(const lb_params* p, void* workspace, size_t workspace_bytes, c
   c->dcur = 0;
   c->step = 0;
   c->omega = 1.0f / p->tau;
+  c->omega_m = p->trt_magic > 0.0f
+                   ? (float)(1.0 / (0.5 + (double)p->trt_magic / ((double)p->tau - 0.5)))
+                   : c->omega;
 
   char* ws = c->ws;
   // zero everything the step relies on being zero
@@ -617,8 +621,8 @@ AdjLayout plan_adjoint(const lb_ctx* c, int k) {
     l.lv[q] = take(12 * N);
   }
   l.dg_part = take(8 * (size_t)adjoint_atom_blocks(c));
-  l.dom_part = take(8 * (size_t)c->geo.nblocks);
-  l.acc = take(16);
+  l.dom_part = take(16 * (size_t)c->geo.nblocks);
+  l.acc = take(24);
   l.total = off;
   return l;
 }
@@ -676,7 +680,7 @@ lb_status lb_backward(lb_ctx* c, const void* ckpts, int32_t n_steps, int32_t k, 
   c->astream = c->fstream = c->stream;
   if ((st = lb_state_save(c, A + L.final_state)) != LB_OK) goto restore;
   if ((e = launch_zero(A + L.lam[0], 19 * (size_t)c->geo.plane * 4, c->stream)) != hipSuccess ||
-      (e = launch_zero(A + L.acc, 16, c->stream)) != hipSuccess ||
+      (e = launch_zero(A + L.acc, 24, c->stream)) != hipSuccess ||
       (dL_db && (e = launch_zero(dL_db, 12 * (size_t)c->geo.S, c->stream)) != hipSuccess) ||
       (e = hipMemcpyAsync(A + L.lx[0], dL_dX, 4 * N3, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess ||
       (e = dL_dv ? hipMemcpyAsync(A + L.lv[0], dL_dv, 4 * N3, hipMemcpyDeviceToDevice, c->stream)
@@ -757,15 +761,24 @@ lb_status lb_backward(lb_ctx* c, const void* ckpts, int32_t n_steps, int32_t k, 
       st = hip_fail(c, e, "adjoint output");
       goto restore;
     }
-    double acc[2];
-    if ((e = hipMemcpyAsync(acc, A + L.acc, 16, hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+    double acc[3];
+    if ((e = hipMemcpyAsync(acc, A + L.acc, 24, hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
         (e = hipStreamSynchronize(c->stream)) != hipSuccess) {
       st = hip_fail(c, e, "adjoint result");
       goto restore;
     }
     *dL_dgamma = acc[0];
-    // omega = 1/tau
-    *dL_dtau = -acc[1] / ((double)c->p.tau * (double)c->p.tau);
+    // omega+ = 1/tau; omega- = omega+ (BGK) or 1/(1/2 + magic/(tau - 1/2)), whose derivative
+    // is omega-^2 magic/(tau - 1/2)^2
+    const double tau = c->p.tau, magic = c->p.trt_magic;
+    double dtau = -acc[1] / (tau * tau);
+    if (magic > 0.0) {
+      const double om = 1.0 / (0.5 + magic / (tau - 0.5));
+      dtau += acc[2] * om * om * magic / ((tau - 0.5) * (tau - 0.5));
+    } else {
+      dtau -= acc[2] / (tau * tau);
+    }
+    *dL_dtau = dtau;
   }
 restore:
   c->couple_u = nullptr;

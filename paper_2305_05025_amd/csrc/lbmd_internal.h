@@ -97,6 +97,7 @@ struct lb_ctx {
   int dcur;       // which displacement buffer holds X^n - x0
   int64_t step;
   float omega;    // 1 / tau
+  float omega_m;  // rate of the odd part under the two-relaxation-time collision (= omega for BGK)
   std::string err;
   // second stream for the atom work that overlaps the sweep, and its fork/join events
   hipStream_t astream = nullptr;  // atom stream (the caller's stream when single-stream)
@@ -143,9 +144,9 @@ struct AdjointBuffers {
   float* phi;            // [3][plane] dL/dF on flagged tiles
   float* luc;            // [3][plane] dL/du_c on flagged tiles
   float* db;             // [3][S] dL/dF_ext accumulated, or NULL
-  double* dom_part;      // [nblocks]
+  double* dom_part;      // [2][nblocks]: dL/domega+, dL/domega- per workgroup
   double* dg_part;       // [adjoint_atom_blocks]
-  double* acc;           // [2]: dL/dgamma, dL/domega
+  double* acc;           // [3]: dL/dgamma, dL/domega+, dL/domega-
   const float* U;        // [N][3]
   float* lU;             // [N][3]
   float4* lf;            // [N]
