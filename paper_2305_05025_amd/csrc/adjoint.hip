@@ -80,7 +80,6 @@ __device__ __forceinline__ void collide_adjoint(float mu[19], const float g[19],
   const float uF = ux * Fx + uy * Fy + uz * Fz;
   const float ca = 0.5f * (omega_p + omega_m), cb = 0.5f * (omega_p - omega_m);
   float lrho_e = 0.f, lux = 0.f, luy = 0.f, luz = 0.f, lfx = 0.f, lfy = 0.f, lfz = 0.f;
-  float nu[19];
   dom_p = dom_m = 0.f;
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
@@ -88,7 +87,6 @@ __device__ __forceinline__ void collide_adjoint(float mu[19], const float g[19],
     const float cF = cdot<0>(Fx, Fy, Fz, CX[i], CY[i], CZ[i]);
     const float n = ca * mu[i] + cb * mu[OPP(i)];
     const float k = mu[i] - 0.5f * n;
-    nu[i] = n;
     const float geq = WQ[i] * (drho + rho * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu));
     const float si = WQ[i] * (3.0f * (cF - uF) + 9.0f * cu * cF);
     const float d = g[i] - geq + 0.5f * si;
@@ -112,9 +110,16 @@ __device__ __forceinline__ void collide_adjoint(float mu[19], const float g[19],
   phx = lfx + 0.5f * ljx;
   phy = lfy + 0.5f * ljy;
   phz = lfz + 0.5f * ljz;
+  // a_i = mu_i - nu_i + l_rho + c_i . l_j, nu recomputed from the old mu of i and its
+  // opposite, so each opposite pair is updated together
 #pragma unroll
-  for (int i = 0; i < 19; ++i)
-    mu[i] = mu[i] - nu[i] + lrho + cdot<0>(ljx, ljy, ljz, CX[i], CY[i], CZ[i]);
+  for (int i = 0; i < 19; ++i) {
+    if (i != 0 && (i & 1) == 0) continue;
+    const int o = OPP(i);
+    const float mi = mu[i], mo = mu[o];
+    mu[i] = mi - (ca * mi + cb * mo) + lrho + cdot<0>(ljx, ljy, ljz, CX[i], CY[i], CZ[i]);
+    if (o != i) mu[o] = mo - (ca * mo + cb * mi) + lrho + cdot<0>(ljx, ljy, ljz, CX[o], CY[o], CZ[o]);
+  }
 }
 
 // per-site work shared by the tile pass and the sweep
@@ -366,33 +371,76 @@ __global__ __launch_bounds__(256) void k_adj_spread(AdjSpreadArgs a) {
     const int t = s / nx;
     const int y = t % ny;
     const int z = t / ny;
-    float sx = 0.f, sy = 0.f, sz = 0.f;
+    // the 8 candidate base nodes; counts and first two list entries loaded up front
+    int base[8], nb[8], e0[8], e1[8];
+    bool few = true;   // every base node lists at most two atoms
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int dx = k & 1, dy = (k >> 1) & 1, dz = (k >> 2) & 1;
       const int bx = dx ? (x == 0 ? nx - 1 : x - 1) : x;
       const int by = dy ? (y == 0 ? ny - 1 : y - 1) : y;
       const int bz = dz ? (z == 0 ? nz - 1 : z - 1) : z;
-      const int base = bx + nx * (by + ny * bz);
-      int n = a.base_count[base];
-      n = n > kBaseCap ? kBaseCap : n;
-      int ids[kBaseCap];
-      for (int q = 0; q < n; ++q) {
-        // insertion into the sorted prefix
-        int v = a.base_list[(size_t)base * kBaseCap + q], r = q;
-        while (r > 0 && ids[r - 1] > v) {
-          ids[r] = ids[r - 1];
-          --r;
+      base[k] = bx + nx * (by + ny * bz);
+      const int c = a.base_count[base[k]];
+      nb[k] = c > kBaseCap ? kBaseCap : c;
+      e0[k] = a.base_list[(size_t)base[k] * kBaseCap];
+      e1[k] = a.base_list[(size_t)base[k] * kBaseCap + 1];
+      few = few && c <= 2;
+    }
+    // FP32 sums in a fixed order that depends only on the lists' contents (their order comes
+    // from atomics): with at most two atoms per base node, the lower atom index of every
+    // corner (corners in order), then the higher; otherwise corner by corner, atoms in
+    // ascending index order.
+    float sx = 0.f, sy = 0.f, sz = 0.f;
+    auto term = [&](int k, int at, const float4& fr, float lx, float ly, float lz) {
+      const int dx = k & 1, dy = (k >> 1) & 1, dz = (k >> 2) & 1;
+      const float w = (dx ? fr.x : 1.0f - fr.x) * (dy ? fr.y : 1.0f - fr.y) * (dz ? fr.z : 1.0f - fr.z);
+      sx += w * lx;
+      sy += w * ly;
+      sz += w * lz;
+    };
+    if (few) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (nb[k] == 2 && e1[k] < e0[k]) {
+          const int t0 = e0[k];
+          e0[k] = e1[k];
+          e1[k] = t0;
         }
-        ids[r] = v;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        float4 fr[8];
+        float l[8][3];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {   // a corner without entry q reads atom 0, unused
+          const int at = nb[k] > q ? (q ? e1[k] : e0[k]) : 0;
+          fr[k] = a.atom_frac[at];
+          l[k][0] = a.lU[3 * at];
+          l[k][1] = a.lU[3 * at + 1];
+          l[k][2] = a.lU[3 * at + 2];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (nb[k] > q) term(k, 0, fr[k], l[k][0], l[k][1], l[k][2]);
       }
-      for (int q = 0; q < n; ++q) {
-        const int at = ids[q];
-        const float4 fr = a.atom_frac[at];
-        const float w = (dx ? fr.x : 1.0f - fr.x) * (dy ? fr.y : 1.0f - fr.y) * (dz ? fr.z : 1.0f - fr.z);
-        sx += w * a.lU[3 * at];
-        sy += w * a.lU[3 * at + 1];
-        sz += w * a.lU[3 * at + 2];
+    } else {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int n = nb[k];
+        int ids[kBaseCap];
+        for (int q = 0; q < n; ++q) {
+          // insertion into the sorted prefix
+          int v = a.base_list[(size_t)base[k] * kBaseCap + q], r = q;
+          while (r > 0 && ids[r - 1] > v) {
+            ids[r] = ids[r - 1];
+            --r;
+          }
+          ids[r] = v;
+        }
+        for (int q = 0; q < n; ++q) {
+          const int at = ids[q];
+          term(k, at, a.atom_frac[at], a.lU[3 * at], a.lU[3 * at + 1], a.lU[3 * at + 2]);
+        }
       }
     }
     a.luc[s] = sx;

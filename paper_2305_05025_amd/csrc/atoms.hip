@@ -13,22 +13,27 @@
 //               64-site tiles, append the atom to the list of its stencil base node (lower
 //               corner), and append a record of it to its neighbour-list cell
 //   k_compact   lists of the occupied cells and of the flagged tiles
-//   k_node_u    u_c at every flagged node, pulled once per node (19 loads) rather than once
-//               per atom corner
+//   k_node_compact  list of the flagged nodes (within the flagged tiles)
+//   k_node_u    u_c at every flagged node, one thread per node, pulled once per node (19
+//               loads) rather than once per atom corner
 //   k_couple    eight lanes per atom: weighted u_c of its node, xor-shuffle sum -> U,
 //               F_c = gamma (U - v)
-//   k_spread    every flagged node gathers -W F_c from the atoms listed at the 8 base nodes
+//   k_spread    every flagged node (one thread each) gathers -W F_c from the atoms listed at
+//               the 8 base nodes
 //               whose stencil covers it, summed in 2^-40 fixed point (order-independent) and
 //               stored as a float; no atomics on the force
 //   (lattice sweep: adds the spread force on flagged tiles and clears the per-step buffers)
 //   k_cell_sort each occupied cell's records in atom-index order
-//   k_forces_cells  tethers, bonds and Lennard-Jones at X^n, one wavefront per occupied
-//               cell with the 27 neighbour cells staged in LDS, FP32 sums in a fixed order
+//   k_forces_cells  tethers, bonds and the pair terms (Lennard-Jones, implicit-solvent
+//               Coulomb) at X^n, one wavefront per occupied cell with the 27 neighbour
+//               cells staged in LDS, FP32 sums in a fixed order
 //   k_integrate symplectic Euler update
 //
 // Positions are kept as the caller's unwrapped anchors x0 plus a displacement d.  Stencil
 // fractions and pair vectors are formed from small numbers only (fractions in [0, 1) and
 // small integer offsets), so they keep full FP32 precision at any box size.
+#include <climits>
+
 #include "atoms_common.h"
 
 namespace lbmd {
@@ -225,7 +230,6 @@ struct NodeArgs {
   const void* f;
   long plane;
   int nx, ny, nz, S;
-  int ntiles;
   float rho0;
   int bf_kind;
   const float* fext_tab;
@@ -337,18 +341,56 @@ __global__ __launch_bounds__(256) void k_spread(SpreadArgs a) {
     const int t = s / nx;
     const int y = t % ny;
     const int z = t / ny;
-    long long Sx = 0, Sy = 0, Sz = 0;
+    // the 8 candidate base nodes; their counts and first two list entries are loaded up front
+    // (independent loads; every site owns kBaseCap list slots, and an entry is used only
+    // below its count)
+    int base[8], nb[8], e0[8], e1[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int dx = k & 1, dy = (k >> 1) & 1, dz = (k >> 2) & 1;
       const int bx = dx ? (x == 0 ? nx - 1 : x - 1) : x;
       const int by = dy ? (y == 0 ? ny - 1 : y - 1) : y;
       const int bz = dz ? (z == 0 ? nz - 1 : z - 1) : z;
-      const int base = bx + nx * (by + ny * bz);
-      int n = a.base_count[base];
-      n = n > kBaseCap ? kBaseCap : n;
-      for (int q = 0; q < n; ++q) {
-        const int at = a.base_list[(size_t)base * kBaseCap + q];
+      base[k] = bx + nx * (by + ny * bz);
+      nb[k] = a.base_count[base[k]];
+      e0[k] = a.base_list[(size_t)base[k] * kBaseCap];
+      e1[k] = a.base_list[(size_t)base[k] * kBaseCap + 1];
+    }
+    long long Sx = 0, Sy = 0, Sz = 0;
+    // entry q of every corner in one round: the round's loads are all in flight before the
+    // first is used (a corner without entry q reads atom 0's values and skips them).  The
+    // fixed-point sum does not depend on the order of its terms.
+    auto add_round = [&](const int (&e)[8], int q) {
+      float4 fr[8];
+      float fx[8], fy[8], fz[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int at = nb[k] > q ? e[k] : 0;
+        fr[k] = a.atom_frac[at];
+        fx[k] = a.fc[3 * at];
+        fy[k] = a.fc[3 * at + 1];
+        fz[k] = a.fc[3 * at + 2];
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        if (nb[k] <= q) continue;
+        const int dx = k & 1, dy = (k >> 1) & 1, dz = (k >> 2) & 1;
+        const float w = (dx ? fr[k].x : 1.0f - fr[k].x) * (dy ? fr[k].y : 1.0f - fr[k].y) *
+                        (dz ? fr[k].z : 1.0f - fr[k].z);
+        Sx += to_fixed(-w * fx[k], kFixScale);
+        Sy += to_fixed(-w * fy[k], kFixScale);
+        Sz += to_fixed(-w * fz[k], kFixScale);
+      }
+    };
+    add_round(e0, 0);
+    add_round(e1, 1);
+    // entries 2 .. count-1 (base nodes holding more than two atoms)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int dx = k & 1, dy = (k >> 1) & 1, dz = (k >> 2) & 1;
+      const int n = nb[k] > kBaseCap ? kBaseCap : nb[k];
+      for (int q = 2; q < n; ++q) {
+        const int at = a.base_list[(size_t)base[k] * kBaseCap + q];
         const float4 fr = a.atom_frac[at];
         const float w = (dx ? fr.x : 1.0f - fr.x) * (dy ? fr.y : 1.0f - fr.y) * (dz ? fr.z : 1.0f - fr.z);
         Sx += to_fixed(-w * a.fc[3 * at], kFixScale);
@@ -391,16 +433,56 @@ struct ForceArgs {
   float* lx_out;
 };
 
-// Tethers and bonds of atom i added to its Lennard-Jones part.  Forward: the total stand-in
+// Tethers and bonds of atom i added to its pair-term part.  Forward: the total stand-in
 // force field at X^n is stored for the integration.  Adjoint (kAdj): the same terms of the
 // force Jacobian applied to the direction lf (the Jacobian is symmetric), added to lx_in.
 // For a pair term f(r) = g(|r|^2) r with r = X_i - X_j, the Jacobian block is
 // J = g I + 2 g' r r^T, and atom i receives J (lf_i - lf_j).
 template <bool kAdj>
+__device__ __forceinline__ void add_bond(const ForceArgs& a, float rx, float ry, float rz,
+                                         float4 li, float4 lj, float& Fx, float& Fy, float& Fz) {
+  const float rl = sqrtf(rx * rx + ry * ry + rz * rz);
+  const float f = -a.k_bond * (rl - a.r0_bond) / rl;
+  if constexpr (kAdj) {
+    // g = -k (1 - r0/|r|), 2 g' = -k r0 / |r|^3
+    const float ex = li.x - lj.x, ey = li.y - lj.y, ez = li.z - lj.z;
+    const float t = -a.k_bond * a.r0_bond / (rl * rl * rl) * (rx * ex + ry * ey + rz * ez);
+    Fx += f * ex + t * rx;
+    Fy += f * ey + t * ry;
+    Fz += f * ez + t * rz;
+  } else {
+    Fx += f * rx;
+    Fy += f * ry;
+    Fz += f * rz;
+  }
+}
+
+constexpr int kBondPre = 4;   // bond partners whose positions are loaded together, up front
+
+template <bool kAdj>
 __device__ __forceinline__ void bonded_and_store(const ForceArgs& a, int i, float Fx, float Fy,
                                                  float Fz) {
   const float xi = a.x0[3 * i], yi = a.x0[3 * i + 1], zi = a.x0[3 * i + 2];
   const float dxi = a.d[3 * i], dyi = a.d[3 * i + 1], dzi = a.d[3 * i + 2];
+  const int b0 = a.bond_off[i], b1 = a.bond_off[i + 1];
+  // the first kBondPre partners (atom i itself stands in for a missing one): all loads are
+  // in flight before the first is used
+  int pj[kBondPre];
+#pragma unroll
+  for (int k = 0; k < kBondPre; ++k) pj[k] = b0 + k < b1 ? a.bond_nbr[b0 + k] : i;
+  float xj[kBondPre][3], dj[kBondPre][3];
+  float4 lj[kBondPre];
+#pragma unroll
+  for (int k = 0; k < kBondPre; ++k) {
+    const int j = pj[k];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      xj[k][d] = a.x0[3 * j + d];
+      dj[k][d] = a.d[3 * j + d];
+    }
+    lj[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if constexpr (kAdj) lj[k] = a.lf[j];
+  }
   float4 li = make_float4(0.f, 0.f, 0.f, 0.f);
   if constexpr (kAdj) {
     li = a.lf[i];
@@ -412,27 +494,23 @@ __device__ __forceinline__ void bonded_and_store(const ForceArgs& a, int i, floa
     Fy -= a.k_tether * dyi;
     Fz -= a.k_tether * dzi;
   }
-  const int b0 = a.bond_off[i], b1 = a.bond_off[i + 1];
-  for (int b = b0; b < b1; ++b) {
+  // bonds in list order
+#pragma unroll
+  for (int k = 0; k < kBondPre; ++k) {
+    if (b0 + k >= b1) break;
+    add_bond<kAdj>(a, min_image((xi - xj[k][0]) + (dxi - dj[k][0]), a.L[0], a.invL[0]),
+                   min_image((yi - xj[k][1]) + (dyi - dj[k][1]), a.L[1], a.invL[1]),
+                   min_image((zi - xj[k][2]) + (dzi - dj[k][2]), a.L[2], a.invL[2]), li, lj[k],
+                   Fx, Fy, Fz);
+  }
+  for (int b = b0 + kBondPre; b < b1; ++b) {
     const int j = a.bond_nbr[b];
-    const float rx = min_image((xi - a.x0[3 * j]) + (dxi - a.d[3 * j]), a.L[0], a.invL[0]);
-    const float ry = min_image((yi - a.x0[3 * j + 1]) + (dyi - a.d[3 * j + 1]), a.L[1], a.invL[1]);
-    const float rz = min_image((zi - a.x0[3 * j + 2]) + (dzi - a.d[3 * j + 2]), a.L[2], a.invL[2]);
-    const float rl = sqrtf(rx * rx + ry * ry + rz * rz);
-    const float f = -a.k_bond * (rl - a.r0_bond) / rl;
-    if constexpr (kAdj) {
-      // g = -k (1 - r0/|r|), 2 g' = -k r0 / |r|^3
-      const float4 lj = a.lf[j];
-      const float ex = li.x - lj.x, ey = li.y - lj.y, ez = li.z - lj.z;
-      const float t = -a.k_bond * a.r0_bond / (rl * rl * rl) * (rx * ex + ry * ey + rz * ez);
-      Fx += f * ex + t * rx;
-      Fy += f * ey + t * ry;
-      Fz += f * ez + t * rz;
-    } else {
-      Fx += f * rx;
-      Fy += f * ry;
-      Fz += f * rz;
-    }
+    float4 l = make_float4(0.f, 0.f, 0.f, 0.f);
+    if constexpr (kAdj) l = a.lf[j];
+    add_bond<kAdj>(a, min_image((xi - a.x0[3 * j]) + (dxi - a.d[3 * j]), a.L[0], a.invL[0]),
+                   min_image((yi - a.x0[3 * j + 1]) + (dyi - a.d[3 * j + 1]), a.L[1], a.invL[1]),
+                   min_image((zi - a.x0[3 * j + 2]) + (dzi - a.d[3 * j + 2]), a.L[2], a.invL[2]),
+                   li, l, Fx, Fy, Fz);
   }
   if constexpr (kAdj) {
     a.lx_out[3 * i] = a.lx_in[3 * i] + Fx;
@@ -445,42 +523,60 @@ __device__ __forceinline__ void bonded_and_store(const ForceArgs& a, int i, floa
   }
 }
 
-// Lennard-Jones, cell-centric, staged in LDS.  A wavefront takes one occupied cell at a time
+// Pair terms, cell-centric, staged in LDS.  A wavefront takes one occupied cell at a time
 // (persistent over the occupied-cell list):
 //   1. lanes 0..26 find the 27 neighbour cells (with the periodic shift of each) and their
-//      counts; a wave scan gives each cell's offset in the staged list;
-//   2. the records of those cells are copied into LDS (one coalesced load per cell, issued
-//      back to back), already shifted into the home cell's frame; if they exceed the stage,
-//      cells are staged in several rounds;
+//      counts; a wave scan gives each cell's offset in the concatenation of their records;
+//   2. the records of as many whole cells as fit are read (further rounds take the rest),
+//      shifted into the home cell's frame, and those within the cut-off of the home atoms'
+//      bounding box are copied into LDS in their original order.  Lanes cover record slots,
+//      not cells: a lane finds the cell of each of its slots by a lower-bound search over
+//      the scan, so every load of a round is in flight before the first is used.  Charges
+//      (with the Coulomb term) and the adjoint's directions are staged beside the records;
 //   3. the 64 lanes are split into G = floor(64 / nh) groups of nh lanes, nh the number of
 //      home atoms (lane = group * nh + home slot; the remaining lanes idle); group g takes
 //      staged records g, g + G, ...; all lanes of a group read the same LDS record (a
-//      broadcast).
-// Each lane sums in FP32 in a fixed order (records in cell order, atom-index order inside a
-// cell); the group partials meet in LDS and group 0 adds them in ascending group order,
-// then adds tethers and bonds and stores.  Pair vectors come from exact fixed-point differences.
-// Each atom sits in exactly one cell slot, so every atom is written once.
-constexpr int kStage = 320;   // staged records per wavefront (27 cells of ~9 atoms need ~240)
+//      broadcast).  Pairs beyond the cut-off, the atom itself and excluded bonded partners
+//      contribute an exact zero (a select, so the loop has no branch).
+// The box test only drops records that no home atom can reach (it keeps a 0.1% margin over
+// FP32 rounding); every kept pair passes the same cut-off test as before, so the result
+// does not depend on it.  Each lane sums in FP32 in a fixed order (records in cell order,
+// atom-index order inside a cell); the group partials meet in LDS and group 0 adds them in
+// ascending group order, then adds tethers and bonds and stores.  Pair vectors come from
+// exact fixed-point differences.  Each atom sits in exactly one cell slot, so every atom is
+// written once.
+constexpr int kStage = 320;   // records read per staging round (27 cells of ~9 atoms: ~240)
+constexpr int kStageRounds = kStage / 64;
+constexpr int kStagePad = kStage + 64;   // room for the pair loop's read-ahead past the end
 
-template <bool kAdj>
+// kCoul: the implicit-solvent Coulomb term is on (coul2 != 0)
+template <bool kAdj, bool kCoul>
 __global__ __launch_bounds__(256) void k_forces_cells(ForceArgs a) {
-  __shared__ int4 stage_all[4][kStage];
-  const int lane = threadIdx.x & 63;
-  int4* stage = stage_all[threadIdx.x >> 6];
+  __shared__ int4 stage_all[4][kStagePad];
+  __shared__ float stage_q_all[kCoul ? 4 : 1][kCoul ? kStagePad : 1];
+  __shared__ float4 stage_l_all[kAdj ? 4 : 1][kAdj ? kStagePad : 1];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int4* stage = stage_all[wid];
+  float* stage_q = stage_q_all[kCoul ? wid : 0];
+  float4* stage_l = stage_l_all[kAdj ? wid : 0];
+  constexpr bool coul = kCoul;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  const float keep_r2 = a.lj_rc2 * 1.001f;
   const int nc0 = a.g.nc[0], nc1 = a.g.nc[1], nc2 = a.g.nc[2];
   const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6, nwave = gridDim.x * 4;
   const int nocc = *a.occ_count;
   for (int k = wave; k < nocc; k += nwave) {
-    const long cell = a.occ_cells[k];
+    const int cell = a.occ_cells[k];
     int nh = a.cell_count[cell];
     nh = nh > kCellCap ? kCellCap : nh;
     nh = nh < 1 ? 1 : nh;   // listed cells are occupied; kept for the division below
     const int ngrp = 64 / nh;
     const int grp = lane / nh, hl = lane - grp * nh;
-    const int q[3] = {(int)(cell % nc0), (int)((cell / nc0) % nc1), (int)(cell / ((long)nc0 * nc1))};
-    // this lane's home atom
+    const int cxy = cell / nc0;
+    const int q[3] = {cell - cxy * nc0, cxy % nc1, cxy / nc1};
+    // this lane's home atom (lanes 0..nh-1 hold the nh home atoms)
     const bool hv = grp < ngrp;
-    const int4 me = a.cell_rec[cell * kCellCap + (hv ? hl : 0)];
+    const int4 me = a.cell_rec[(long)cell * kCellCap + (hv ? hl : 0)];
     const int i = me.w;
     const int b0 = a.bond_off[i], b1 = a.bond_off[i + 1];
     int pb[4] = {-1, -1, -1, -1};
@@ -491,65 +587,132 @@ __global__ __launch_bounds__(256) void k_forces_cells(ForceArgs a) {
       if (deg > 2) pb[2] = a.bond_nbr[b0 + 2];
       if (deg > 3) pb[3] = a.bond_nbr[b0 + 3];
     }
-    const bool excl = a.lj_exclude_bonded && b1 > b0;
+    // atoms with more than four bonded partners check the rest of their list in the pair
+    // loop (a branch taken by the whole wavefront, rare)
+    const bool many = __ballot(hv && a.lj_exclude_bonded && b1 - b0 > 4) != 0ull;
     float4 lfi = make_float4(0.f, 0.f, 0.f, 0.f);
     if constexpr (kAdj) lfi = a.lf[i];
-    const float qi = a.coul2 != 0.f ? a.charge[i] : 0.f;
+    float qi = 0.f;
+    if constexpr (coul) qi = a.charge[i];
+    // bounding box of the home atoms (fixed point, home frame)
+    int lo[3] = {lane < nh ? me.x : INT_MAX, lane < nh ? me.y : INT_MAX, lane < nh ? me.z : INT_MAX};
+    int hi[3] = {lane < nh ? me.x : INT_MIN, lane < nh ? me.y : INT_MIN, lane < nh ? me.z : INT_MIN};
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = min(lo[d], __shfl_xor(lo[d], o, 64));
+        hi[d] = max(hi[d], __shfl_xor(hi[d], o, 64));
+      }
     float Fx = 0.f, Fy = 0.f, Fz = 0.f;
     // neighbour cells: lane l < 27 holds cell l of the 3x3x3 block
-    long nbc = 0;
+    int nbc = 0;
     int nbn = 0, shx = 0, shy = 0, shz = 0;
     if (lane < 27) {
       int cx, cy, cz;
       nbr_cell(q[0], lane % 3 - 1, a.g.n[0], nc0, cx, shx);
       nbr_cell(q[1], (lane / 3) % 3 - 1, a.g.n[1], nc1, cy, shy);
       nbr_cell(q[2], lane / 9 - 1, a.g.n[2], nc2, cz, shz);
-      nbc = cx + (long)nc0 * (cy + (long)nc1 * cz);
+      nbc = cx + nc0 * (cy + nc1 * cz);
       nbn = a.cell_count[nbc];
       nbn = nbn > kCellCap ? kCellCap : nbn;
     }
-    int pre = nbn;   // inclusive scan over lanes
+    int pre = nbn;   // inclusive scan over lanes 0..31 (only lanes 0..26 are read)
 #pragma unroll
     for (int o = 1; o < 32; o <<= 1) {
       const int t = __shfl_up(pre, o, 64);
       if (lane >= o) pre += t;
     }
+    const int pex = pre - nbn;   // first record of cell `lane` in the concatenation
     for (int kc = 0; kc < 27;) {
-      const int base = kc ? __shfl(pre, kc - 1, 64) : 0;
-      // stage cells kc .. kend-1 (as many as fit)
-      int kend = kc;
-      while (kend < 27 && __shfl(pre, kend, 64) - base <= kStage) ++kend;
-      for (int c = kc; c < kend; ++c) {
-        const int n_c = __shfl(nbn, c, 64);
-        const int off = (c ? __shfl(pre, c - 1, 64) : 0) - base;
-        const long cc = __shfl(nbc, c, 64);
-        const int sx = __shfl(shx, c, 64) << 24, sy = __shfl(shy, c, 64) << 24, sz = __shfl(shz, c, 64) << 24;
-        if (lane < n_c) {
-          int4 r = a.cell_rec[cc * kCellCap + lane];
-          // neighbour position in the home cell's frame (fixed point)
-          r.x -= sx;
-          r.y -= sy;
-          r.z -= sz;
-          stage[off + lane] = r;
+      const int base = __shfl(pex, kc, 64);
+      // cells kc .. kend-1 fit (each cell holds at most kCellCap <= kStage records, so at
+      // least one does); the cells that fit form a prefix of 0..26
+      const int kend = __popcll(__ballot(lane < 27 && pre - base <= kStage));
+      const int ntot = __shfl(pre, kend - 1, 64) - base;
+      int4 rec[kStageRounds];
+      int rc[kStageRounds];
+#pragma unroll
+      for (int r = 0; r < kStageRounds; ++r) {
+        const int t = r * 64 + lane, gt = base + t;
+        // lower bound: c = number of cells whose records all precede gt
+        int c = 0;
+#pragma unroll
+        for (int step = 16; step >= 1; step >>= 1) {
+          const int probe = c + step - 1;
+          const int pv = __shfl(pre, probe < 26 ? probe : 26, 64);
+          if (probe < 27 && pv <= gt) c += step;
         }
+        c = c < 26 ? c : 26;
+        const int j = gt - __shfl(pex, c, 64);
+        const int cc = __shfl(nbc, c, 64);
+        rc[r] = c;
+        // slots past the end read the home cell's first record (valid, unused), so the
+        // loads carry no branch
+        rec[r] = a.cell_rec[t < ntot ? (long)cc * kCellCap + j : (long)cell * kCellCap];
+      }
+      int nkeep = 0, kpos[kStageRounds];
+#pragma unroll
+      for (int r = 0; r < kStageRounds; ++r) {
+        const int c = rc[r];
+        // neighbour position in the home cell's frame (fixed point)
+        const int4 v = make_int4(rec[r].x - (__shfl(shx, c, 64) << 24),
+                                 rec[r].y - (__shfl(shy, c, 64) << 24),
+                                 rec[r].z - (__shfl(shz, c, 64) << 24), rec[r].w);
+        const float ex = (float)max(max(lo[0] - v.x, v.x - hi[0]), 0) * kCellFixInv;
+        const float ey = (float)max(max(lo[1] - v.y, v.y - hi[1]), 0) * kCellFixInv;
+        const float ez = (float)max(max(lo[2] - v.z, v.z - hi[2]), 0) * kCellFixInv;
+        const bool keep = r * 64 + lane < ntot && ex * ex + ey * ey + ez * ez < keep_r2;
+        const unsigned long long m = __ballot(keep);
+        kpos[r] = keep ? nkeep + __popcll(m & below) : -1;
+        if (keep) stage[kpos[r]] = v;
+        nkeep += __popcll(m);
+      }
+      // per-atom values of the staged records
+      if constexpr (coul) {
+        float qv[kStageRounds];
+#pragma unroll
+        for (int r = 0; r < kStageRounds; ++r) qv[r] = a.charge[rec[r].w];
+#pragma unroll
+        for (int r = 0; r < kStageRounds; ++r)
+          if (kpos[r] >= 0) stage_q[kpos[r]] = qv[r];
+      }
+      if constexpr (kAdj) {
+        float4 lv[kStageRounds];
+#pragma unroll
+        for (int r = 0; r < kStageRounds; ++r) lv[r] = a.lf[rec[r].w];
+#pragma unroll
+        for (int r = 0; r < kStageRounds; ++r)
+          if (kpos[r] >= 0) stage_l[kpos[r]] = lv[r];
       }
       wave_lds_sync();
-      const int ntot = __shfl(pre, kend - 1, 64) - base;
       if (hv) {
-        for (int c = grp; c < ntot; c += ngrp) {
-          const int4 r4 = stage[c];
+        // each record is read from LDS one iteration ahead of its use (reads past nkeep
+        // stay inside the padded stage and are not used)
+        int4 r_next = stage[grp];
+        float q_next = 0.f;
+        if constexpr (coul) q_next = stage_q[grp];
+        float4 l_next = make_float4(0.f, 0.f, 0.f, 0.f);
+        if constexpr (kAdj) l_next = stage_l[grp];
+#pragma unroll 2
+        for (int c = grp; c < nkeep; c += ngrp) {
+          const int4 r4 = r_next;
+          const float qj = q_next;
+          const float4 lj = l_next;
+          r_next = stage[c + ngrp];
+          if constexpr (coul) q_next = stage_q[c + ngrp];
+          if constexpr (kAdj) l_next = stage_l[c + ngrp];
           // pair vector X_i - X_j: exact integer difference, one rounding
           const float rx = (float)(me.x - r4.x) * kCellFixInv;
           const float ry = (float)(me.y - r4.y) * kCellFixInv;
           const float rz = (float)(me.z - r4.z) * kCellFixInv;
           const float r2 = rx * rx + ry * ry + rz * rz;
           const int j = r4.w;
-          if (!(r2 < a.lj_rc2) || j == i) continue;
-          if (excl) {
-            bool bonded = j == pb[0] || j == pb[1] || j == pb[2] || j == pb[3];
+          // excluded bonded partners (pb holds -1 where there is none)
+          bool bonded = j == pb[0] || j == pb[1] || j == pb[2] || j == pb[3];
+          if (many)
             for (int bb = b0 + 4; bb < b1; ++bb) bonded = bonded || (a.bond_nbr[bb] == j);
-            if (bonded) continue;
-          }
+          const bool use = r2 < a.lj_rc2 && j != i && !bonded;
           const float inv2 = __builtin_amdgcn_rcpf(r2);
           const float sr2 = a.lj_sigma2 * inv2;
           const float sr6 = sr2 * sr2 * sr2;
@@ -558,14 +721,15 @@ __global__ __launch_bounds__(256) void k_forces_cells(ForceArgs a) {
           // the Jacobian uses 2 g'(s)
           float gp2 = 0.f;
           if constexpr (kAdj) gp2 = 2.0f * a.lj_eps24 * (4.0f * sr6 - 14.0f * sr6 * sr6) * inv2 * inv2;
-          if (a.coul2 != 0.f) {
+          if constexpr (coul) {
             // implicit-solvent Coulomb: g = 2 k_C q_i q_j s^-2, 2 g' = -4 g / s
-            const float gc = a.coul2 * qi * a.charge[j] * inv2 * inv2;
+            const float gc = a.coul2 * qi * qj * inv2 * inv2;
             f += gc;
             if constexpr (kAdj) gp2 -= 4.0f * gc * inv2;
           }
+          f = use ? f : 0.f;
           if constexpr (kAdj) {
-            const float4 lj = a.lf[j];
+            gp2 = use ? gp2 : 0.f;
             const float ex = lfi.x - lj.x, ey = lfi.y - lj.y, ez = lfi.z - lj.z;
             const float t = gp2 * (rx * ex + ry * ey + rz * ez);
             Fx += f * ex + t * rx;
@@ -814,10 +978,11 @@ constexpr unsigned kForceGridCap = 1024;
 
 hipError_t launch_forces(lb_ctx* c) {
   const ForceArgs a = force_args(c);
-  if (a.ncell > 0)
-    hipLaunchKernelGGL(k_forces_cells<false>,
-                       dim3(std::min(persistent_grid(std::min(a.ncell, (long)a.N)), kForceGridCap)), dim3(256), 0,
-                       c->fstream, a);
+  const dim3 grid(std::min(persistent_grid(std::min(a.ncell, (long)a.N)), kForceGridCap));
+  if (a.ncell > 0 && a.coul2 != 0.f)
+    hipLaunchKernelGGL((k_forces_cells<false, true>), grid, dim3(256), 0, c->fstream, a);
+  else if (a.ncell > 0)
+    hipLaunchKernelGGL((k_forces_cells<false, false>), grid, dim3(256), 0, c->fstream, a);
   else
     hipLaunchKernelGGL(k_bonded_forces<false>, dim3(blocks(a.N, 256)), dim3(256), 0, c->fstream, a);
   return hipGetLastError();
@@ -828,9 +993,11 @@ hipError_t launch_force_hvp(lb_ctx* c, const float4* lf, const float* lx_in, flo
   a.lf = lf;
   a.lx_in = lx_in;
   a.lx_out = lx_out;
-  if (a.ncell > 0)
-    hipLaunchKernelGGL(k_forces_cells<true>, dim3(persistent_grid(std::min(a.ncell, (long)a.N))), dim3(256), 0,
-                       c->stream, a);
+  const dim3 grid(persistent_grid(std::min(a.ncell, (long)a.N)));
+  if (a.ncell > 0 && a.coul2 != 0.f)
+    hipLaunchKernelGGL((k_forces_cells<true, true>), grid, dim3(256), 0, c->stream, a);
+  else if (a.ncell > 0)
+    hipLaunchKernelGGL((k_forces_cells<true, false>), grid, dim3(256), 0, c->stream, a);
   else
     hipLaunchKernelGGL(k_bonded_forces<true>, dim3(blocks(a.N, 256)), dim3(256), 0, c->stream, a);
   return hipGetLastError();

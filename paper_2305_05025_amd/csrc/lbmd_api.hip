@@ -21,7 +21,7 @@ bool geometry(const lb_params* p, Geometry* g) {
   g->ny = p->L[1];
   g->nz = p->L[2];
   g->S = (long)p->L[0] * p->L[1] * p->L[2];
-  g->plane = (long)round_up((size_t)g->S, 64);
+  g->plane = (long)round_up((size_t)g->S, 64) + kPlanePad;
   g->nblocks = (int)((g->S + kSweepBlock - 1) / kSweepBlock);
   g->ntiles = (int)((g->S + 63) / 64);
   g->elem = elem_bytes(p->storage);

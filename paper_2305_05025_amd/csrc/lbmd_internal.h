@@ -23,6 +23,10 @@ constexpr float WQ[19] = {
 
 constexpr int kSweepBlock = 256;        // sites per sweep workgroup
 constexpr int kTileShift = 6;           // force tile = 64 sites (one wavefront of the sweep)
+// Per-site planes (populations, forces, flags) start kPlanePad elements apart beyond the
+// site count rounded to 64: with a power-of-two lattice the 19 population planes would
+// otherwise share every low address bit, and the sweep's 38 streams measured about 1% slower.
+constexpr long kPlanePad = 256;
 constexpr int kCellCap = 48;            // atoms per neighbour-list cell
 constexpr int kBaseCap = 8;             // atoms whose stencil base is one node
 constexpr float kFixScale = 1099511627776.0f;      // 2^40: fixed-point scale of spread forces
