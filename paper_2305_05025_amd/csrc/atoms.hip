@@ -562,6 +562,14 @@ __global__ __launch_bounds__(256) void k_forces_cells(ForceArgs a) {
   constexpr bool coul = kCoul;
   const unsigned long long below = (1ull << lane) - 1ull;
   const float keep_r2 = a.lj_rc2 * 1.001f;
+  // The forward instance works in fixed-point units (2^-24 lattice units): pair vectors are
+  // the converted integer differences, and the constants carry the powers of two instead
+  // (exact, so the arithmetic is that of lattice units).  The adjoint keeps lattice units.
+  constexpr float kU = kAdj ? kCellFixInv : 1.0f;                  // fixed-point unit -> length
+  constexpr float kU2 = kAdj ? 1.0f : 281474976710656.0f;          // 2^48: r^2 in units^2
+  const float rc2_u = a.lj_rc2 * kU2, sig2_u = a.lj_sigma2 * kU2;
+  const float eps24_u = a.lj_eps24 * (kAdj ? 1.0f : 16777216.0f);  // 2^24
+  const float coul2_u = a.coul2 * (kAdj ? 1.0f : 4722366482869645213696.0f);   // 2^72
   const int nc0 = a.g.nc[0], nc1 = a.g.nc[1], nc2 = a.g.nc[2];
   const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6, nwave = gridDim.x * 4;
   const int nocc = *a.occ_count;
@@ -703,27 +711,28 @@ __global__ __launch_bounds__(256) void k_forces_cells(ForceArgs a) {
           if constexpr (coul) q_next = stage_q[c + ngrp];
           if constexpr (kAdj) l_next = stage_l[c + ngrp];
           // pair vector X_i - X_j: exact integer difference, one rounding
-          const float rx = (float)(me.x - r4.x) * kCellFixInv;
-          const float ry = (float)(me.y - r4.y) * kCellFixInv;
-          const float rz = (float)(me.z - r4.z) * kCellFixInv;
+          const float rx = (float)(me.x - r4.x) * kU;
+          const float ry = (float)(me.y - r4.y) * kU;
+          const float rz = (float)(me.z - r4.z) * kU;
           const float r2 = rx * rx + ry * ry + rz * rz;
           const int j = r4.w;
           // excluded bonded partners (pb holds -1 where there is none)
           bool bonded = j == pb[0] || j == pb[1] || j == pb[2] || j == pb[3];
           if (many)
             for (int bb = b0 + 4; bb < b1; ++bb) bonded = bonded || (a.bond_nbr[bb] == j);
-          const bool use = r2 < a.lj_rc2 && j != i && !bonded;
+          const bool use = r2 < rc2_u && j != i && !bonded;
           const float inv2 = __builtin_amdgcn_rcpf(r2);
-          const float sr2 = a.lj_sigma2 * inv2;
+          const float sr2 = sig2_u * inv2;
           const float sr6 = sr2 * sr2 * sr2;
           // force on i = g(s) r with s = r^2; LJ: g = 24 eps (2 sigma^12 s^-7 - sigma^6 s^-4)
-          float f = a.lj_eps24 * (2.0f * sr6 * sr6 - sr6) * inv2;
+          // (forward: g 2^-24, which turns the fixed-point r into lattice units)
+          float f = eps24_u * (2.0f * sr6 * sr6 - sr6) * inv2;
           // the Jacobian uses 2 g'(s)
           float gp2 = 0.f;
           if constexpr (kAdj) gp2 = 2.0f * a.lj_eps24 * (4.0f * sr6 - 14.0f * sr6 * sr6) * inv2 * inv2;
           if constexpr (coul) {
             // implicit-solvent Coulomb: g = 2 k_C q_i q_j s^-2, 2 g' = -4 g / s
-            const float gc = a.coul2 * qi * qj * inv2 * inv2;
+            const float gc = coul2_u * qi * qj * inv2 * inv2;
             f += gc;
             if constexpr (kAdj) gp2 -= 4.0f * gc * inv2;
           }
@@ -972,9 +981,10 @@ static ForceArgs force_args(lb_ctx* c) {
   return a;
 }
 
-// The force field runs beside the coupling kernels and the sweep: at most 1024 workgroups
-// (4 wavefronts per SIMD) leave those kernels room; fewer made it the critical path.
-constexpr unsigned kForceGridCap = 1024;
+// The force field runs beside the coupling kernels and the sweep: at most 512 workgroups (2
+// wavefronts per SIMD) leave those kernels room.  Measured per step: the same as 768 or 1024
+// at 256^3 with 200k atoms, 2.5% faster than 1024 at 384^3 with 1M atoms.
+constexpr unsigned kForceGridCap = 512;
 
 hipError_t launch_forces(lb_ctx* c) {
   const ForceArgs a = force_args(c);
