@@ -290,6 +290,18 @@ __global__ void k_zero(uint32_t* p, size_t n_words) {
     p[i] = 0u;
 }
 
+// two equal-length word copies in one launch (the atoms' displacement and velocity)
+__global__ void k_copy_pair(uint32_t* d0, const uint32_t* s0, uint32_t* d1, const uint32_t* s1,
+                            size_t n_words) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < 2 * n_words;
+       i += (size_t)gridDim.x * blockDim.x) {
+    if (i < n_words)
+      d0[i] = s0[i];
+    else
+      d1[i - n_words] = s1[i - n_words];
+  }
+}
+
 __global__ void k_store_i64(int64_t* dst, int64_t v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v;
 }
@@ -305,6 +317,18 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
   int blocks = (int)((words + 255) / 256);
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, (uint32_t*)p, words);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_pair(void* d0, const void* s0, void* d1, const void* s1, size_t bytes,
+                            hipStream_t s) {
+  // both regions are multiples of 4 bytes (FP32 arrays)
+  const size_t words = bytes / 4;
+  if (words == 0) return hipSuccess;
+  int blocks = (int)((2 * words + 255) / 256);
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_copy_pair, dim3(blocks), dim3(256), 0, s, (uint32_t*)d0, (const uint32_t*)s0,
+                     (uint32_t*)d1, (const uint32_t*)s1, words);
   return hipGetLastError();
 }
 

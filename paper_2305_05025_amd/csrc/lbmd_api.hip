@@ -631,10 +631,7 @@ AdjLayout plan_adjoint(const lb_ctx* c, int k) {
 size_t state_atom_offset(const lb_ctx* c) { return 256 + round_up(state_pop_bytes(c), 256); }
 
 hipError_t copy_atoms(lb_ctx* c, char* dst_disp, char* dst_vel, const char* src_disp, const char* src_vel) {
-  const size_t n = 12 * (size_t)c->p.n_atoms;
-  hipError_t e = hipMemcpyAsync(dst_disp, src_disp, n, hipMemcpyDeviceToDevice, c->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(dst_vel, src_vel, n, hipMemcpyDeviceToDevice, c->stream);
-  return e;
+  return launch_copy_pair(dst_disp, src_disp, dst_vel, src_vel, 12 * (size_t)c->p.n_atoms, c->stream);
 }
 
 }  // namespace
@@ -696,11 +693,12 @@ lb_status lb_backward(lb_ctx* c, const void* ckpts, int32_t n_steps, int32_t k, 
         st = hip_fail(c, e, "checkpoint copy");
         goto restore;
       }
-      // recompute the segment, each step's output going straight into the next slot
+      // recompute the segment, each step's output going straight into the next slot (the
+      // atoms' state of step q + 1 is still in the context when step q + 1 starts)
       for (int q = 0; q + 1 < len; ++q) {
         char* disp = c->ws + c->lay.disp[c->dcur];
         char* vel = c->ws + c->lay.vel;
-        if ((e = copy_atoms(c, disp, vel, slot(q) + aoff, slot(q) + aoff + abytes)) != hipSuccess) {
+        if (q == 0 && (e = copy_atoms(c, disp, vel, slot(q) + aoff, slot(q) + aoff + abytes)) != hipSuccess) {
           st = hip_fail(c, e, "recompute copy");
           goto restore;
         }

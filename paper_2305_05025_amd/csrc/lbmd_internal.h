@@ -118,6 +118,8 @@ namespace lbmd {
 
 // ---- kernel launchers (lb_sweep.hip) ----
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_copy_pair(void* d0, const void* s0, void* d1, const void* s1, size_t bytes,
+                            hipStream_t s);
 hipError_t launch_sweep(lb_ctx* c, const void* fin, void* fout, hipStream_t st);
 hipError_t launch_read_fields(lb_ctx* c, float* rho, float* u);
 hipError_t launch_read_populations(lb_ctx* c, float* g);

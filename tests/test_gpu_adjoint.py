@@ -135,3 +135,37 @@ def test_autograd_function_matches_direct_call(O):
     db = b.grad.double().cpu().numpy()
     for df, ref in zip(dfields, dbs):
         assert abs(float((db * df).sum()) - ref) < 1e-3 * abs(ref)
+
+
+def _max_stencil_records(w):
+    """Largest number of atom records in the 27 neighbour-list cells around an occupied cell
+    (cells as wide as the cut-off allows, periodic)."""
+    L = np.array(w.L)
+    nc = np.floor(L / w.lj_rc).astype(int)
+    x = np.mod(w.x0.astype(np.float64), L)
+    c = np.minimum(np.floor(x / (L / nc)).astype(int), nc - 1)
+    cnt = np.zeros(tuple(nc[::-1]), int)
+    np.add.at(cnt, (c[:, 2], c[:, 1], c[:, 0]), 1)
+    occ = np.argwhere(cnt > 0)
+    tot = np.zeros(len(occ), int)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                tot += cnt[(occ[:, 0] + dz) % nc[2], (occ[:, 1] + dy) % nc[1], (occ[:, 2] + dx) % nc[0]]
+    return int(tot.max())
+
+
+def test_adjoint_dense_globule_two_staging_rounds(O):
+    """A 700-atom globule in a 16^3 box: around its densest cells the 27 neighbour cells hold
+    more than the 320 records one staging round takes, so the force field and its
+    Hessian-vector product stage them in two rounds.  10 steps in segments of 4."""
+    from workloads import globule_workload
+    L = 16
+    w = globule_workload(L, 1, 700, seed=8, tau=0.7, gamma=0.15)
+    assert _max_stencil_records(w) > 320
+    rng = np.random.default_rng(17)
+    field = rng.normal(0, 1e-5, size=(3, L, L, L))
+    D = np.array([0.48, 0.6, -0.64])
+    dfields = _dfields(rng, field.shape)
+    outs, _ = _gpu_grads(w, field, D, 10, 4)
+    _check(outs, _oracle_grads(O, w, field, D, 10, dfields), dfields, 1e-3)
