@@ -89,8 +89,11 @@ __device__ __forceinline__ void compact_block(bool keep, int item, int* list, in
 
 // The flagged nodes inside the flagged tiles.  Each workgroup takes a contiguous range of the
 // tile list and each of its wavefronts a contiguous quarter of that, so the list keeps the
-// tiles' order within a workgroup; the workgroup counts its flagged nodes, reserves room with
-// a single counter atomic, then writes them in a second pass over the same tiles.
+// tiles' order within a workgroup (consecutive entries are neighbouring sites, which the node
+// kernels' gathers rely on); the workgroup counts its flagged nodes, reserves room with a
+// single counter atomic, then writes them in a second pass over the same tiles.  Tiles are
+// visited four at a time with their loads issued together: this kernel runs beside the
+// sweep, where every memory round trip is long.
 struct NodeCompactArgs {
   int S;
   const int* occ_tiles;
@@ -98,6 +101,24 @@ struct NodeCompactArgs {
   int* node_list;
   int* occ_count;    // [1] tiles (in), [2] nodes (out)
 };
+
+constexpr int kNodeBatch = 4;
+
+// flags of this lane's site in tiles k .. k+3 of the list (0 past t1)
+__device__ __forceinline__ void tile_flags(const NodeCompactArgs& a, int k, int t1, int lane,
+                                           int (&s)[kNodeBatch], bool (&f)[kNodeBatch]) {
+  int tile[kNodeBatch];
+#pragma unroll
+  for (int j = 0; j < kNodeBatch; ++j) tile[j] = k + j < t1 ? a.occ_tiles[k + j] : -1;
+  uint8_t v[kNodeBatch];
+#pragma unroll
+  for (int j = 0; j < kNodeBatch; ++j) {
+    s[j] = (tile[j] << kTileShift) + lane;
+    v[j] = a.node_flag[tile[j] >= 0 && s[j] < a.S ? s[j] : 0];   // unconditional load
+  }
+#pragma unroll
+  for (int j = 0; j < kNodeBatch; ++j) f[j] = tile[j] >= 0 && s[j] < a.S && v[j] != 0;
+}
 
 __global__ __launch_bounds__(256) void k_node_compact(NodeCompactArgs a) {
   __shared__ int wave_n[4];
@@ -109,9 +130,12 @@ __global__ __launch_bounds__(256) void k_node_compact(NodeCompactArgs a) {
   const int t0 = min((int)blockIdx.x * chunk + wid * q, ntile);
   const int t1 = min(min(t0 + q, (int)(blockIdx.x + 1) * chunk), ntile);
   int n = 0;
-  for (int k = t0; k < t1; ++k) {
-    const int s = (a.occ_tiles[k] << kTileShift) + lane;
-    n += __popcll(__ballot(s < a.S && a.node_flag[s] != 0));
+  for (int k = t0; k < t1; k += kNodeBatch) {
+    int s[kNodeBatch];
+    bool f[kNodeBatch];
+    tile_flags(a, k, t1, lane, s, f);
+#pragma unroll
+    for (int j = 0; j < kNodeBatch; ++j) n += __popcll(__ballot(f[j]));
   }
   if (lane == 0) wave_n[wid] = n;
   __syncthreads();
@@ -122,12 +146,16 @@ __global__ __launch_bounds__(256) void k_node_compact(NodeCompactArgs a) {
   __syncthreads();
   int off = block_base;
   for (int w = 0; w < wid; ++w) off += wave_n[w];
-  for (int k = t0; k < t1; ++k) {
-    const int s = (a.occ_tiles[k] << kTileShift) + lane;
-    const bool keep = s < a.S && a.node_flag[s] != 0;
-    const unsigned long long m = __ballot(keep);
-    if (keep) a.node_list[off + __popcll(m & ((1ull << lane) - 1ull))] = s;
-    off += __popcll(m);
+  for (int k = t0; k < t1; k += kNodeBatch) {
+    int s[kNodeBatch];
+    bool f[kNodeBatch];
+    tile_flags(a, k, t1, lane, s, f);
+#pragma unroll
+    for (int j = 0; j < kNodeBatch; ++j) {
+      const unsigned long long m = __ballot(f[j]);
+      if (f[j]) a.node_list[off + __popcll(m & ((1ull << lane) - 1ull))] = s[j];
+      off += __popcll(m);
+    }
   }
 }
 
@@ -850,7 +878,7 @@ hipError_t launch_compact(lb_ctx* c) {
   b.node_flag = (const uint8_t*)(c->ws + c->lay.node_flag);
   b.node_list = (int*)(c->ws + c->lay.node_list[c->step & 1]);
   b.occ_count = a.occ_count;
-  hipLaunchKernelGGL(k_node_compact, dim3(256), dim3(256), 0, c->astream, b);
+  hipLaunchKernelGGL(k_node_compact, dim3(1024), dim3(256), 0, c->astream, b);
   return hipGetLastError();
 }
 
