@@ -41,6 +41,10 @@
 // double (the oracle proper), float (to measure the FP32 error floor) or Dual (forward-mode
 // derivative of a loss with respect to gamma, tau or a body-force direction).
 //
+// Velocity sets: the paper's D3Q19, and (as the higher-order set its outlook in Section 4
+// proposes) the 27-speed D3Q27 with the same equilibrium, forcing and collision written over
+// its velocities and weights.  The thermal noise is defined on the D3Q19 moment basis only.
+//
 // Parity status: every sub-step is pinned by the CPU tests (closed forms, invariants,
 // brute force); the long coupled trajectory itself has no published values to pin
 // against beyond those invariants.
@@ -54,20 +58,36 @@
 namespace {
 
 // ---------------------------------------------------------------------------------------
-// D3Q19 velocity set: the rest velocity, the 6 face neighbours and the 12 edge neighbours.
+// Velocity sets.  D3Q19: the rest velocity, the 6 face neighbours and the 12 edge
+// neighbours (the first 19 rows below).  D3Q27 adds the 8 corner neighbours.
 // Ordering: opposite(i) = i + 1 for odd i, i - 1 for even i > 0.
+// Weights: D3Q19 1/3, 1/18, 1/36; D3Q27 8/27, 2/27, 1/54, 1/216 (rest, face, edge, corner).
 // ---------------------------------------------------------------------------------------
-const int CV[19][3] = {
+constexpr int QMAX = 27;
+const int CV[QMAX][3] = {
     {0, 0, 0},
     {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
     {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
     {1, 0, 1}, {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
-    {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
-const double WV[19] = {
+    {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1},
+    {1, 1, 1}, {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1},
+    {1, -1, 1}, {-1, 1, -1}, {-1, 1, 1}, {1, -1, -1}};
+const double WV19[19] = {
     1.0 / 3.0,
     1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
     1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
     1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+const double WV27[27] = {
+    8.0 / 27.0,
+    2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0,
+    1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0,
+    1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0,
+    1.0 / 216.0, 1.0 / 216.0, 1.0 / 216.0, 1.0 / 216.0,
+    1.0 / 216.0, 1.0 / 216.0, 1.0 / 216.0, 1.0 / 216.0};
+// weight w_i of velocity set Q (19 or 27)
+inline double wq(int Q, int i) { return Q == 27 ? WV27[i] : WV19[i]; }
+// the D3Q19 weights (the moment basis of the thermal noise is defined on them)
+inline double WV(int i) { return WV19[i]; }
 
 // ---------------------------------------------------------------------------------------
 // Forward-mode dual number: value + derivative along one seeded direction.
@@ -102,6 +122,7 @@ inline Dual sqrtT(Dual x) { return sqrt(x); }
 // ---------------------------------------------------------------------------------------
 template <class T>
 struct Model {
+  int Q = 19;                                // velocity set: 19 or 27
   int L[3];
   long S;
   T tau, rho0, gamma, mass, k_tether, k_bond, r0_bond, lj_eps, lj_sigma, lj_rc;
@@ -121,7 +142,7 @@ struct Model {
 template <class T>
 struct State {
   int64_t step = 0;   // step index (counts the noise)
-  std::vector<T> g;   // pre-collision populations, deviation form, [19][S]
+  std::vector<T> g;   // pre-collision populations, deviation form, [Q][S]
   std::vector<T> X;   // unwrapped positions [N][3]
   std::vector<T> V;   // velocities [N][3]
 };
@@ -138,7 +159,7 @@ template <class T>
 void moments_at(const Model<T>& m, const std::vector<T>& g, long s, T& drho, T j[3]) {
   drho = T(0.0);
   j[0] = j[1] = j[2] = T(0.0);
-  for (int i = 0; i < 19; ++i) {
+  for (int i = 0; i < m.Q; ++i) {
     T gi = g[i * m.S + s];
     drho += gi;
     j[0] += T((double)CV[i][0]) * gi;
@@ -150,11 +171,11 @@ void moments_at(const Model<T>& m, const std::vector<T>& g, long s, T& drho, T j
 // Second-order equilibrium (Section 2.2 after Eq. 1), minus its rest part w_i rho0:
 //   g_eq_i = w_i [ delta_rho + rho (3 c.u + 9/2 (c.u)^2 - 3/2 u.u) ].
 template <class T>
-void equilibrium_dev(T drho, T rho, const T u[3], T out[19]) {
+void equilibrium_dev(int Q, T drho, T rho, const T u[3], T out[]) {
   T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-  for (int i = 0; i < 19; ++i) {
+  for (int i = 0; i < Q; ++i) {
     T cu = T((double)CV[i][0]) * u[0] + T((double)CV[i][1]) * u[1] + T((double)CV[i][2]) * u[2];
-    out[i] = T(WV[i]) * (drho + rho * (T(3.0) * cu + T(4.5) * cu * cu - T(1.5) * uu));
+    out[i] = T(wq(Q, i)) * (drho + rho * (T(3.0) * cu + T(4.5) * cu * cu - T(1.5) * uu));
   }
 }
 
@@ -177,35 +198,35 @@ T omega_minus(T tau, T magic) {
 //     g*_i = g_i + s_i - omega+ d+_i - omega- d-_i,  omega+ = 1/tau, omega- from magic,
 //   which is the BGK form above when omega- = omega+.
 template <class T>
-void collide_node(T tau, T rho0, const T g[19], const T F[3], T out[19], T magic = T(0.0)) {
+void collide_node(int Q, T tau, T rho0, const T g[], const T F[3], T out[], T magic = T(0.0)) {
   T drho = T(0.0), j[3] = {T(0.0), T(0.0), T(0.0)};
-  for (int i = 0; i < 19; ++i) {
+  for (int i = 0; i < Q; ++i) {
     drho += g[i];
     for (int a = 0; a < 3; ++a) j[a] += T((double)CV[i][a]) * g[i];
   }
   T rho = rho0 + drho;
   T u[3];
   for (int a = 0; a < 3; ++a) u[a] = (j[a] + T(0.5) * F[a]) / rho;
-  T geq[19];
-  equilibrium_dev(drho, rho, u, geq);
+  T geq[QMAX];
+  equilibrium_dev(Q, drho, rho, u, geq);
   T pref = T(1.0) - T(1.0) / (T(2.0) * tau);
-  T sraw[19];
-  for (int i = 0; i < 19; ++i) {
+  T sraw[QMAX];
+  for (int i = 0; i < Q; ++i) {
     T cu = T((double)CV[i][0]) * u[0] + T((double)CV[i][1]) * u[1] + T((double)CV[i][2]) * u[2];
     T src = T(0.0);
     for (int a = 0; a < 3; ++a) {
       T ca = T((double)CV[i][a]);
       src += (T(3.0) * (ca - u[a]) + T(9.0) * cu * ca) * F[a];
     }
-    T Si = pref * T(WV[i]) * src;
+    T Si = pref * T(wq(Q, i)) * src;
     out[i] = g[i] - (g[i] - geq[i]) / tau + Si;
-    sraw[i] = T(WV[i]) * src;
+    sraw[i] = T(wq(Q, i)) * src;
   }
   if (val(magic) > 0.0) {
     const T om_p = T(1.0) / tau, om_m = omega_minus(tau, magic);
-    T d[19];
-    for (int i = 0; i < 19; ++i) d[i] = g[i] - geq[i] + T(0.5) * sraw[i];
-    for (int i = 0; i < 19; ++i) {
+    T d[QMAX];
+    for (int i = 0; i < Q; ++i) d[i] = g[i] - geq[i] + T(0.5) * sraw[i];
+    for (int i = 0; i < Q; ++i) {
       const T dp = T(0.5) * (d[i] + d[opposite(i)]);
       const T dm = T(0.5) * (d[i] - d[opposite(i)]);
       out[i] = g[i] + sraw[i] - om_p * dp - om_m * dm;
@@ -218,7 +239,7 @@ void collide_node(T tau, T rho0, const T g[19], const T F[3], T out[19], T magic
 template <class T>
 void stream(const Model<T>& m, const std::vector<T>& post, std::vector<T>& pre) {
   const int* L = m.L;
-  for (int i = 0; i < 19; ++i)
+  for (int i = 0; i < m.Q; ++i)
     for (long z = 0; z < L[2]; ++z)
       for (long y = 0; y < L[1]; ++y)
         for (long x = 0; x < L[0]; ++x) {
@@ -360,7 +381,7 @@ double mode_norm(int k) {
   if (b[0] < 0.0)
     for (int q = 0; q < 19; ++q) {
       double acc = 0.0;
-      for (int i = 0; i < 19; ++i) acc += WV[i] * mode_poly(q, CV[i]) * mode_poly(q, CV[i]);
+      for (int i = 0; i < 19; ++i) acc += WV(i) * mode_poly(q, CV[i]) * mode_poly(q, CV[i]);
       b[q] = acc;
     }
   return b[k];
@@ -388,7 +409,7 @@ void site_noise(double kT, T tau, T rho, const uint32_t seed[2], int64_t step, l
       const T amp2 = (k >= 10 && k <= 15) ? amp2_m : amp2_p;
       acc += T(mode_poly(k, CV[i]) * z[k - 4]) * sqrtT(amp2 * T(b)) / T(b);
     }
-    xi[i] = T(WV[i]) * acc;
+    xi[i] = T(WV(i)) * acc;
   }
 }
 
@@ -571,18 +592,18 @@ void coupled_step(const Model<T>& m, State<T>& s, std::vector<T>& scratch_post) 
   std::vector<T> Fc, Ftot;
   coupling_forces(m, s, Fc, Ftot);
   for (long x = 0; x < S; ++x) {
-    T gin[19], gout[19], F[3];
-    for (int i = 0; i < 19; ++i) gin[i] = s.g[i * S + x];
+    T gin[QMAX], gout[QMAX], F[3];
+    for (int i = 0; i < m.Q; ++i) gin[i] = s.g[i * S + x];
     for (int c = 0; c < 3; ++c) F[c] = Ftot[c * S + x];
-    collide_node(m.tau, m.rho0, gin, F, gout, m.trt_magic);
-    if (m.kT > 0.0) {
+    collide_node(m.Q, m.tau, m.rho0, gin, F, gout, m.trt_magic);
+    if (m.kT > 0.0) {   // D3Q19 only (checked by the callers)
       T rho = m.rho0;
       for (int i = 0; i < 19; ++i) rho += gin[i];
       T xi[19];
       site_noise(m.kT, m.tau, rho, m.seed, s.step, x, xi, m.trt_magic);
       for (int i = 0; i < 19; ++i) gout[i] += xi[i];
     }
-    for (int i = 0; i < 19; ++i) scratch_post[i * S + x] = gout[i];
+    for (int i = 0; i < m.Q; ++i) scratch_post[i * S + x] = gout[i];
   }
   stream(m, scratch_post, s.g);
   std::vector<T> Fff(3 * N);
@@ -598,7 +619,8 @@ void coupled_step(const Model<T>& m, State<T>& s, std::vector<T>& scratch_post) 
 
 // =======================================================================================
 // C interface (ctypes).  Arrays are float64 unless stated; layouts:
-//   populations [19][nz][ny][nx] (x fastest), fields [3][nz][ny][nx], atoms [N][3].
+//   populations [Q][nz][ny][nx] (x fastest, Q = 19 or 27), fields [3][nz][ny][nx],
+//   atoms [N][3].
 // =======================================================================================
 extern "C" {
 
@@ -616,11 +638,21 @@ struct or_params {
   double coul_k;      // implicit-solvent Coulomb prefactor k_C (0: off)
   const double* charge;   // [n_atoms] charges, or NULL (all zero)
   double trt_magic;   // two-relaxation-time collision: Lambda (0: BGK)
+  int32_t velocity_set;   // 19 or 27 (0 means 19); thermal noise needs 19
+  int32_t pad2;
 };
 
 }  // extern "C"
 
 namespace {
+
+// the velocity set is 19 or 27 (or 0 for 19), and the thermal noise runs on D3Q19 only
+bool params_ok(const or_params* p) {
+  const int q = p->velocity_set == 0 ? 19 : p->velocity_set;
+  return (q == 19 || q == 27) && !(q == 27 && p->kT > 0.0);
+}
+
+inline int q_of(const or_params* p) { return p->velocity_set == 27 ? 27 : 19; }
 
 template <class T>
 void external_force(const or_params* p, const double* field, std::vector<T>& fext, long S) {
@@ -647,6 +679,7 @@ void external_force(const or_params* p, const double* field, std::vector<T>& fex
 template <class T>
 void build_model(const or_params* p, const double* X0, const int32_t* bonds, const double* field,
                  Model<T>& m) {
+  m.Q = p->velocity_set == 27 ? 27 : 19;
   for (int a = 0; a < 3; ++a) m.L[a] = p->L[a];
   m.S = (long)p->L[0] * p->L[1] * p->L[2];
   m.tau = T(p->tau);
@@ -687,21 +720,22 @@ void build_model(const or_params* p, const double* X0, const int32_t* bonds, con
 template <class T>
 int run_impl(const or_params* p, double* g, double* X, double* V, const double* X0,
              const int32_t* bonds, const double* field, int32_t n_steps) {
+  if (!params_ok(p)) return 2;
   Model<T> m;
   build_model<T>(p, X0, bonds, field, m);
   State<T> s;
   s.step = p->step0;
-  s.g.resize(19 * m.S);
+  s.g.resize(m.Q * m.S);
   s.X.resize(3 * (size_t)m.n_atoms);
   s.V.resize(3 * (size_t)m.n_atoms);
-  for (long k = 0; k < 19 * m.S; ++k) s.g[k] = T(g[k]);
+  for (long k = 0; k < m.Q * m.S; ++k) s.g[k] = T(g[k]);
   for (long k = 0; k < 3L * m.n_atoms; ++k) {
     s.X[k] = T(X[k]);
     s.V[k] = T(V[k]);
   }
-  std::vector<T> post(19 * m.S);
+  std::vector<T> post(m.Q * m.S);
   for (int n = 0; n < n_steps; ++n) coupled_step(m, s, post);
-  for (long k = 0; k < 19 * m.S; ++k) g[k] = val(s.g[k]);
+  for (long k = 0; k < m.Q * m.S; ++k) g[k] = val(s.g[k]);
   for (long k = 0; k < 3L * m.n_atoms; ++k) {
     X[k] = val(s.X[k]);
     V[k] = val(s.V[k]);
@@ -734,37 +768,54 @@ void or_site_noise(double kT, double tau, double rho, const uint32_t* seed, int6
   site_noise(kT, tau, rho, seed, step, (long)site, xi, magic);
 }
 
-void or_velocity_set(int32_t* c, double* w) {
-  for (int i = 0; i < 19; ++i) {
+// Velocities c[Q][3] and weights w[Q] of the set with q = 19 or 27; 1 for any other q.
+int or_velocity_set_q(int32_t q, int32_t* c, double* w) {
+  if (q != 19 && q != 27) return 1;
+  for (int i = 0; i < q; ++i) {
     for (int a = 0; a < 3; ++a) c[3 * i + a] = CV[i][a];
-    w[i] = WV[i];
+    w[i] = wq(q, i);
   }
+  return 0;
 }
+
+void or_velocity_set(int32_t* c, double* w) { or_velocity_set_q(19, c, w); }
 
 // Deviation equilibrium g_eq_i(delta rho, u) around rest density rho0.
-void or_equilibrium(double rho0, double drho, const double* u, double* out) {
-  equilibrium_dev<double>(drho, rho0 + drho, u, out);
+void or_equilibrium_q(int32_t q, double rho0, double drho, const double* u, double* out) {
+  equilibrium_dev<double>(q == 27 ? 27 : 19, drho, rho0 + drho, u, out);
 }
 
-// One BGK + Guo collision at a single node.
+void or_equilibrium(double rho0, double drho, const double* u, double* out) {
+  or_equilibrium_q(19, rho0, drho, u, out);
+}
+
+// One Guo-forced collision at a single node: BGK (magic = 0) or two relaxation times.
+void or_collide_node_q(int32_t q, double tau, double magic, double rho0, const double* g,
+                       const double* F, double* out) {
+  collide_node<double>(q == 27 ? 27 : 19, tau, rho0, g, F, out, magic);
+}
+
 void or_collide_node(double tau, double rho0, const double* g, const double* F, double* out) {
-  collide_node<double>(tau, rho0, g, F, out);
+  or_collide_node_q(19, tau, 0.0, rho0, g, F, out);
 }
 
 void or_collide_node_trt(double tau, double magic, double rho0, const double* g, const double* F,
                          double* out) {
-  collide_node<double>(tau, rho0, g, F, out, magic);
+  or_collide_node_q(19, tau, magic, rho0, g, F, out);
 }
 
-// Streaming of a [19][S] population array (post-collision in, pre-collision out).
-void or_stream(const int32_t* L, const double* post, double* pre) {
+// Streaming of a [Q][S] population array (post-collision in, pre-collision out).
+void or_stream_q(int32_t q, const int32_t* L, const double* post, double* pre) {
   Model<double> m;
+  m.Q = q == 27 ? 27 : 19;
   for (int a = 0; a < 3; ++a) m.L[a] = L[a];
   m.S = (long)L[0] * L[1] * L[2];
-  std::vector<double> in(post, post + 19 * m.S), out(19 * m.S);
+  std::vector<double> in(post, post + m.Q * m.S), out(m.Q * m.S);
   stream(m, in, out);
-  std::memcpy(pre, out.data(), sizeof(double) * 19 * m.S);
+  std::memcpy(pre, out.data(), sizeof(double) * m.Q * m.S);
 }
+
+void or_stream(const int32_t* L, const double* post, double* pre) { or_stream_q(19, L, post, pre); }
 
 // Trilinear interpolation of a [3][S] field at n positions.
 void or_interpolate(const int32_t* L, const double* field, int32_t n, const double* X, double* U) {
@@ -812,11 +863,12 @@ void or_external_force(const or_params* p, const double* field, double* out) {
 void or_observables(const or_params* p, const double* g, const double* field, double* rho,
                     double* u) {
   Model<double> m;
+  m.Q = q_of(p);
   for (int a = 0; a < 3; ++a) m.L[a] = p->L[a];
   m.S = (long)p->L[0] * p->L[1] * p->L[2];
   std::vector<double> fext;
   external_force<double>(p, field, fext, m.S);
-  std::vector<double> gv(g, g + 19 * m.S);
+  std::vector<double> gv(g, g + m.Q * m.S);
   for (long x = 0; x < m.S; ++x) {
     double dr, j[3];
     moments_at(m, gv, x, dr, j);
@@ -832,8 +884,9 @@ void or_invariants(const or_params* p, const double* g, const double* V, double*
   long S = (long)p->L[0] * p->L[1] * p->L[2];
   for (int k = 0; k < 7; ++k) out[k] = 0.0;
   double dm = 0.0;   // sum of deviations, kept apart from the (large) rest mass
+  const int Q = q_of(p);
   for (long x = 0; x < S; ++x) {
-    for (int i = 0; i < 19; ++i) {
+    for (int i = 0; i < Q; ++i) {
       double gi = g[i * S + x];
       dm += gi;
       for (int a = 0; a < 3; ++a) out[1 + a] += CV[i][a] * gi;
@@ -865,6 +918,7 @@ int or_loss_derivative(const or_params* p, const double* g, const double* X, con
                        const double* X0, const int32_t* bonds, const double* field,
                        const double* D, int32_t n_steps, int32_t wrt, const double* dfield,
                        double* loss, double* dloss) {
+  if (!params_ok(p)) return 2;
   Model<Dual> m;
   build_model<Dual>(p, X0, bonds, field, m);
   if (wrt == 0) m.gamma = Dual(p->gamma, 1.0);
@@ -877,15 +931,15 @@ int or_loss_derivative(const or_params* p, const double* g, const double* X, con
   }
   State<Dual> s;
   s.step = p->step0;
-  s.g.resize(19 * m.S);
+  s.g.resize(m.Q * m.S);
   s.X.resize(3 * (size_t)m.n_atoms);
   s.V.resize(3 * (size_t)m.n_atoms);
-  for (long k = 0; k < 19 * m.S; ++k) s.g[k] = Dual(g[k]);
+  for (long k = 0; k < m.Q * m.S; ++k) s.g[k] = Dual(g[k]);
   for (long k = 0; k < 3L * m.n_atoms; ++k) {
     s.X[k] = Dual(X[k]);
     s.V[k] = Dual(V[k]);
   }
-  std::vector<Dual> post(19 * m.S);
+  std::vector<Dual> post(m.Q * m.S);
   for (int n = 0; n < n_steps; ++n) coupled_step(m, s, post);
   Dual acc(0.0);
   for (int a = 0; a < m.n_atoms; ++a)
@@ -900,18 +954,19 @@ int or_loss_derivative(const or_params* p, const double* g, const double* X, con
 }
 
 // One coupled step from (g, X, V), with the outputs evaluated only where asked: the
-// post-step pre-collision populations g'[k][0..18] at sites site_idx[k], and X', V' of atoms
-// atom_idx[k].  Same algorithm as or_run; the collision is evaluated only at the 19
+// post-step pre-collision populations g'[k][0..Q-1] at sites site_idx[k], and X', V' of atoms
+// atom_idx[k].  Same algorithm as or_run; the collision is evaluated only at the Q
 // upstream nodes of each requested site, the force field only for requested atoms.
 int or_step_sampled(const or_params* p, const double* g, const double* X, const double* V,
                     const double* X0, const int32_t* bonds, const double* field,
                     int32_t n_sites, const int64_t* site_idx, double* g_out,
                     int32_t n_idx, const int32_t* atom_idx, double* X_out, double* V_out) {
+  if (!params_ok(p)) return 2;
   Model<double> m;
   build_model<double>(p, X0, bonds, field, m);
   State<double> s;
   s.step = p->step0;
-  s.g.assign(g, g + 19 * m.S);
+  s.g.assign(g, g + m.Q * m.S);
   s.X.assign(X, X + 3 * (size_t)m.n_atoms);
   s.V.assign(V, V + 3 * (size_t)m.n_atoms);
   std::vector<double> Fc, Ftot;
@@ -920,12 +975,12 @@ int or_step_sampled(const or_params* p, const double* g, const double* X, const 
   for (int k = 0; k < n_sites; ++k) {
     long xs = site_idx[k];
     long x = xs % L[0], y = (xs / L[0]) % L[1], z = xs / ((long)L[0] * L[1]);
-    for (int i = 0; i < 19; ++i) {
+    for (int i = 0; i < m.Q; ++i) {
       long src = site_index(L, wrap(x - CV[i][0], L[0]), wrap(y - CV[i][1], L[1]), wrap(z - CV[i][2], L[2]));
-      double gin[19], gout[19], F[3];
-      for (int q = 0; q < 19; ++q) gin[q] = s.g[q * m.S + src];
+      double gin[QMAX], gout[QMAX], F[3];
+      for (int q = 0; q < m.Q; ++q) gin[q] = s.g[q * m.S + src];
       for (int c = 0; c < 3; ++c) F[c] = Ftot[c * m.S + src];
-      collide_node(m.tau, m.rho0, gin, F, gout, m.trt_magic);
+      collide_node(m.Q, m.tau, m.rho0, gin, F, gout, m.trt_magic);
       if (m.kT > 0.0) {
         double rho = val(m.rho0);
         for (int q = 0; q < 19; ++q) rho += gin[q];
@@ -933,7 +988,7 @@ int or_step_sampled(const or_params* p, const double* g, const double* X, const 
         site_noise(m.kT, val(m.tau), rho, m.seed, s.step, src, xi, m.trt_magic);
         gout[i] += xi[i];
       }
-      g_out[19 * k + i] = gout[i];
+      g_out[(long)m.Q * k + i] = gout[i];
     }
   }
   for (int k = 0; k < n_idx; ++k) {
@@ -953,7 +1008,8 @@ int or_step_sampled(const or_params* p, const double* g, const double* X, const 
 int or_loss(const or_params* p, const double* g, const double* X, const double* V,
             const double* X0, const int32_t* bonds, const double* field, const double* D,
             int32_t n_steps, double* loss) {
-  std::vector<double> gv(g, g + 19 * (size_t)p->L[0] * p->L[1] * p->L[2]);
+  if (!params_ok(p)) return 2;
+  std::vector<double> gv(g, g + q_of(p) * (size_t)p->L[0] * p->L[1] * p->L[2]);
   std::vector<double> Xv(X, X + 3 * (size_t)p->n_atoms), Vv(V, V + 3 * (size_t)p->n_atoms);
   run_impl<double>(p, gv.data(), Xv.data(), Vv.data(), X0, bonds, field, n_steps);
   double acc = 0.0;

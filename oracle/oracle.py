@@ -4,7 +4,8 @@ TEST INFRASTRUCTURE ONLY: imported by ``tests/``, the smoke check and the benchm
 baseline leg, never by the product path.  It shares no code with the HIP library.
 
 Arrays crossing this interface are float64 (int32 for bonds), C-contiguous:
-populations [19, nz, ny, nx], fields [3, nz, ny, nx], atom arrays [N, 3].
+populations [Q, nz, ny, nx] (Q = 19 or 27 velocities), fields [3, nz, ny, nx], atom arrays
+[N, 3].
 """
 from __future__ import annotations
 
@@ -57,6 +58,8 @@ class OrParams(ctypes.Structure):
         ("coul_k", ctypes.c_double),
         ("charge", ctypes.POINTER(ctypes.c_double)),
         ("trt_magic", ctypes.c_double),
+        ("velocity_set", ctypes.c_int32),
+        ("pad2", ctypes.c_int32),
     ]
 
 
@@ -102,6 +105,12 @@ def lib():
         L.or_site_noise.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, up,
                                     ctypes.c_int64, ctypes.c_int64, dp, ctypes.c_double]
         L.or_collide_node_trt.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp, dp]
+        L.or_velocity_set_q.argtypes = [ctypes.c_int32, ip, dp]
+        L.or_velocity_set_q.restype = ctypes.c_int
+        L.or_equilibrium_q.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double, dp, dp]
+        L.or_collide_node_q.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, dp, dp, dp]
+        L.or_stream_q.argtypes = [ctypes.c_int32, ip, dp, dp]
         _lib = L
     return _lib
 
@@ -131,7 +140,7 @@ def i32(a):
 def make_params(L, tau, rho0=1.0, gamma=0.0, mass=1.0, k_tether=0.0, k_bond=0.0, r0_bond=1.0,
                 lj_eps=0.0, lj_sigma=1.0, lj_rc=2.5, lj_exclude_bonded=0, bf_kind=0, bf_amp=0.0,
                 n_atoms=0, n_bonds=0, kT=0.0, seed=0, step0=0, coul_k=0.0, charges=None,
-                trt_magic=0.0) -> OrParams:
+                trt_magic=0.0, velocity_set=19) -> OrParams:
     p = OrParams()
     Ls = (L, L, L) if np.isscalar(L) else tuple(L)
     for a in range(3):
@@ -146,6 +155,7 @@ def make_params(L, tau, rho0=1.0, gamma=0.0, mass=1.0, k_tether=0.0, k_bond=0.0,
     p.step0 = int(step0)
     p.coul_k = float(coul_k)
     p.trt_magic = float(trt_magic)
+    p.velocity_set = int(velocity_set)
     if charges is not None:
         q = f64(charges).reshape(-1)
         assert q.size == p.n_atoms
@@ -159,40 +169,49 @@ def params_from_workload(w) -> OrParams:
                        w.lj_eps, w.lj_sigma, w.lj_rc, w.lj_exclude_bonded, w.bf_kind, w.bf_amp,
                        n_atoms=w.n_atoms, n_bonds=len(w.bonds), kT=getattr(w, "kT", 0.0),
                        seed=getattr(w, "noise_seed", 0), coul_k=getattr(w, "coul_k", 0.0),
-                       charges=getattr(w, "charges", None), trt_magic=getattr(w, "trt_magic", 0.0))
+                       charges=getattr(w, "charges", None), trt_magic=getattr(w, "trt_magic", 0.0),
+                       velocity_set=getattr(w, "velocity_set", 19))
 
 
 def n_sites(p: OrParams) -> int:
     return int(p.L[0]) * int(p.L[1]) * int(p.L[2])
 
 
+def n_velocities(p: OrParams) -> int:
+    return 27 if int(p.velocity_set) == 27 else 19
+
+
 def pop_shape(p: OrParams):
-    return (19, int(p.L[2]), int(p.L[1]), int(p.L[0]))
+    return (n_velocities(p), int(p.L[2]), int(p.L[1]), int(p.L[0]))
 
 
-def velocity_set():
-    c = np.zeros((19, 3), np.int32)
-    w = np.zeros(19, np.float64)
-    lib().or_velocity_set(_i(c), _d(w))
+def velocity_set(q=19):
+    """(c [q, 3], w [q]) of the D3Q19 or D3Q27 set."""
+    c = np.zeros((q, 3), np.int32)
+    w = np.zeros(q, np.float64)
+    if lib().or_velocity_set_q(int(q), _i(c), _d(w)) != 0:
+        raise ValueError("velocity set must be 19 or 27")
     return c, w
 
 
-def equilibrium(rho0, drho, u):
-    out = np.zeros(19)
-    lib().or_equilibrium(float(rho0), float(drho), _d(f64(u)), _d(out))
+def equilibrium(rho0, drho, u, q=19):
+    out = np.zeros(q)
+    lib().or_equilibrium_q(int(q), float(rho0), float(drho), _d(f64(u)), _d(out))
     return out
 
 
-def collide_node(tau, rho0, g, F):
-    out = np.zeros(19)
-    lib().or_collide_node(float(tau), float(rho0), _d(f64(g)), _d(f64(F)), _d(out))
+def collide_node(tau, rho0, g, F, q=19, magic=0.0):
+    out = np.zeros(q)
+    lib().or_collide_node_q(int(q), float(tau), float(magic), float(rho0), _d(f64(g)), _d(f64(F)),
+                            _d(out))
     return out
 
 
 def stream(L, post):
+    """Streaming of a [Q, nz, ny, nx] array (Q = 19 or 27 from its first axis)."""
     post = f64(post)
     pre = np.zeros_like(post)
-    lib().or_stream(_i(i32(L)), _d(post), _d(pre))
+    lib().or_stream_q(int(post.shape[0]), _i(i32(L)), _d(post), _d(pre))
     return pre
 
 
@@ -259,10 +278,10 @@ def run(p: OrParams, g, X, V, X0, bonds, field=None, n_steps=1, precision="f64")
 
 
 def step_sampled(p: OrParams, g, X, V, X0, bonds, field, site_idx, atom_idx):
-    """One step; returns (g' [n_sites, 19] at site_idx, X' [n, 3], V' [n, 3] of atom_idx)."""
+    """One step; returns (g' [n_sites, Q] at site_idx, X' [n, 3], V' [n, 3] of atom_idx)."""
     site_idx = np.ascontiguousarray(site_idx, dtype=np.int64)
     atom_idx = i32(atom_idx)
-    gout = np.zeros((len(site_idx), 19))
+    gout = np.zeros((len(site_idx), n_velocities(p)))
     Xo = np.zeros((len(atom_idx), 3))
     Vo = np.zeros((len(atom_idx), 3))
     rc = lib().or_step_sampled(

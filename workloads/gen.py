@@ -71,6 +71,7 @@ class Workload:
     coul_k: float = 0.0                 # implicit-solvent Coulomb prefactor (0: off)
     charges: Optional[np.ndarray] = None  # [N] float32 atom charges
     trt_magic: float = 0.0              # two-relaxation-time collision parameter (0: BGK)
+    velocity_set: int = 19              # lattice velocities: 19 (D3Q19) or 27 (D3Q27)
 
     @property
     def n_atoms(self) -> int:
@@ -85,7 +86,7 @@ class Workload:
         return {k: getattr(self, k) for k in (
             "L", "tau", "rho0", "gamma", "mass", "k_tether", "k_bond", "r0_bond",
             "lj_eps", "lj_sigma", "lj_rc", "lj_exclude_bonded", "bf_kind", "bf_amp", "kT",
-            "noise_seed", "coul_k", "trt_magic")}
+            "noise_seed", "coul_k", "trt_magic", "velocity_set")}
 
 
 # ---------------------------------------------------------------------------------------
