@@ -33,10 +33,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def sweep_bytes_per_site(storage: str, field: bool) -> int:
-    """Algorithmic bytes of one sweep per site: 19 populations read + 19 written."""
+def sweep_bytes_per_site(storage: str, field: bool, q: int = 19) -> int:
+    """Algorithmic bytes of one sweep per site: q populations read + q written."""
     s = 4 if storage == "f32" else 2
-    return 2 * 19 * s + (12 if field else 0)
+    return 2 * q * s + (12 if field else 0)
 
 
 def source_hash() -> str:
@@ -197,6 +197,25 @@ def run(args):
         thermal = {"kT": 1e-4, "ms_per_step": round(time_steps(s3, args.steps, args.warmup)[0], 5)}
         s3.close()
         log("thermal: %s" % thermal)
+    # the 27-velocity lattice (D3Q27, the higher-order set): same workload, schedule and
+    # storage; its sweep moves 27/19 of the bytes, timed live like the main sweep
+    d3q27 = None
+    if args.formats:
+        import dataclasses
+        wq = dataclasses.replace(w, velocity_set=27)
+        s4 = CoupledLB.from_workload(wq, storage=args.storage, device=dev, flags=flags)
+        ms27 = time_steps(s4, args.steps, args.warmup)[0]
+        A.lb_timing_begin(s4.ctx, args.steps)
+        s4.step(args.steps)
+        sw27, _, n27 = A.lb_timing_end(s4.ctx)
+        s4.check()
+        s4.close()
+        bps27 = sweep_bytes_per_site(args.storage, w.bf_kind == 3, 27)
+        d3q27 = {"ms_per_step": round(ms27, 5),
+                 "mlups": round(w.n_sites / (ms27 * 1e-3) / 1e6, 1),
+                 "sweep_ms": round(sw27 / n27, 5), "bytes_per_site": bps27,
+                 "sweep_gbs": round(bps27 * w.n_sites / (sw27 / n27 * 1e-3) / 1e9, 1)}
+        log("d3q27: %s" % d3q27)
     adj = None
     if args.adjoint:
         adj = adjoint_ratio(dev)
@@ -244,6 +263,7 @@ def run(args):
         "f16_speedup": (round(storage_ms["f32"] / storage_ms["f16"], 4)
                         if "f32" in storage_ms and "f16" in storage_ms else None),
         "thermal": thermal,
+        "d3q27": d3q27,
         "adjoint_forward_ratio": adj["ratio"] if adj else None,
         "adjoint": adj,
     }
@@ -277,7 +297,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--no-formats", dest="formats", action="store_false",
-                    help="skip the FP16/BF16 (or FP32) storage and thermal-noise timings")
+                    help="skip the FP16/BF16 (or FP32) storage, thermal-noise and D3Q27 timings")
     ap.add_argument("--no-adjoint", dest="adjoint", action="store_false",
                     help="skip the adjoint/forward timing on the differentiation workload")
     ap.add_argument("--single-stream", action="store_true",

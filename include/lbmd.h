@@ -2,7 +2,8 @@
  * lbmd.h -- C interface of the MI355X (gfx950) coupled lattice-Boltzmann / atom library.
  *
  * The operation (Lauricella et al., arXiv 2305.05025, Section 2.2):
- *   a periodic D3Q19 lattice evolved by the single-relaxation-time (BGK) lattice Boltzmann
+ *   a periodic D3Q19 lattice (optionally D3Q27, the higher-order velocity set proposed in
+ *   Section 4) evolved by the single-relaxation-time (BGK) lattice Boltzmann
  *   equation, Eq. (1), with relaxation time tau = 1/omega = 3 nu + 1/2, the second-order
  *   equilibrium and the moments of Eqs. (2)-(3); atoms coupled to it by a friction force
  *   gamma (u - v), u interpolated linearly over the eight nearest nodes, the opposite force
@@ -17,7 +18,7 @@
  * Layouts (all arrays C-contiguous):
  *   site index s = x + nx * (y + ny * z), x fastest; S = nx * ny * nz
  *   scalar field [S], vector field [3][S] (component-major), atom arrays [N][3] float32.
- * Velocity ordering of the 19 populations: see lb_velocity_set().
+ * Velocity ordering of the Q = 19 (or 27) populations: see lb_velocity_set_q().
  *
  * Ownership: the library never allocates device memory.  The caller provides one device
  * workspace of lb_workspace_bytes() bytes (256-byte aligned) that must stay valid until
@@ -109,6 +110,11 @@ typedef struct {
                                 the part of f - f_eq odd under c -> -c relaxing at omega- with
                                 (tau - 1/2)(1/omega- - 1/2) = trt_magic (tau sets the viscosity
                                 as before; trt_magic = (tau - 1/2)^2 is BGK again) */
+  int32_t velocity_set;      /* lattice velocities: 19 (D3Q19, the set of Eq. 1; 0 also means
+                                19) or 27 (D3Q27, the higher-order set of the outlook in
+                                Section 4: same equilibrium, forcing and collision over its 27
+                                velocities).  With 27: kT must be 0 (the noise is defined on the
+                                D3Q19 moment basis) and lb_backward is not available */
 } lb_params;
 
 /* The 19 lattice velocities c[i][0..2] and weights w[i] in the library's ordering:
@@ -117,6 +123,13 @@ typedef struct {
  * opposite(i) = i+1 for odd i.  Weights 1/3, 1/18, 1/36 (the D3Q19 set named after Eq. 1).
  * Host pointers; either may be NULL. */
 void lb_velocity_set(int8_t c[19][3], double w[19]);
+
+/* Velocities c[q][3] and weights w[q] of the set with q = 19 (as lb_velocity_set) or 27:
+ * the D3Q19 rows in the same order, then the corners i = 19..26 = (1,1,1),(-1,-1,-1),
+ * (1,1,-1),(-1,-1,1),(1,-1,1),(-1,1,-1),(-1,1,1),(1,-1,-1) (opposite(i) = i+1 for odd i);
+ * D3Q27 weights 8/27, 2/27, 1/54, 1/216 by speed class.  Host pointers; either may be
+ * NULL.  LB_EINVAL for any other q. */
+lb_status lb_velocity_set_q(int32_t q, int8_t* c, double* w);
 
 /* Bytes of device workspace lb_init needs for these parameters (0 if they are invalid). */
 size_t lb_workspace_bytes(const lb_params* p);
@@ -162,11 +175,12 @@ lb_status lb_read_displacement(lb_ctx* c, float* d);
 lb_status lb_set_charges(lb_ctx* c, const float* q);
 
 /* Raw populations of the current pre-collision state as float32 deviations g_i
- * [19][S] (device pointer), in the lb_velocity_set ordering.  Asynchronous. */
+ * [Q][S] (device pointer, Q = velocity_set), in the lb_velocity_set_q ordering.
+ * Asynchronous. */
 lb_status lb_read_populations(lb_ctx* c, float* g);
 
-/* Replace the current pre-collision state by caller deviations g [19][S] (float32, device
- * pointer, lb_velocity_set ordering), rounded to the storage format.  Atoms are unchanged.
+/* Replace the current pre-collision state by caller deviations g [Q][S] (float32, device
+ * pointer, lb_velocity_set_q ordering), rounded to the storage format.  Atoms are unchanged.
  * Lets a run start from any lattice state (restart from external data, tests).
  * Asynchronous. */
 lb_status lb_set_populations(lb_ctx* c, const float* g);
@@ -207,8 +221,9 @@ lb_status lb_timing_end(lb_ctx* c, double out_ms[3]);
  *
  * Usage: save the state with lb_state_save into ckpts + s * lb_state_bytes(c) before each
  * segment s = 0, 1, ... of k steps (the last segment may be shorter), run all n_steps with
- * lb_couple_step, then call lb_backward.  Size of the adjoint workspace for segments of k
- * steps (0 if the context has no atoms or k < 1): */
+ * lb_couple_step, then call lb_backward.  The adjoint is written for D3Q19 (velocity_set
+ * 19).  Size of the adjoint workspace for segments of k steps (0 if the context has no
+ * atoms, uses 27 velocities, or k < 1): */
 size_t lb_adjoint_workspace_bytes(const lb_ctx* c, int32_t k);
 
 /* ckpts     device, 256-aligned: ceil(n_steps / k) states of lb_state_bytes(c) each, the s-th
@@ -223,7 +238,7 @@ size_t lb_adjoint_workspace_bytes(const lb_ctx* c, int32_t k);
  *           (positions taken with the tether anchors held fixed)
  * Everything runs on the context's stream; the call synchronises before returning.  The
  * context's state is restored to the one before the call.  Rounding of FP16/BF16 storage is
- * treated as the identity. */
+ * treated as the identity.  LB_EINVAL for a context with 27 velocities. */
 lb_status lb_backward(lb_ctx* c, const void* ckpts, int32_t n_steps, int32_t k, void* adj_ws,
                       size_t adj_ws_bytes, const float* dL_dX, const float* dL_dv,
                       double* dL_dgamma, double* dL_dtau, float* dL_db, float* dL_dX0,

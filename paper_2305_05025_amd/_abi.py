@@ -46,6 +46,7 @@ class lb_params(ctypes.Structure):
         ("seed", ctypes.c_uint32 * 2),
         ("coul_k", ctypes.c_float),
         ("trt_magic", ctypes.c_float),
+        ("velocity_set", ctypes.c_int32),
     ]
 
 
@@ -60,6 +61,7 @@ _lib = None
 # (name, restype, argtypes)
 _SIGS = [
     ("lb_velocity_set", None, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("lb_velocity_set_q", ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     ("lb_workspace_bytes", ctypes.c_size_t, [ctypes.POINTER(lb_params)]),
     ("lb_init", ctypes.c_int, [ctypes.POINTER(lb_params), ctypes.c_void_p, ctypes.c_size_t,
                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -120,6 +122,15 @@ def lb_velocity_set():
     w = (ctypes.c_double * 19)()
     lib().lb_velocity_set(ctypes.addressof(c), ctypes.addressof(w))
     return [tuple(c[3 * i:3 * i + 3]) for i in range(19)], list(w)
+
+
+def lb_velocity_set_q(q: int):
+    c = (ctypes.c_int8 * (3 * 27))()
+    w = (ctypes.c_double * 27)()
+    st = lib().lb_velocity_set_q(int(q), ctypes.addressof(c), ctypes.addressof(w))
+    if st != 0:
+        raise LBError(st, lb_last_error())
+    return [tuple(c[3 * i:3 * i + 3]) for i in range(q)], list(w)[:q]
 
 
 def lb_workspace_bytes(p: lb_params) -> int:

@@ -19,7 +19,7 @@ STORAGE = {"f32": A.LB_STORE_F32, "f16": A.LB_STORE_F16, "bf16": A.LB_STORE_BF16
 def make_params(L, tau, rho0=1.0, storage="f32", n_atoms=0, mass=1.0, gamma=0.0, k_tether=0.0,
                 n_bonds=0, k_bond=0.0, r0_bond=1.0, lj_eps=0.0, lj_sigma=1.0, lj_rc=2.5,
                 lj_exclude_bonded=0, bf_kind=0, bf_amp=0.0, flags=0, kT=0.0, seed=0,
-                coul_k=0.0, trt_magic=0.0) -> A.lb_params:
+                coul_k=0.0, trt_magic=0.0, velocity_set=19) -> A.lb_params:
     p = A.lb_params()
     Ls = (L, L, L) if isinstance(L, int) else tuple(L)
     for k in range(3):
@@ -35,6 +35,7 @@ def make_params(L, tau, rho0=1.0, storage="f32", n_atoms=0, mass=1.0, gamma=0.0,
     p.seed[0], p.seed[1] = int(seed) & 0xffffffff, (int(seed) >> 32) & 0xffffffff
     p.coul_k = float(coul_k)
     p.trt_magic = float(trt_magic)
+    p.velocity_set = int(velocity_set)
     return p
 
 
@@ -43,7 +44,7 @@ def params_from_workload(w, storage="f32", flags=0) -> A.lb_params:
                        len(w.bonds), w.k_bond, w.r0_bond, w.lj_eps, w.lj_sigma, w.lj_rc,
                        w.lj_exclude_bonded, w.bf_kind, w.bf_amp, flags,
                        getattr(w, "kT", 0.0), getattr(w, "noise_seed", 0), getattr(w, "coul_k", 0.0),
-                       getattr(w, "trt_magic", 0.0))
+                       getattr(w, "trt_magic", 0.0), getattr(w, "velocity_set", 19))
 
 
 def _aligned_workspace(nbytes: int, device) -> tuple:
@@ -68,6 +69,7 @@ class CoupledLB:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.L = tuple(int(params.L[k]) for k in range(3))
         self.S = self.L[0] * self.L[1] * self.L[2]
+        self.Q = 27 if int(params.velocity_set) == 27 else 19
         self.N = int(params.n_atoms)
         nbytes = A.lb_workspace_bytes(params)
         if nbytes == 0:
@@ -129,15 +131,15 @@ class CoupledLB:
         return d
 
     def populations(self):
-        """Pre-collision deviations g [19, nz, ny, nx] (float32)."""
-        g = torch.empty((19, self.L[2], self.L[1], self.L[0]), dtype=torch.float32, device=self.device)
+        """Pre-collision deviations g [Q, nz, ny, nx] (float32, Q = 19 or 27)."""
+        g = torch.empty((self.Q, self.L[2], self.L[1], self.L[0]), dtype=torch.float32, device=self.device)
         A.lb_read_populations(self.ctx, g.data_ptr())
         self.stream.synchronize()
         return g
 
     def set_populations(self, g):
-        """Load pre-collision deviations g [19, nz, ny, nx] as the current lattice state."""
-        gt = torch.as_tensor(g, dtype=torch.float32).reshape(19, self.S).contiguous().to(self.device)
+        """Load pre-collision deviations g [Q, nz, ny, nx] as the current lattice state."""
+        gt = torch.as_tensor(g, dtype=torch.float32).reshape(self.Q, self.S).contiguous().to(self.device)
         torch.cuda.synchronize(self.device)
         A.lb_set_populations(self.ctx, gt.data_ptr())
         self.stream.synchronize()

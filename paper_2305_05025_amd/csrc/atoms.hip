@@ -14,8 +14,8 @@
 //               corner), and append a record of it to its neighbour-list cell
 //   k_compact   lists of the occupied cells and of the flagged tiles
 //   k_node_compact  list of the flagged nodes (within the flagged tiles)
-//   k_node_u    u_c at every flagged node, one thread per node, pulled once per node (19
-//               loads) rather than once per atom corner
+//   k_node_u    u_c at every flagged node, one thread per node, pulled once per node (19 or
+//               27 loads) rather than once per atom corner
 //   k_couple    eight lanes per atom: weighted u_c of its node, xor-shuffle sum -> U,
 //               F_c = gamma (U - v)
 //   k_spread    every flagged node (one thread each) gathers -W F_c from the atoms listed at
@@ -268,7 +268,7 @@ struct NodeArgs {
 };
 
 // one thread per flagged node (persistent over the node list)
-template <int ST>
+template <int ST, int Q>
 __global__ __launch_bounds__(256) void k_node_u(NodeArgs a) {
   using T = typename Store<ST>::T;
   const int n = *a.node_count;
@@ -278,10 +278,10 @@ __global__ __launch_bounds__(256) void k_node_u(NodeArgs a) {
     const int t = s / a.nx;
     const int y = t % a.ny;
     const int z = t / a.ny;
-    float g[19];
-    gather<ST>(reinterpret_cast<const T*>(a.f), a.plane, x, y, z, a.nx, a.ny, a.nz, g);
+    float g[Q];
+    gather<ST, Q>(reinterpret_cast<const T*>(a.f), a.plane, x, y, z, a.nx, a.ny, a.nz, g);
     float drho, jx, jy, jz, Fx, Fy, Fz;
-    moments(g, drho, jx, jy, jz);
+    moments<Q>(g, drho, jx, jy, jz);
     external_force(a.bf_kind, a.fext_tab, a.fext_field, a.plane, s, y, Fx, Fy, Fz);
     const float inv = 1.0f / (a.rho0 + drho);
     a.uc[s] = (jx + 0.5f * Fx) * inv;
@@ -929,10 +929,20 @@ hipError_t launch_node_u(lb_ctx* c) {
   a.node_count = (const int*)(c->ws + c->lay.occ_count[c->step & 1]) + 2;
   a.uc = (float*)(c->ws + c->lay.uc);
   const dim3 grid(node_grid(c)), block(256);
+  const bool q27 = c->geo.q == 27;
   switch (c->p.storage) {
-    case LB_STORE_F32: hipLaunchKernelGGL(k_node_u<LB_STORE_F32>, grid, block, 0, c->stream, a); break;
-    case LB_STORE_F16: hipLaunchKernelGGL(k_node_u<LB_STORE_F16>, grid, block, 0, c->stream, a); break;
-    default: hipLaunchKernelGGL(k_node_u<LB_STORE_BF16>, grid, block, 0, c->stream, a); break;
+    case LB_STORE_F32:
+      if (q27) hipLaunchKernelGGL((k_node_u<LB_STORE_F32, 27>), grid, block, 0, c->stream, a);
+      else hipLaunchKernelGGL((k_node_u<LB_STORE_F32, 19>), grid, block, 0, c->stream, a);
+      break;
+    case LB_STORE_F16:
+      if (q27) hipLaunchKernelGGL((k_node_u<LB_STORE_F16, 27>), grid, block, 0, c->stream, a);
+      else hipLaunchKernelGGL((k_node_u<LB_STORE_F16, 19>), grid, block, 0, c->stream, a);
+      break;
+    default:
+      if (q27) hipLaunchKernelGGL((k_node_u<LB_STORE_BF16, 27>), grid, block, 0, c->stream, a);
+      else hipLaunchKernelGGL((k_node_u<LB_STORE_BF16, 19>), grid, block, 0, c->stream, a);
+      break;
   }
   return hipGetLastError();
 }

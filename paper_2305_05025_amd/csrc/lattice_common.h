@@ -48,10 +48,11 @@ struct Store<LB_STORE_BF16> {
 };
 
 // ---- pull gather: pre-collision values at (x, y, z) -----------------------------------------
-template <int ST>
+// Q = 19 or 27 velocities (the default 19 is the D3Q19 set of Eq. 1)
+template <int ST, int Q = 19>
 __device__ __forceinline__ void gather(const typename Store<ST>::T* __restrict__ f, long plane,
                                        int x, int y, int z, int nx, int ny, int nz,
-                                       float g[19]) {
+                                       float g[Q]) {
   const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
   const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
   const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
@@ -60,19 +61,20 @@ __device__ __forceinline__ void gather(const typename Store<ST>::T* __restrict__
   const int Y3[3] = {ym * nx, y * nx, yp * nx};
   const int Z3[3] = {zm * nxy, z * nxy, zp * nxy};
 #pragma unroll
-  for (int i = 0; i < 19; ++i) {
+  for (int i = 0; i < Q; ++i) {
     const int src = X3[1 - CX[i]] + Y3[1 - CY[i]] + Z3[1 - CZ[i]];
     g[i] = Store<ST>::ld(f + (size_t)i * plane + src);
   }
 }
 
 // ---- moments (Eqs. 2-3 in deviation form) --------------------------------------------------
-__device__ __forceinline__ void moments(const float g[19], float& drho, float& jx, float& jy,
+template <int Q = 19>
+__device__ __forceinline__ void moments(const float g[Q], float& drho, float& jx, float& jy,
                                         float& jz) {
   drho = 0.f;
   jx = jy = jz = 0.f;
 #pragma unroll
-  for (int i = 0; i < 19; ++i) {
+  for (int i = 0; i < Q; ++i) {
     drho += g[i];
     if (CX[i] == 1) jx += g[i];
     if (CX[i] == -1) jx -= g[i];
@@ -96,10 +98,11 @@ __device__ __forceinline__ float cdot(float ax, float ay, float az, int cx, int 
 }
 
 // ---- BGK + Guo collision in place; returns false on a non-finite moment ---------------------
-__device__ __forceinline__ bool collide(float g[19], float Fx, float Fy, float Fz, float rho0,
+template <int Q = 19>
+__device__ __forceinline__ bool collide(float g[Q], float Fx, float Fy, float Fz, float rho0,
                                         float omega, float pref) {
   float drho, jx, jy, jz;
-  moments(g, drho, jx, jy, jz);
+  moments<Q>(g, drho, jx, jy, jz);
   const float rho = rho0 + drho;
   const float inv = 1.0f / rho;
   const float ux = (jx + 0.5f * Fx) * inv;
@@ -109,11 +112,11 @@ __device__ __forceinline__ bool collide(float g[19], float Fx, float Fy, float F
   const float uF = ux * Fx + uy * Fy + uz * Fz;
   const float base = drho - 1.5f * rho * uu;
 #pragma unroll
-  for (int i = 0; i < 19; ++i) {
+  for (int i = 0; i < Q; ++i) {
     const float cu = cdot<0>(ux, uy, uz, CX[i], CY[i], CZ[i]);
     const float cF = cdot<0>(Fx, Fy, Fz, CX[i], CY[i], CZ[i]);
-    const float geq = WQ[i] * (base + rho * (3.0f * cu + 4.5f * cu * cu));
-    const float src = pref * WQ[i] * (3.0f * (cF - uF) + 9.0f * cu * cF);
+    const float geq = wq<Q>(i) * (base + rho * (3.0f * cu + 4.5f * cu * cu));
+    const float src = pref * wq<Q>(i) * (3.0f * (cF - uF) + 9.0f * cu * cF);
     g[i] = g[i] - omega * (g[i] - geq) + src;
   }
   return __builtin_isfinite(drho + jx + jy + jz);
@@ -241,10 +244,11 @@ constexpr int OPP(int i) { return i == 0 ? 0 : (i % 2 ? i + 1 : i - 1); }
 // its prefactor) split into parts even and odd under c -> -c,
 //   g*_i = g_i + s_i - omega+ d+_i - omega- d-_i = g_i + s_i - a d_i - b d_opp(i),
 // a = (omega+ + omega-)/2, b = (omega+ - omega-)/2; omega- = omega+ is the BGK collision.
-__device__ __forceinline__ bool collide_trt(float g[19], float Fx, float Fy, float Fz, float rho0,
+template <int Q = 19>
+__device__ __forceinline__ bool collide_trt(float g[Q], float Fx, float Fy, float Fz, float rho0,
                                             float omega_p, float omega_m) {
   float drho, jx, jy, jz;
-  moments(g, drho, jx, jy, jz);
+  moments<Q>(g, drho, jx, jy, jz);
   const float rho = rho0 + drho;
   const float inv = 1.0f / rho;
   const float ux = (jx + 0.5f * Fx) * inv;
@@ -253,19 +257,19 @@ __device__ __forceinline__ bool collide_trt(float g[19], float Fx, float Fy, flo
   const float uu = ux * ux + uy * uy + uz * uz;
   const float uF = ux * Fx + uy * Fy + uz * Fz;
   const float base = drho - 1.5f * rho * uu;
-  float d[19];
+  float d[Q];
 #pragma unroll
-  for (int i = 0; i < 19; ++i) {
+  for (int i = 0; i < Q; ++i) {
     const float cu = cdot<0>(ux, uy, uz, CX[i], CY[i], CZ[i]);
     const float cF = cdot<0>(Fx, Fy, Fz, CX[i], CY[i], CZ[i]);
-    const float geq = WQ[i] * (base + rho * (3.0f * cu + 4.5f * cu * cu));
-    const float si = WQ[i] * (3.0f * (cF - uF) + 9.0f * cu * cF);
+    const float geq = wq<Q>(i) * (base + rho * (3.0f * cu + 4.5f * cu * cu));
+    const float si = wq<Q>(i) * (3.0f * (cF - uF) + 9.0f * cu * cF);
     d[i] = g[i] - geq + 0.5f * si;
     g[i] += si;
   }
   const float a = 0.5f * (omega_p + omega_m), b = 0.5f * (omega_p - omega_m);
 #pragma unroll
-  for (int i = 0; i < 19; ++i) g[i] -= a * d[i] + b * d[OPP(i)];
+  for (int i = 0; i < Q; ++i) g[i] -= a * d[i] + b * d[OPP(i)];
   return __builtin_isfinite(drho + jx + jy + jz);
 }
 

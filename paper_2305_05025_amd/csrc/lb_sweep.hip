@@ -7,15 +7,18 @@
 // with omega = 1/tau, the second-order equilibrium, the moments of Eqs. (2)-(3), and the
 // forcing term S_i in the Guo form (velocity shifted by F/2, prefactor 1 - omega/2).
 //
-// Layout: populations are 19 planes (structure of arrays) of `plane` elements, site index
-// s = x + nx (y + ny z).  The stored buffer holds post-collision values at the site that
-// produced them; a site's pre-collision values are pulled from its 19 upstream neighbours
+// Layout: populations are Q planes (structure of arrays) of `plane` elements, Q = 19 (D3Q19)
+// or 27 (D3Q27), site index s = x + nx (y + ny z).  The stored buffer holds post-collision
+// values at the site that produced them; a site's pre-collision values are pulled from its Q
+// upstream neighbours
 // (x - c_i), so every load of a wavefront is a contiguous (possibly 4-byte shifted) run and
 // every store is a full aligned run.  The sweep reads buffer A and writes buffer B.
 //
 // One thread per site, 256 sites per workgroup.  A workgroup is also the unit ("tile") of
 // the sparse atom force: tiles that atoms touched in this step carry a flag, and only their
 // sites read (and clear) the fixed-point coupling-force field.
+#include <type_traits>
+
 #include "lattice_common.h"
 
 namespace lbmd {
@@ -40,15 +43,17 @@ struct SweepArgs {
   float omega_m;               // rate of the odd part (TRT instances only)
 };
 
-template <int ST, bool NOISE, bool TRT>
+// Q velocities; the thermal noise is defined for Q = 19 only
+template <int ST, bool NOISE, bool TRT, int Q>
 __device__ __forceinline__ void sweep_site(const SweepArgs& a, int s, bool hot) {
+  static_assert(!NOISE || Q == 19, "thermal noise needs the D3Q19 moment basis");
   using T = typename Store<ST>::T;
   const int x = s % a.nx;
   const int t = s / a.nx;
   const int y = t % a.ny;
   const int z = t / a.ny;
-  float g[19];
-  gather<ST>(reinterpret_cast<const T*>(a.fin), a.plane, x, y, z, a.nx, a.ny, a.nz, g);
+  float g[Q];
+  gather<ST, Q>(reinterpret_cast<const T*>(a.fin), a.plane, x, y, z, a.nx, a.ny, a.nz, g);
   float Fx, Fy, Fz;
   external_force(a.bf_kind, a.fext_tab, a.fext_field, a.plane, s, y, Fx, Fy, Fz);
   if (hot) {
@@ -70,8 +75,8 @@ __device__ __forceinline__ void sweep_site(const SweepArgs& a, int s, bool hot) 
     for (int i = 0; i < 19; ++i) rho += g[i];
   }
   bool ok;
-  if constexpr (TRT) ok = collide_trt(g, Fx, Fy, Fz, a.rho0, a.omega, a.omega_m);
-  else ok = collide(g, Fx, Fy, Fz, a.rho0, a.omega, a.pref);
+  if constexpr (TRT) ok = collide_trt<Q>(g, Fx, Fy, Fz, a.rho0, a.omega, a.omega_m);
+  else ok = collide<Q>(g, Fx, Fy, Fz, a.rho0, a.omega, a.pref);
   if (!ok) atomicOr(a.err, kErrNonFinite);
   if constexpr (NOISE) {
     float pe[19], po[19];
@@ -83,24 +88,48 @@ __device__ __forceinline__ void sweep_site(const SweepArgs& a, int s, bool hot) 
   }
   T* out = reinterpret_cast<T*>(a.fout);
 #pragma unroll
-  for (int i = 0; i < 19; ++i) Store<ST>::st(out + (size_t)i * a.plane + s, g[i]);
+  for (int i = 0; i < Q; ++i) Store<ST>::st(out + (size_t)i * a.plane + s, g[i]);
 }
 
 // One thread per site, in site order.
-template <int ST, bool NOISE, bool TRT>
+template <int ST, bool NOISE, bool TRT, int Q>
 __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
   const int s = blockIdx.x * kSweepBlock + threadIdx.x;
   if (s >= a.S) return;
   const bool hot = a.tile_flag != nullptr && a.tile_flag[s >> kTileShift] != 0u;
-  sweep_site<ST, NOISE, TRT>(a, s, hot);
+  sweep_site<ST, NOISE, TRT, Q>(a, s, hot);
 }
 
 template <int ST>
-void launch_sweep_st(bool noise, bool trt, dim3 grid, dim3 block, hipStream_t st, const SweepArgs& a) {
-  if (noise && trt) hipLaunchKernelGGL((k_sweep<ST, true, true>), grid, block, 0, st, a);
-  else if (noise) hipLaunchKernelGGL((k_sweep<ST, true, false>), grid, block, 0, st, a);
-  else if (trt) hipLaunchKernelGGL((k_sweep<ST, false, true>), grid, block, 0, st, a);
-  else hipLaunchKernelGGL((k_sweep<ST, false, false>), grid, block, 0, st, a);
+void launch_sweep_st(int q, bool noise, bool trt, dim3 grid, dim3 block, hipStream_t st,
+                     const SweepArgs& a) {
+  if (q == 27) {   // no noise (refused at initialisation)
+    if (trt) hipLaunchKernelGGL((k_sweep<ST, false, true, 27>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_sweep<ST, false, false, 27>), grid, block, 0, st, a);
+  } else if (noise && trt) hipLaunchKernelGGL((k_sweep<ST, true, true, 19>), grid, block, 0, st, a);
+  else if (noise) hipLaunchKernelGGL((k_sweep<ST, true, false, 19>), grid, block, 0, st, a);
+  else if (trt) hipLaunchKernelGGL((k_sweep<ST, false, true, 19>), grid, block, 0, st, a);
+  else hipLaunchKernelGGL((k_sweep<ST, false, false, 19>), grid, block, 0, st, a);
+}
+
+// Launch kernel template K<ST, Q> for the context's storage format and velocity set.
+template <class F>
+void dispatch_store_q(const lb_ctx* c, F&& launch) {
+  const bool q27 = c->geo.q == 27;
+  switch (c->p.storage) {
+    case LB_STORE_F32:
+      if (q27) launch(std::integral_constant<int, LB_STORE_F32>{}, std::integral_constant<int, 27>{});
+      else launch(std::integral_constant<int, LB_STORE_F32>{}, std::integral_constant<int, 19>{});
+      break;
+    case LB_STORE_F16:
+      if (q27) launch(std::integral_constant<int, LB_STORE_F16>{}, std::integral_constant<int, 27>{});
+      else launch(std::integral_constant<int, LB_STORE_F16>{}, std::integral_constant<int, 19>{});
+      break;
+    default:
+      if (q27) launch(std::integral_constant<int, LB_STORE_BF16>{}, std::integral_constant<int, 27>{});
+      else launch(std::integral_constant<int, LB_STORE_BF16>{}, std::integral_constant<int, 19>{});
+      break;
+  }
 }
 
 // ---- readback -------------------------------------------------------------------------------
@@ -114,10 +143,10 @@ struct ReadArgs {
   const float* fext_field;
   float* rho;   // [S] or NULL
   float* u;     // [3][S] or NULL
-  float* pops;  // [19][S] or NULL
+  float* pops;  // [Q][S] or NULL
 };
 
-template <int ST>
+template <int ST, int Q>
 __global__ __launch_bounds__(256) void k_read(ReadArgs a) {
   using T = typename Store<ST>::T;
   const int s = blockIdx.x * 256 + threadIdx.x;
@@ -126,15 +155,15 @@ __global__ __launch_bounds__(256) void k_read(ReadArgs a) {
   const int t = s / a.nx;
   const int y = t % a.ny;
   const int z = t / a.ny;
-  float g[19];
-  gather<ST>(reinterpret_cast<const T*>(a.f), a.plane, x, y, z, a.nx, a.ny, a.nz, g);
+  float g[Q];
+  gather<ST, Q>(reinterpret_cast<const T*>(a.f), a.plane, x, y, z, a.nx, a.ny, a.nz, g);
   if (a.pops) {
 #pragma unroll
-    for (int i = 0; i < 19; ++i) a.pops[(size_t)i * a.S + s] = g[i];
+    for (int i = 0; i < Q; ++i) a.pops[(size_t)i * a.S + s] = g[i];
   }
   if (a.rho || a.u) {
     float drho, jx, jy, jz, Fx, Fy, Fz;
-    moments(g, drho, jx, jy, jz);
+    moments<Q>(g, drho, jx, jy, jz);
     external_force(a.bf_kind, a.fext_tab, a.fext_field, a.plane, s, y, Fx, Fy, Fz);
     const float rho = a.rho0 + drho;
     if (a.rho) a.rho[s] = rho;
@@ -152,10 +181,10 @@ struct WriteArgs {
   void* f;
   long plane;
   int nx, ny, nz, S;
-  const float* pops;  // [19][S]
+  const float* pops;  // [Q][S]
 };
 
-template <int ST>
+template <int ST, int Q>
 __global__ __launch_bounds__(256) void k_write(WriteArgs a) {
   using T = typename Store<ST>::T;
   const int s = blockIdx.x * 256 + threadIdx.x;
@@ -173,7 +202,7 @@ __global__ __launch_bounds__(256) void k_write(WriteArgs a) {
   const int Z3[3] = {zm * nxy, z * nxy, zp * nxy};
   T* f = reinterpret_cast<T*>(a.f);
 #pragma unroll
-  for (int i = 0; i < 19; ++i) {
+  for (int i = 0; i < Q; ++i) {
     const int dst = X3[1 - CX[i]] + Y3[1 - CY[i]] + Z3[1 - CZ[i]];
     Store<ST>::st(f + (size_t)i * a.plane + dst, a.pops[(size_t)i * a.S + s]);
   }
@@ -196,19 +225,19 @@ struct RedArgs {
   uint32_t* err;
 };
 
-template <int ST>
+template <int ST, int Q>
 __global__ __launch_bounds__(256) void k_reduce_pops(RedArgs a) {
   using T = typename Store<ST>::T;
   const T* f = reinterpret_cast<const T*>(a.f);
   double m = 0.0, px = 0.0, py = 0.0, pz = 0.0;
   bool finite = true;
   for (int s = blockIdx.x * 256 + threadIdx.x; s < a.S; s += gridDim.x * 256) {
-    float g[19];
+    float g[Q];
 #pragma unroll
-    for (int i = 0; i < 19; ++i) g[i] = Store<ST>::ld(f + (size_t)i * a.plane + s);
+    for (int i = 0; i < Q; ++i) g[i] = Store<ST>::ld(f + (size_t)i * a.plane + s);
     double dm = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
-    for (int i = 0; i < 19; ++i) {
+    for (int i = 0; i < Q; ++i) {
       const double gi = (double)g[i];
       dm += gi;
       if (CX[i] == 1) jx += gi;
@@ -366,9 +395,9 @@ hipError_t launch_sweep(lb_ctx* c, const void* fin, void* fout, hipStream_t st) 
   const dim3 block(kSweepBlock), grid(g.nblocks);
   const bool noise = c->p.kT > 0.0f, trt = c->p.trt_magic > 0.0f;
   switch (c->p.storage) {
-    case LB_STORE_F32: launch_sweep_st<LB_STORE_F32>(noise, trt, grid, block, st, a); break;
-    case LB_STORE_F16: launch_sweep_st<LB_STORE_F16>(noise, trt, grid, block, st, a); break;
-    default: launch_sweep_st<LB_STORE_BF16>(noise, trt, grid, block, st, a); break;
+    case LB_STORE_F32: launch_sweep_st<LB_STORE_F32>(g.q, noise, trt, grid, block, st, a); break;
+    case LB_STORE_F16: launch_sweep_st<LB_STORE_F16>(g.q, noise, trt, grid, block, st, a); break;
+    default: launch_sweep_st<LB_STORE_BF16>(g.q, noise, trt, grid, block, st, a); break;
   }
   return hipGetLastError();
 }
@@ -390,11 +419,9 @@ static hipError_t launch_read(lb_ctx* c, float* rho, float* u, float* pops) {
   a.u = u;
   a.pops = pops;
   const dim3 grid(blocks_for(g.S, 256)), block(256);
-  switch (c->p.storage) {
-    case LB_STORE_F32: hipLaunchKernelGGL(k_read<LB_STORE_F32>, grid, block, 0, c->stream, a); break;
-    case LB_STORE_F16: hipLaunchKernelGGL(k_read<LB_STORE_F16>, grid, block, 0, c->stream, a); break;
-    default: hipLaunchKernelGGL(k_read<LB_STORE_BF16>, grid, block, 0, c->stream, a); break;
-  }
+  dispatch_store_q(c, [&](auto st, auto q) {
+    hipLaunchKernelGGL((k_read<decltype(st)::value, decltype(q)::value>), grid, block, 0, c->stream, a);
+  });
   return hipGetLastError();
 }
 
@@ -413,11 +440,9 @@ hipError_t launch_write_populations(lb_ctx* c, const float* g) {
   a.S = (int)geo.S;
   a.pops = g;
   const dim3 grid(blocks_for(geo.S, 256)), block(256);
-  switch (c->p.storage) {
-    case LB_STORE_F32: hipLaunchKernelGGL(k_write<LB_STORE_F32>, grid, block, 0, c->stream, a); break;
-    case LB_STORE_F16: hipLaunchKernelGGL(k_write<LB_STORE_F16>, grid, block, 0, c->stream, a); break;
-    default: hipLaunchKernelGGL(k_write<LB_STORE_BF16>, grid, block, 0, c->stream, a); break;
-  }
+  dispatch_store_q(c, [&](auto st, auto q) {
+    hipLaunchKernelGGL((k_write<decltype(st)::value, decltype(q)::value>), grid, block, 0, c->stream, a);
+  });
   return hipGetLastError();
 }
 
@@ -431,11 +456,10 @@ hipError_t launch_invariants(lb_ctx* c) {
   a.err = (uint32_t*)(c->ws + c->lay.err);
   int nb = blocks_for(g.S, 256);
   if (nb > kRedBlocks) nb = kRedBlocks;
-  switch (c->p.storage) {
-    case LB_STORE_F32: hipLaunchKernelGGL(k_reduce_pops<LB_STORE_F32>, dim3(nb), dim3(256), 0, c->stream, a); break;
-    case LB_STORE_F16: hipLaunchKernelGGL(k_reduce_pops<LB_STORE_F16>, dim3(nb), dim3(256), 0, c->stream, a); break;
-    default: hipLaunchKernelGGL(k_reduce_pops<LB_STORE_BF16>, dim3(nb), dim3(256), 0, c->stream, a); break;
-  }
+  dispatch_store_q(c, [&](auto st, auto q) {
+    hipLaunchKernelGGL((k_reduce_pops<decltype(st)::value, decltype(q)::value>), dim3(nb), dim3(256), 0,
+                       c->stream, a);
+  });
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   FinalArgs f;

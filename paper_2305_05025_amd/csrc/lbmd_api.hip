@@ -17,6 +17,7 @@ static size_t round_up(size_t n, size_t a) { return (n + a - 1) / a * a; }
 static size_t elem_bytes(int storage) { return storage == LB_STORE_F32 ? 4 : 2; }
 
 bool geometry(const lb_params* p, Geometry* g) {
+  g->q = p->velocity_set == 27 ? 27 : 19;
   g->nx = p->L[0];
   g->ny = p->L[1];
   g->nz = p->L[2];
@@ -52,7 +53,7 @@ Layout plan(const lb_params* p, const Geometry& g) {
     return o;
   };
   const size_t N = (size_t)p->n_atoms;
-  const size_t popb = 19 * (size_t)g.plane * g.elem;
+  const size_t popb = (size_t)g.q * g.plane * g.elem;
   l.pop[0] = take(popb);
   l.pop[1] = take(popb);
   for (int k = 0; k < 2; ++k) {
@@ -108,6 +109,10 @@ static std::string validate(const lb_params* p) {
     return "flags holds an unknown bit";
   if (!finite(p->kT) || p->kT < 0.0f) return "kT must be finite and >= 0";
   if (!finite(p->trt_magic) || p->trt_magic < 0.0f) return "trt_magic must be finite and >= 0";
+  if (p->velocity_set != 0 && p->velocity_set != 19 && p->velocity_set != 27)
+    return "velocity_set must be 19 or 27 (0 means 19)";
+  if (p->velocity_set == 27 && p->kT > 0.0f)
+    return "thermal noise (kT > 0) is defined on the D3Q19 moment basis: use velocity_set 19";
   if (!finite(p->rho0) || !(p->rho0 > 0.0f)) return "rho0 must be finite and > 0";
   if (p->storage < LB_STORE_F32 || p->storage > LB_STORE_BF16) return "unknown storage format";
   if (p->bf_kind < LB_BF_NONE || p->bf_kind > LB_BF_FIELD) return "unknown body-force kind";
@@ -160,6 +165,22 @@ static lb_status hip_fail(lb_ctx* c, hipError_t e, const char* what) {
 }
 
 extern "C" {
+
+lb_status lb_velocity_set_q(int32_t q, int8_t* c, double* w) {
+  if (q != 19 && q != 27) return fail(nullptr, LB_EINVAL, "q must be 19 or 27");
+  static const double w19[3] = {1.0 / 3.0, 1.0 / 18.0, 1.0 / 36.0};
+  static const double w27[4] = {8.0 / 27.0, 2.0 / 27.0, 1.0 / 54.0, 1.0 / 216.0};
+  for (int i = 0; i < q; ++i) {
+    if (c) {
+      c[3 * i] = (int8_t)CX[i];
+      c[3 * i + 1] = (int8_t)CY[i];
+      c[3 * i + 2] = (int8_t)CZ[i];
+    }
+    const int n2 = CX[i] * CX[i] + CY[i] * CY[i] + CZ[i] * CZ[i];
+    if (w) w[i] = q == 27 ? w27[n2] : w19[n2];
+  }
+  return LB_OK;
+}
 
 void lb_velocity_set(int8_t c[19][3], double w[19]) {
   static const double wq[3] = {1.0 / 3.0, 1.0 / 18.0, 1.0 / 36.0};
@@ -271,7 +292,7 @@ lb_status lb_init(const lb_params* p, void* workspace, size_t workspace_bytes, c
 
   char* ws = c->ws;
   // zero everything the step relies on being zero
-  const size_t popb = 19 * (size_t)g.plane * g.elem;
+  const size_t popb = (size_t)g.q * g.plane * g.elem;
   struct Z { size_t off, bytes; } zs[] = {
       {lay.pop[0], popb}, {lay.pop[1], popb},
       {lay.fcoup[0], N ? 3 * (size_t)g.plane * 4 : 0}, {lay.tile_flag[0], N ? (size_t)g.ntiles * 4 : 0},
@@ -492,7 +513,7 @@ lb_status lb_invariants(lb_ctx* c, double out7[7]) {
 int64_t lb_step_count(const lb_ctx* c) { return c ? c->step : -1; }
 
 // snapshot layout: [256-byte header: int64 step][populations][displacement][velocity]
-static size_t state_pop_bytes(const lb_ctx* c) { return 19 * (size_t)c->geo.plane * c->geo.elem; }
+static size_t state_pop_bytes(const lb_ctx* c) { return (size_t)c->geo.q * c->geo.plane * c->geo.elem; }
 
 size_t lb_state_bytes(const lb_ctx* c) {
   if (!c) return 0;
@@ -637,7 +658,7 @@ hipError_t copy_atoms(lb_ctx* c, char* dst_disp, char* dst_vel, const char* src_
 }  // namespace
 
 size_t lb_adjoint_workspace_bytes(const lb_ctx* c, int32_t k) {
-  if (!c || k < 1 || c->p.n_atoms <= 0) return 0;
+  if (!c || k < 1 || c->p.n_atoms <= 0 || c->geo.q != 19) return 0;
   return plan_adjoint(c, k).total;
 }
 
@@ -646,6 +667,7 @@ lb_status lb_backward(lb_ctx* c, const void* ckpts, int32_t n_steps, int32_t k, 
                       double* dL_dtau, float* dL_db, float* dL_dX0, float* dL_dv0) {
   if (!c) return fail(nullptr, LB_EINVAL, "context is NULL");
   if (c->p.n_atoms <= 0) return fail(c, LB_EINVAL, "lb_backward needs atoms (the loss is a function of them)");
+  if (c->geo.q != 19) return fail(c, LB_EINVAL, "the adjoint is written for D3Q19 (velocity_set 19)");
   if (n_steps < 1 || k < 1) return fail(c, LB_EINVAL, "n_steps and k must be >= 1");
   if (!ckpts || (uintptr_t)ckpts % 256) return fail(c, LB_EINVAL, "ckpts must be a 256-byte aligned device buffer");
   if (!adj_ws || (uintptr_t)adj_ws % 256) return fail(c, LB_EINVAL, "adj_ws must be a 256-byte aligned device buffer");

@@ -11,15 +11,30 @@
 
 namespace lbmd {
 
-// D3Q19 lattice (the 19-speed set named after Eq. 1 of the paper): velocities and weights,
-// in the ordering published by lb_velocity_set().
-constexpr int CX[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
-constexpr int CY[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
-constexpr int CZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+// Lattice velocities in the ordering published by lb_velocity_set_q(): the first 19 are the
+// D3Q19 set named after Eq. 1 of the paper, the last 8 the corners that complete D3Q27 (the
+// higher-order set of the paper's outlook, Section 4).  opposite(i) = i + 1 for odd i.
+constexpr int CX[27] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0,
+                        1, -1, 1, -1, 1, -1, -1, 1};
+constexpr int CY[27] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1,
+                        1, -1, 1, -1, -1, 1, 1, -1};
+constexpr int CZ[27] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1,
+                        1, -1, -1, 1, 1, -1, 1, -1};
+// D3Q19 weights (also those of the thermal-noise moment basis and of the adjoint)
 constexpr float WQ[19] = {
     1.f / 3.f, 1.f / 18.f, 1.f / 18.f, 1.f / 18.f, 1.f / 18.f, 1.f / 18.f, 1.f / 18.f,
     1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f,
     1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f};
+// D3Q27 weights: 8/27 rest, 2/27 faces, 1/54 edges, 1/216 corners
+constexpr float WQ27[27] = {
+    8.f / 27.f, 2.f / 27.f, 2.f / 27.f, 2.f / 27.f, 2.f / 27.f, 2.f / 27.f, 2.f / 27.f,
+    1.f / 54.f, 1.f / 54.f, 1.f / 54.f, 1.f / 54.f, 1.f / 54.f, 1.f / 54.f,
+    1.f / 54.f, 1.f / 54.f, 1.f / 54.f, 1.f / 54.f, 1.f / 54.f, 1.f / 54.f,
+    1.f / 216.f, 1.f / 216.f, 1.f / 216.f, 1.f / 216.f,
+    1.f / 216.f, 1.f / 216.f, 1.f / 216.f, 1.f / 216.f};
+// weight of velocity i in the Q-velocity set (Q = 19 or 27)
+template <int Q>
+constexpr float wq(int i) { return Q == 27 ? WQ27[i] : WQ[i]; }
 
 constexpr int kSweepBlock = 256;        // sites per sweep workgroup
 constexpr int kTileShift = 6;           // force tile = 64 sites (one wavefront of the sweep)
@@ -38,7 +53,7 @@ constexpr uint32_t kErrNonFinite = 2u;
 
 // Byte offsets of every buffer inside the caller's workspace.
 struct Layout {
-  size_t pop[2];       // population buffers A / B, 19 planes of `plane` elements
+  size_t pop[2];       // population buffers A / B, q planes of `plane` elements
   // [step parity]: a step's sweep still reads these while the next step bins its atoms
   size_t fcoup[2];     // float [3][plane]: spread coupling force at marked nodes
   size_t tile_flag[2]; // uint32 per 64-site force tile
@@ -73,9 +88,10 @@ constexpr int kRedBlocks = 1024;
 constexpr int kTimedEvents = 8;
 
 struct Geometry {
+  int q;             // lattice velocities: 19 or 27
   int nx, ny, nz;
   long S;            // sites
-  long plane;        // population plane stride (elements), S rounded up to 64
+  long plane;        // population plane stride (elements), S rounded up to 64 plus kPlanePad
   int nblocks;       // ceil(S / kSweepBlock)
   int ntiles;        // ceil(S / 64): force tiles
   int nc[3];         // neighbour-list cells per axis (0 when LJ is off)

@@ -35,6 +35,16 @@ def test_velocity_set_matches_oracle_ordering(O):
     np.testing.assert_array_equal(np.array(w), wo)
 
 
+@pytest.mark.parametrize("q", [19, 27])
+def test_velocity_set_q_matches_oracle_ordering(O, q):
+    c, w = A.lb_velocity_set_q(q)
+    co, wo = O.velocity_set(q)
+    assert np.array_equal(np.array(c), co)
+    np.testing.assert_allclose(np.array(w), wo, rtol=0, atol=1e-16)
+    with pytest.raises(A.LBError):
+        A.lb_velocity_set_q(21)
+
+
 def _params(**kw):
     from paper_2305_05025_amd.coupled import make_params
     d = dict(L=16, tau=0.8, n_atoms=10, mass=8.0, gamma=0.1, lj_eps=0.01)
@@ -49,6 +59,9 @@ def test_workspace_bytes():
     assert A.lb_workspace_bytes(_params(L=32, storage="f16")) < big
     # populations dominate: two FP32 buffers of 19 planes
     assert big > 2 * 19 * 32 ** 3 * 4
+    # 27 velocities: 8 more planes in each population buffer
+    big27 = A.lb_workspace_bytes(_params(L=32, velocity_set=27))
+    assert big27 - big >= 2 * 8 * 32 ** 3 * 4
 
 
 @pytest.mark.parametrize("kw,msg", [
@@ -63,6 +76,8 @@ def test_workspace_bytes():
     (dict(L=(16, 16, 7)), "cut-offs"),
     (dict(n_atoms=0, n_bonds=3), "bonds"),
     (dict(n_atoms=-1), "n_atoms"),
+    (dict(velocity_set=15), "velocity_set"),
+    (dict(velocity_set=27, kT=1e-4), "moment basis"),
 ])
 def test_invalid_parameters_rejected_before_device_work(kw, msg):
     p = _params(**kw)
