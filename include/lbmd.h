@@ -113,8 +113,8 @@ typedef struct {
   int32_t velocity_set;      /* lattice velocities: 19 (D3Q19, the set of Eq. 1; 0 also means
                                 19) or 27 (D3Q27, the higher-order set of the outlook in
                                 Section 4: same equilibrium, forcing and collision over its 27
-                                velocities).  With 27: kT must be 0 (the noise is defined on the
-                                D3Q19 moment basis) and lb_backward is not available */
+                                velocities).  With 27, kT must be 0 (the noise is defined on the
+                                D3Q19 moment basis) */
 } lb_params;
 
 /* The 19 lattice velocities c[i][0..2] and weights w[i] in the library's ordering:
@@ -221,9 +221,8 @@ lb_status lb_timing_end(lb_ctx* c, double out_ms[3]);
  *
  * Usage: save the state with lb_state_save into ckpts + s * lb_state_bytes(c) before each
  * segment s = 0, 1, ... of k steps (the last segment may be shorter), run all n_steps with
- * lb_couple_step, then call lb_backward.  The adjoint is written for D3Q19 (velocity_set
- * 19).  Size of the adjoint workspace for segments of k steps (0 if the context has no
- * atoms, uses 27 velocities, or k < 1): */
+ * lb_couple_step, then call lb_backward.  Size of the adjoint workspace for segments of k
+ * steps (0 if the context has no atoms or k < 1): */
 size_t lb_adjoint_workspace_bytes(const lb_ctx* c, int32_t k);
 
 /* ckpts     device, 256-aligned: ceil(n_steps / k) states of lb_state_bytes(c) each, the s-th
@@ -238,7 +237,7 @@ size_t lb_adjoint_workspace_bytes(const lb_ctx* c, int32_t k);
  *           (positions taken with the tether anchors held fixed)
  * Everything runs on the context's stream; the call synchronises before returning.  The
  * context's state is restored to the one before the call.  Rounding of FP16/BF16 storage is
- * treated as the identity.  LB_EINVAL for a context with 27 velocities. */
+ * treated as the identity. */
 lb_status lb_backward(lb_ctx* c, const void* ckpts, int32_t n_steps, int32_t k, void* adj_ws,
                       size_t adj_ws_bytes, const float* dL_dX, const float* dL_dv,
                       double* dL_dgamma, double* dL_dtau, float* dL_db, float* dL_dX0,

@@ -38,7 +38,7 @@ namespace {
 
 struct AdjLatticeArgs {
   const void* P;          // P^n (storage format)
-  const float* lam_in;    // Lam^{n+1}, FP32 [19][plane]
+  const float* lam_in;    // Lam^{n+1}, FP32 [Q][plane]
   float* lam_out;         // Lam^n
   long plane;
   int nx, ny, nz, S;
@@ -61,16 +61,18 @@ struct AdjLatticeArgs {
   int64_t step;
 };
 
-// Adjoint of the collision at one site: from mu (adjoint of the output) and the site's
-// pre-collision values g and force F, the adjoint of g (in place of mu), phi = dL/dF, and this
-// site's dL/domega+ and dL/domega- terms.  Also returns rho and the moments for the caller.
-__device__ __forceinline__ void collide_adjoint(float mu[19], const float g[19], float Fx, float Fy,
+// Adjoint of the collision at one site (Q = 19 or 27 velocities): from mu (adjoint of the
+// output) and the site's pre-collision values g and force F, the adjoint of g (in place of
+// mu), phi = dL/dF, and this site's dL/domega+ and dL/domega- terms.  Also returns rho and the
+// moments for the caller.
+template <int Q>
+__device__ __forceinline__ void collide_adjoint(float mu[Q], const float g[Q], float Fx, float Fy,
                                                 float Fz, float rho0, float omega_p, float omega_m,
                                                 float& phx, float& phy, float& phz, float& dom_p,
                                                 float& dom_m, float& rho, float& jx, float& jy,
                                                 float& jz) {
   float drho;
-  moments(g, drho, jx, jy, jz);
+  moments<Q>(g, drho, jx, jy, jz);
   rho = rho0 + drho;
   const float inv = 1.0f / rho;
   const float ux = (jx + 0.5f * Fx) * inv;
@@ -82,17 +84,17 @@ __device__ __forceinline__ void collide_adjoint(float mu[19], const float g[19],
   float lrho_e = 0.f, lux = 0.f, luy = 0.f, luz = 0.f, lfx = 0.f, lfy = 0.f, lfz = 0.f;
   dom_p = dom_m = 0.f;
 #pragma unroll
-  for (int i = 0; i < 19; ++i) {
+  for (int i = 0; i < Q; ++i) {
     const float cu = cdot<0>(ux, uy, uz, CX[i], CY[i], CZ[i]);
     const float cF = cdot<0>(Fx, Fy, Fz, CX[i], CY[i], CZ[i]);
     const float n = ca * mu[i] + cb * mu[OPP(i)];
     const float k = mu[i] - 0.5f * n;
-    const float geq = WQ[i] * (drho + rho * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu));
-    const float si = WQ[i] * (3.0f * (cF - uF) + 9.0f * cu * cF);
+    const float geq = wq<Q>(i) * (drho + rho * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu));
+    const float si = wq<Q>(i) * (3.0f * (cF - uF) + 9.0f * cu * cF);
     const float d = g[i] - geq + 0.5f * si;
     dom_p -= 0.5f * (mu[i] + mu[OPP(i)]) * d;
     dom_m -= 0.5f * (mu[i] - mu[OPP(i)]) * d;
-    const float An = n * WQ[i], Ak = k * WQ[i];
+    const float An = n * wq<Q>(i), Ak = k * wq<Q>(i);
     lrho_e += An * (1.0f + 3.0f * cu + 4.5f * cu * cu - 1.5f * uu);
     // d geq_i / d u*: w rho (3 c + 9 cu c - 3 u);  d s_i / d u*: w (9 cF c - 3 F)
     const float kc = rho * (3.0f + 9.0f * cu);
@@ -113,7 +115,7 @@ __device__ __forceinline__ void collide_adjoint(float mu[19], const float g[19],
   // a_i = mu_i - nu_i + l_rho + c_i . l_j, nu recomputed from the old mu of i and its
   // opposite, so each opposite pair is updated together
 #pragma unroll
-  for (int i = 0; i < 19; ++i) {
+  for (int i = 0; i < Q; ++i) {
     if (i != 0 && (i & 1) == 0) continue;
     const int o = OPP(i);
     const float mi = mu[i], mo = mu[o];
@@ -122,8 +124,8 @@ __device__ __forceinline__ void collide_adjoint(float mu[19], const float g[19],
   }
 }
 
-// per-site work shared by the tile pass and the sweep
-template <int ST>
+// per-site work shared by the tile pass and the sweep (thermal noise: Q = 19 only)
+template <int ST, int Q>
 __device__ __forceinline__ void adj_site(const AdjLatticeArgs& a, int s, bool hot, bool sweep,
                                          float& dom_p, float& dom_m) {
   using T = typename Store<ST>::T;
@@ -131,10 +133,10 @@ __device__ __forceinline__ void adj_site(const AdjLatticeArgs& a, int s, bool ho
   const int t = s / a.nx;
   const int y = t % a.ny;
   const int z = t / a.ny;
-  float g[19], mu[19];
-  gather<ST>(reinterpret_cast<const T*>(a.P), a.plane, x, y, z, a.nx, a.ny, a.nz, g);
+  float g[Q], mu[Q];
+  gather<ST, Q>(reinterpret_cast<const T*>(a.P), a.plane, x, y, z, a.nx, a.ny, a.nz, g);
 #pragma unroll
-  for (int i = 0; i < 19; ++i) mu[i] = a.lam_in[(size_t)i * a.plane + s];
+  for (int i = 0; i < Q; ++i) mu[i] = a.lam_in[(size_t)i * a.plane + s];
   float Ex, Ey, Ez;
   external_force(a.bf_kind, a.fext_tab, a.fext_field, a.plane, s, y, Ex, Ey, Ez);
   float Fx = Ex, Fy = Ey, Fz = Ez;
@@ -144,25 +146,27 @@ __device__ __forceinline__ void adj_site(const AdjLatticeArgs& a, int s, bool ho
     Fz += a.fcoup[2 * a.plane + s];
   }
   // the noise does not depend on F, so only the sweep needs its terms
-  const bool noise = sweep && a.kT > 0.f;
+  const bool noise = Q == 19 && sweep && a.kT > 0.f;
   float mpe = 0.f, mpo = 0.f;   // sum_i mu_i pe_i, sum_i mu_i po_i of the noise patterns
-  if (noise) {
-    float pe[19], po[19];
-    noise_patterns(a.seed0, a.seed1, a.step, s, pe, po);
+  if constexpr (Q == 19) {
+    if (noise) {
+      float pe[19], po[19];
+      noise_patterns(a.seed0, a.seed1, a.step, s, pe, po);
 #pragma unroll
-    for (int i = 0; i < 19; ++i) {
-      mpe += mu[i] * pe[i];
-      mpo += mu[i] * po[i];
+      for (int i = 0; i < 19; ++i) {
+        mpe += mu[i] * pe[i];
+        mpo += mu[i] * po[i];
+      }
     }
   }
   float phx, phy, phz, rho, jx, jy, jz;
-  collide_adjoint(mu, g, Fx, Fy, Fz, a.rho0, a.omega, a.omega_m, phx, phy, phz, dom_p, dom_m, rho,
-                  jx, jy, jz);
+  collide_adjoint<Q>(mu, g, Fx, Fy, Fz, a.rho0, a.omega, a.omega_m, phx, phy, phz, dom_p, dom_m, rho,
+                     jx, jy, jz);
   if (noise) {
     const float Ap = noise_amp(a.kT, rho, a.omega), Am = noise_amp(a.kT, rho, a.omega_m);
     const float lr = (mpe * Ap + mpo * Am) / (2.0f * rho);
 #pragma unroll
-    for (int i = 0; i < 19; ++i) mu[i] += lr;
+    for (int i = 0; i < Q; ++i) mu[i] += lr;
     dom_p += mpe * Ap * (1.0f - a.omega) / (a.omega * (2.0f - a.omega));
     dom_m += mpo * Am * (1.0f - a.omega_m) / (a.omega_m * (2.0f - a.omega_m));
   }
@@ -180,7 +184,7 @@ __device__ __forceinline__ void adj_site(const AdjLatticeArgs& a, int s, bool ho
     const float ucx = (jx + 0.5f * Ex) * inv, ucy = (jy + 0.5f * Ey) * inv, ucz = (jz + 0.5f * Ez) * inv;
     const float lr = -(ucx * lx + ucy * ly + ucz * lz);
 #pragma unroll
-    for (int i = 0; i < 19; ++i) mu[i] += lr + cdot<0>(lx, ly, lz, CX[i], CY[i], CZ[i]);
+    for (int i = 0; i < Q; ++i) mu[i] += lr + cdot<0>(lx, ly, lz, CX[i], CY[i], CZ[i]);
     dbx += 0.5f * lx;
     dby += 0.5f * ly;
     dbz += 0.5f * lz;
@@ -203,7 +207,7 @@ __device__ __forceinline__ void adj_site(const AdjLatticeArgs& a, int s, bool ho
   const int Y3[3] = {ym * a.nx, y * a.nx, yp * a.nx};
   const int Z3[3] = {zm * nxy, z * nxy, zp * nxy};
 #pragma unroll
-  for (int i = 0; i < 19; ++i) {
+  for (int i = 0; i < Q; ++i) {
     const int dst = X3[1 - CX[i]] + Y3[1 - CY[i]] + Z3[1 - CZ[i]];
     a.lam_out[(size_t)i * a.plane + dst] = mu[i];
   }
@@ -222,7 +226,7 @@ __device__ __forceinline__ double block_sum(double v) {
 }
 
 // dL/dF at every site of the flagged tiles (one wavefront per tile)
-template <int ST>
+template <int ST, int Q>
 __global__ __launch_bounds__(256) void k_adj_tiles(AdjLatticeArgs a) {
   const int lane = threadIdx.x & 63;
   const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6, nwave = gridDim.x * 4;
@@ -230,18 +234,18 @@ __global__ __launch_bounds__(256) void k_adj_tiles(AdjLatticeArgs a) {
   for (int k = wave; k < n; k += nwave) {
     const int s = (a.hot_list[k] << kTileShift) + lane;
     float dp, dm;
-    if (s < a.S) adj_site<ST>(a, s, true, false, dp, dm);
+    if (s < a.S) adj_site<ST, Q>(a, s, true, false, dp, dm);
   }
 }
 
 // the adjoint sweep over all sites
-template <int ST>
+template <int ST, int Q>
 __global__ __launch_bounds__(kSweepBlock) void k_adj_sweep(AdjLatticeArgs a) {
   const int s = blockIdx.x * kSweepBlock + threadIdx.x;
   float dp = 0.f, dm = 0.f;
   if (s < a.S) {
     const bool hot = a.tile_flag != nullptr && a.tile_flag[s >> kTileShift] != 0u;
-    adj_site<ST>(a, s, hot, true, dp, dm);
+    adj_site<ST, Q>(a, s, hot, true, dp, dm);
   }
   const double bp = block_sum((double)dp);
   const double bm = block_sum((double)dm);
@@ -549,10 +553,20 @@ hipError_t launch_adjoint_step(lb_ctx* c, const AdjointBuffers& b) {
   // 2. dL/dF on the flagged tiles
   const AdjLatticeArgs la = lattice_args(c, b);
   const dim3 tgrid(persistent_grid(g.ntiles)), blk(256);
+  const bool q27 = g.q == 27;
   switch (c->p.storage) {
-    case LB_STORE_F32: hipLaunchKernelGGL(k_adj_tiles<LB_STORE_F32>, tgrid, blk, 0, st, la); break;
-    case LB_STORE_F16: hipLaunchKernelGGL(k_adj_tiles<LB_STORE_F16>, tgrid, blk, 0, st, la); break;
-    default: hipLaunchKernelGGL(k_adj_tiles<LB_STORE_BF16>, tgrid, blk, 0, st, la); break;
+    case LB_STORE_F32:
+      if (q27) hipLaunchKernelGGL((k_adj_tiles<LB_STORE_F32, 27>), tgrid, blk, 0, st, la);
+      else hipLaunchKernelGGL((k_adj_tiles<LB_STORE_F32, 19>), tgrid, blk, 0, st, la);
+      break;
+    case LB_STORE_F16:
+      if (q27) hipLaunchKernelGGL((k_adj_tiles<LB_STORE_F16, 27>), tgrid, blk, 0, st, la);
+      else hipLaunchKernelGGL((k_adj_tiles<LB_STORE_F16, 19>), tgrid, blk, 0, st, la);
+      break;
+    default:
+      if (q27) hipLaunchKernelGGL((k_adj_tiles<LB_STORE_BF16, 27>), tgrid, blk, 0, st, la);
+      else hipLaunchKernelGGL((k_adj_tiles<LB_STORE_BF16, 19>), tgrid, blk, 0, st, la);
+      break;
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // 3. atoms
@@ -578,9 +592,18 @@ hipError_t launch_adjoint_step(lb_ctx* c, const AdjointBuffers& b) {
   // 5. the adjoint sweep
   const dim3 sgrid(g.nblocks), sblk(kSweepBlock);
   switch (c->p.storage) {
-    case LB_STORE_F32: hipLaunchKernelGGL(k_adj_sweep<LB_STORE_F32>, sgrid, sblk, 0, st, la); break;
-    case LB_STORE_F16: hipLaunchKernelGGL(k_adj_sweep<LB_STORE_F16>, sgrid, sblk, 0, st, la); break;
-    default: hipLaunchKernelGGL(k_adj_sweep<LB_STORE_BF16>, sgrid, sblk, 0, st, la); break;
+    case LB_STORE_F32:
+      if (q27) hipLaunchKernelGGL((k_adj_sweep<LB_STORE_F32, 27>), sgrid, sblk, 0, st, la);
+      else hipLaunchKernelGGL((k_adj_sweep<LB_STORE_F32, 19>), sgrid, sblk, 0, st, la);
+      break;
+    case LB_STORE_F16:
+      if (q27) hipLaunchKernelGGL((k_adj_sweep<LB_STORE_F16, 27>), sgrid, sblk, 0, st, la);
+      else hipLaunchKernelGGL((k_adj_sweep<LB_STORE_F16, 19>), sgrid, sblk, 0, st, la);
+      break;
+    default:
+      if (q27) hipLaunchKernelGGL((k_adj_sweep<LB_STORE_BF16, 27>), sgrid, sblk, 0, st, la);
+      else hipLaunchKernelGGL((k_adj_sweep<LB_STORE_BF16, 19>), sgrid, sblk, 0, st, la);
+      break;
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // 6. FP64 accumulators

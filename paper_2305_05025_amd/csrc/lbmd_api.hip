@@ -630,8 +630,8 @@ AdjLayout plan_adjoint(const lb_ctx* c, int k) {
   const size_t sb = lb_state_bytes(c), N = (size_t)c->p.n_atoms, plane = (size_t)c->geo.plane;
   l.final_state = take(sb);
   l.slots = take(sb * (size_t)k);
-  l.lam[0] = take(19 * plane * 4);
-  l.lam[1] = take(19 * plane * 4);
+  l.lam[0] = take((size_t)c->geo.q * plane * 4);
+  l.lam[1] = take((size_t)c->geo.q * plane * 4);
   l.phi = take(3 * plane * 4);
   l.luc = take(3 * plane * 4);
   l.U = take(12 * N);
@@ -658,7 +658,7 @@ hipError_t copy_atoms(lb_ctx* c, char* dst_disp, char* dst_vel, const char* src_
 }  // namespace
 
 size_t lb_adjoint_workspace_bytes(const lb_ctx* c, int32_t k) {
-  if (!c || k < 1 || c->p.n_atoms <= 0 || c->geo.q != 19) return 0;
+  if (!c || k < 1 || c->p.n_atoms <= 0) return 0;
   return plan_adjoint(c, k).total;
 }
 
@@ -667,7 +667,6 @@ lb_status lb_backward(lb_ctx* c, const void* ckpts, int32_t n_steps, int32_t k, 
                       double* dL_dtau, float* dL_db, float* dL_dX0, float* dL_dv0) {
   if (!c) return fail(nullptr, LB_EINVAL, "context is NULL");
   if (c->p.n_atoms <= 0) return fail(c, LB_EINVAL, "lb_backward needs atoms (the loss is a function of them)");
-  if (c->geo.q != 19) return fail(c, LB_EINVAL, "the adjoint is written for D3Q19 (velocity_set 19)");
   if (n_steps < 1 || k < 1) return fail(c, LB_EINVAL, "n_steps and k must be >= 1");
   if (!ckpts || (uintptr_t)ckpts % 256) return fail(c, LB_EINVAL, "ckpts must be a 256-byte aligned device buffer");
   if (!adj_ws || (uintptr_t)adj_ws % 256) return fail(c, LB_EINVAL, "adj_ws must be a 256-byte aligned device buffer");
@@ -698,7 +697,7 @@ lb_status lb_backward(lb_ctx* c, const void* ckpts, int32_t n_steps, int32_t k, 
   // every kernel of the backward pass runs in order on the caller's stream
   c->astream = c->fstream = c->stream;
   if ((st = lb_state_save(c, A + L.final_state)) != LB_OK) goto restore;
-  if ((e = launch_zero(A + L.lam[0], 19 * (size_t)c->geo.plane * 4, c->stream)) != hipSuccess ||
+  if ((e = launch_zero(A + L.lam[0], (size_t)c->geo.q * c->geo.plane * 4, c->stream)) != hipSuccess ||
       (e = launch_zero(A + L.acc, 24, c->stream)) != hipSuccess ||
       (dL_db && (e = launch_zero(dL_db, 12 * (size_t)c->geo.S, c->stream)) != hipSuccess) ||
       (e = hipMemcpyAsync(A + L.lx[0], dL_dX, 4 * N3, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess ||

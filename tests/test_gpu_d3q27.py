@@ -3,7 +3,7 @@ the oracle: the fused sweep from random states on ragged lattices (BGK and two r
 times, every body-force kind), a shear wave with Kolmogorov forcing over 100 steps, the
 narrow storage formats' one-step bound, the population upload, coupled globules, one
 full-size sampled step at 256^3 with 200,000 atoms in the benchmarked schedule, and the
-refusal of the adjoint."""
+adjoint against the oracle's exact derivatives."""
 import numpy as np
 import pytest
 
@@ -141,15 +141,31 @@ def test_one_step_full_size_sampled(O):
     assert max(errs.values()) < 1e-5, errs
 
 
-def test_adjoint_refused():
-    """The adjoint is written for D3Q19: no workspace size, and lb_backward refuses before any
-    device work."""
-    from paper_2305_05025_amd import _abi as A
-    from paper_2305_05025_amd.coupled import CoupledLB
-    w = _ball((10, 10, 10), 8, seed=3, tau=0.8, gamma=0.1, mass=8.0)
-    sim = CoupledLB.from_workload(w)
-    assert A.lb_adjoint_workspace_bytes(sim.ctx, 4) == 0
-    with pytest.raises(A.LBError) as e:
-        A.lb_backward(sim.ctx, 0, 4, 4, 0, 0, 0)
-    assert e.value.status == A.LB_EINVAL and "D3Q19" in str(e.value)
-    sim.close()
+def test_adjoint_matches_oracle_derivatives(O):
+    """The adjoint on 27 velocities (checkpoint-and-recompute, 12 steps in segments of 5)
+    against the oracle's exact dual-number derivatives: dL/dgamma, dL/dtau and dL/dF_ext along
+    seeded directions, 1e-3 relative (FP32 adjoint against FP64 derivatives)."""
+    from test_gpu_adjoint import _check, _dfields, _gpu_grads, _oracle_grads
+    from workloads import globule_workload
+    L = 10
+    w = globule_workload(L, 1, 60, seed=21, tau=0.7, gamma=0.15, velocity_set=27)
+    rng = np.random.default_rng(3)
+    field = rng.normal(0, 1e-5, size=(3, L, L, L))
+    D = np.array([0.6, -0.48, 0.64])
+    dfields = _dfields(rng, field.shape)
+    outs, _ = _gpu_grads(w, field, D, 12, 5, reps=2)
+    _check(outs, _oracle_grads(O, w, field, D, 12, dfields), dfields, 1e-3)
+
+
+def test_adjoint_linear_ball_two_relaxation_times(O):
+    """Tethers and friction without LJ (linear dynamics) on a ragged box, two relaxation
+    times: 20 steps in segments of 7, 2e-4 relative."""
+    from test_gpu_adjoint import _check, _dfields, _gpu_grads, _oracle_grads
+    w = _ball((14, 12, 10), 40, seed=5, tau=0.8, gamma=0.1, k_tether=0.05, lj=False, mass=8.0,
+              trt_magic=0.1875)
+    rng = np.random.default_rng(9)
+    field = rng.normal(0, 1e-5, size=(3, 10, 12, 14))
+    D = np.array([0.0, 0.8, -0.6])
+    dfields = _dfields(rng, field.shape)
+    outs, _ = _gpu_grads(w, field, D, 20, 7)
+    _check(outs, _oracle_grads(O, w, field, D, 20, dfields), dfields, 2e-4)

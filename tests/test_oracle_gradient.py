@@ -1,15 +1,16 @@
 """The oracle's forward-mode (dual-number) derivative of the trajectory loss
 L = (1/N) sum_a |X_a(T) - (X_a(0) + D)|^2 is pinned against central finite differences of the
-float64 oracle (h = 1e-4 for gamma and tau, truncation error ~h^2)."""
+float64 oracle (h = 1e-4 for gamma and tau, truncation error ~h^2), on the D3Q19 and the
+D3Q27 lattice."""
 import numpy as np
 import pytest
 
 
-@pytest.fixture(scope="module")
-def small(O):
+@pytest.fixture(scope="module", params=[19, 27])
+def small(O, request):
     from workloads import globule_workload
     L = 10
-    w = globule_workload(L, 1, 60, seed=21, tau=0.7, gamma=0.15)
+    w = globule_workload(L, 1, 60, seed=21, tau=0.7, gamma=0.15, velocity_set=request.param)
     rng = np.random.default_rng(3)
     p = O.params_from_workload(w)
     p.bf_kind = 3
