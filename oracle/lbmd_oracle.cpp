@@ -43,7 +43,8 @@
 //
 // Velocity sets: the paper's D3Q19, and (as the higher-order set its outlook in Section 4
 // proposes) the 27-speed D3Q27 with the same equilibrium, forcing and collision written over
-// its velocities and weights.  The thermal noise is defined on the D3Q19 moment basis only.
+// its velocities and weights.  Its thermal noise uses the orthogonal tensor-product basis of
+// the one-dimensional three-speed polynomials (1, c, 3 c^2 - 1) in place of the D3Q19 basis.
 //
 // Parity status: every sub-step is pinned by the CPU tests (closed forms, invariants,
 // brute force); the long coupled trajectory itself has no published values to pin
@@ -327,12 +328,13 @@ void philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]
   for (int q = 0; q < 4; ++q) out[q] = x[q];
 }
 
-// 16 standard normals for one site and step: Philox counters (site, step low word, step
-// high word, q) for q = 0..3 under the seed; each output word w gives the uniform
-// u = (floor(w / 2^8) + 1/2) / 2^24 in (0, 1), and consecutive pairs (u_a, u_b) give
-// sqrt(-2 ln u_a) (cos 2 pi u_b, sin 2 pi u_b) (Box-Muller).
-void site_normals(const uint32_t seed[2], int64_t step, long site, double z[16]) {
-  for (int q = 0; q < 4; ++q) {
+// 4 ncalls standard normals for one site and step (ncalls = 4 for D3Q19, 6 for D3Q27):
+// Philox counters (site, step low word, step high word, q) for q = 0..ncalls-1 under the
+// seed; each output word w gives the uniform u = (floor(w / 2^8) + 1/2) / 2^24 in (0, 1),
+// and consecutive pairs (u_a, u_b) give sqrt(-2 ln u_a) (cos 2 pi u_b, sin 2 pi u_b)
+// (Box-Muller).
+void site_normals(const uint32_t seed[2], int64_t step, long site, double z[], int ncalls = 4) {
+  for (int q = 0; q < ncalls; ++q) {
     const uint32_t ctr[4] = {(uint32_t)site, (uint32_t)((uint64_t)step & 0xffffffffu),
                              (uint32_t)((uint64_t)step >> 32), (uint32_t)q};
     uint32_t w[4];
@@ -387,29 +389,83 @@ double mode_norm(int k) {
   return b[k];
 }
 
-// Noise added to the post-collision populations at one site:
-//   xi_i = w_i sum_{k=4..18} e_k(c_i) phi_k z_{k-4} / b_k,
+// The D3Q27 moment basis: products of the one-dimensional polynomials P_0 = 1, P_1 = c,
+// P_2 = 3 c^2 - 1, orthogonal under the three-speed weights (2/3, 1/6, 1/6) with norms
+// 1, 1/3, 2; so e_(a,b,c)(c) = P_a(c_x) P_b(c_y) P_c(c_z) is orthogonal under the D3Q27
+// weights with norm n_a n_b n_c.  Ordering: k = 0 density (0,0,0); 1..3 momentum (1,0,0),
+// (0,1,0), (0,0,1); then the other 23 triples by increasing a + 3 b + 9 c.  A mode is odd
+// under c -> -c when an odd number of its factors are P_1.
+void mode27_triple(int k, int abc[3]) {
+  static int tab[27][3];
+  static bool ready = false;
+  if (!ready) {
+    const int first[4][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    for (int q = 0; q < 4; ++q)
+      for (int d = 0; d < 3; ++d) tab[q][d] = first[q][d];
+    int n = 4;
+    for (int code = 0; code < 27; ++code) {
+      const int a = code % 3, b = (code / 3) % 3, c = code / 9;
+      if (a + b + c <= 1) continue;   // the four conserved modes above
+      tab[n][0] = a;
+      tab[n][1] = b;
+      tab[n][2] = c;
+      ++n;
+    }
+    ready = true;
+  }
+  for (int d = 0; d < 3; ++d) abc[d] = tab[k][d];
+}
+
+double poly1d(int a, int c) { return a == 0 ? 1.0 : (a == 1 ? (double)c : 3.0 * c * c - 1.0); }
+
+double mode27_poly(int k, const int c[3]) {
+  int abc[3];
+  mode27_triple(k, abc);
+  return poly1d(abc[0], c[0]) * poly1d(abc[1], c[1]) * poly1d(abc[2], c[2]);
+}
+
+bool mode27_odd(int k) {
+  int abc[3];
+  mode27_triple(k, abc);
+  return ((abc[0] == 1) + (abc[1] == 1) + (abc[2] == 1)) % 2 == 1;
+}
+
+double mode27_norm(int k) {
+  static double b[27] = {-1.0};
+  if (b[0] < 0.0)
+    for (int q = 0; q < 27; ++q) {
+      double acc = 0.0;
+      for (int i = 0; i < 27; ++i) acc += WV27[i] * mode27_poly(q, CV[i]) * mode27_poly(q, CV[i]);
+      b[q] = acc;
+    }
+  return b[k];
+}
+
+// Noise added to the post-collision populations at one site (Q = 19 or 27 velocities):
+//   xi_i = w_i sum_{k=4..Q-1} e_k(c_i) phi_k z_{k-4} / b_k,
 //   phi_k = sqrt(mu b_k (1 - (1 - omega_k)^2)),  mu = 3 rho kT,
-// omega_k the rate that relaxes mode k: 1/tau, except the modes odd under c -> -c (k = 10..15)
-// under the two-relaxation-time collision, which relax at omega-.
+// omega_k the rate that relaxes mode k: 1/tau, except the modes odd under c -> -c (D3Q19:
+// k = 10..15) under the two-relaxation-time collision, which relax at omega-.
 template <class T>
-void site_noise(double kT, T tau, T rho, const uint32_t seed[2], int64_t step, long site, T xi[19],
-                T magic = T(0.0)) {
-  double z[16];
-  site_normals(seed, step, site, z);
+void site_noise(int Q, double kT, T tau, T rho, const uint32_t seed[2], int64_t step, long site,
+                T xi[], T magic = T(0.0)) {
+  double z[24];
+  site_normals(seed, step, site, z, Q == 27 ? 6 : 4);
   const T om_p = T(1.0) / tau;
   const T om_m = val(magic) > 0.0 ? omega_minus(tau, magic) : om_p;
   const T gp = T(1.0) - om_p, gm = T(1.0) - om_m;
   const T amp2_p = T(3.0 * kT) * rho * (T(1.0) - gp * gp);
   const T amp2_m = T(3.0 * kT) * rho * (T(1.0) - gm * gm);
-  for (int i = 0; i < 19; ++i) {
+  for (int i = 0; i < Q; ++i) {
     T acc = T(0.0);
-    for (int k = 4; k < 19; ++k) {
-      const double b = mode_norm(k);
-      const T amp2 = (k >= 10 && k <= 15) ? amp2_m : amp2_p;
-      acc += T(mode_poly(k, CV[i]) * z[k - 4]) * sqrtT(amp2 * T(b)) / T(b);
+    for (int k = 4; k < Q; ++k) {
+      const double b = Q == 27 ? mode27_norm(k) : mode_norm(k);
+      const bool odd = Q == 27 ? mode27_odd(k) : (k >= 10 && k <= 15);
+      const double e = Q == 27 ? mode27_poly(k, CV[i]) : mode_poly(k, CV[i]);
+      const T amp2 = odd ? amp2_m : amp2_p;
+      acc += T(e * z[k - 4]) * sqrtT(amp2 * T(b)) / T(b);
     }
-    xi[i] = T(WV(i)) * acc;
+    xi[i] = T(wq(Q, i)) * acc;
   }
 }
 
@@ -596,12 +652,12 @@ void coupled_step(const Model<T>& m, State<T>& s, std::vector<T>& scratch_post) 
     for (int i = 0; i < m.Q; ++i) gin[i] = s.g[i * S + x];
     for (int c = 0; c < 3; ++c) F[c] = Ftot[c * S + x];
     collide_node(m.Q, m.tau, m.rho0, gin, F, gout, m.trt_magic);
-    if (m.kT > 0.0) {   // D3Q19 only (checked by the callers)
+    if (m.kT > 0.0) {
       T rho = m.rho0;
-      for (int i = 0; i < 19; ++i) rho += gin[i];
-      T xi[19];
-      site_noise(m.kT, m.tau, rho, m.seed, s.step, x, xi, m.trt_magic);
-      for (int i = 0; i < 19; ++i) gout[i] += xi[i];
+      for (int i = 0; i < m.Q; ++i) rho += gin[i];
+      T xi[QMAX];
+      site_noise(m.Q, m.kT, m.tau, rho, m.seed, s.step, x, xi, m.trt_magic);
+      for (int i = 0; i < m.Q; ++i) gout[i] += xi[i];
     }
     for (int i = 0; i < m.Q; ++i) scratch_post[i * S + x] = gout[i];
   }
@@ -638,7 +694,7 @@ struct or_params {
   double coul_k;      // implicit-solvent Coulomb prefactor k_C (0: off)
   const double* charge;   // [n_atoms] charges, or NULL (all zero)
   double trt_magic;   // two-relaxation-time collision: Lambda (0: BGK)
-  int32_t velocity_set;   // 19 or 27 (0 means 19); thermal noise needs 19
+  int32_t velocity_set;   // 19 or 27 (0 means 19)
   int32_t pad2;
 };
 
@@ -646,10 +702,10 @@ struct or_params {
 
 namespace {
 
-// the velocity set is 19 or 27 (or 0 for 19), and the thermal noise runs on D3Q19 only
+// the velocity set is 19 or 27 (or 0 for 19)
 bool params_ok(const or_params* p) {
   const int q = p->velocity_set == 0 ? 19 : p->velocity_set;
-  return (q == 19 || q == 27) && !(q == 27 && p->kT > 0.0);
+  return q == 19 || q == 27;
 }
 
 inline int q_of(const or_params* p) { return p->velocity_set == 27 ? 27 : 19; }
@@ -765,7 +821,25 @@ void or_mode_basis(double* e, double* b) {
 
 void or_site_noise(double kT, double tau, double rho, const uint32_t* seed, int64_t step, int64_t site,
                    double* xi, double magic) {
-  site_noise(kT, tau, rho, seed, step, (long)site, xi, magic);
+  site_noise(19, kT, tau, rho, seed, step, (long)site, xi, magic);
+}
+
+void or_site_noise_q(int32_t q, double kT, double tau, double rho, const uint32_t* seed, int64_t step,
+                     int64_t site, double* xi, double magic) {
+  site_noise(q == 27 ? 27 : 19, kT, tau, rho, seed, step, (long)site, xi, magic);
+}
+
+void or_site_normals_n(const uint32_t* seed, int64_t step, int64_t site, int32_t ncalls, double* z) {
+  site_normals(seed, step, (long)site, z, ncalls);
+}
+
+// D3Q27 basis: e[k * 27 + i] = e_k(c_i), b[k] = sum_i w_i e_k(c_i)^2, odd[k] = parity
+void or_mode_basis27(double* e, double* b, int32_t* odd) {
+  for (int k = 0; k < 27; ++k) {
+    for (int i = 0; i < 27; ++i) e[k * 27 + i] = mode27_poly(k, CV[i]);
+    b[k] = mode27_norm(k);
+    odd[k] = mode27_odd(k) ? 1 : 0;
+  }
 }
 
 // Velocities c[Q][3] and weights w[Q] of the set with q = 19 or 27; 1 for any other q.
@@ -983,9 +1057,9 @@ int or_step_sampled(const or_params* p, const double* g, const double* X, const 
       collide_node(m.Q, m.tau, m.rho0, gin, F, gout, m.trt_magic);
       if (m.kT > 0.0) {
         double rho = val(m.rho0);
-        for (int q = 0; q < 19; ++q) rho += gin[q];
-        double xi[19];
-        site_noise(m.kT, val(m.tau), rho, m.seed, s.step, src, xi, m.trt_magic);
+        for (int q = 0; q < m.Q; ++q) rho += gin[q];
+        double xi[QMAX];
+        site_noise(m.Q, m.kT, val(m.tau), rho, m.seed, s.step, src, xi, m.trt_magic);
         gout[i] += xi[i];
       }
       g_out[(long)m.Q * k + i] = gout[i];

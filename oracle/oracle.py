@@ -111,6 +111,10 @@ def lib():
         L.or_collide_node_q.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                         ctypes.c_double, dp, dp, dp]
         L.or_stream_q.argtypes = [ctypes.c_int32, ip, dp, dp]
+        L.or_site_noise_q.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                      up, ctypes.c_int64, ctypes.c_int64, dp, ctypes.c_double]
+        L.or_site_normals_n.argtypes = [up, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, dp]
+        L.or_mode_basis27.argtypes = [dp, dp, ip]
         _lib = L
     return _lib
 
@@ -350,13 +354,30 @@ def mode_basis():
     return e, b
 
 
-def site_noise(kT, tau, rho, seed, step, site, trt_magic=0.0):
-    """The thermal noise xi [19] added after the collision at one site."""
+def site_noise(kT, tau, rho, seed, step, site, trt_magic=0.0, q=19):
+    """The thermal noise xi [q] added after the collision at one site (q = 19 or 27)."""
     k, kp = _u32([seed & 0xffffffff, (seed >> 32) & 0xffffffff])
-    xi = np.zeros(19)
-    lib().or_site_noise(float(kT), float(tau), float(rho), kp, int(step), int(site), _d(xi),
-                        float(trt_magic))
+    xi = np.zeros(q)
+    lib().or_site_noise_q(int(q), float(kT), float(tau), float(rho), kp, int(step), int(site), _d(xi),
+                          float(trt_magic))
     return xi
+
+
+def site_normals_n(seed, step, site, ncalls):
+    """4 * ncalls standard normals of one site and step (ncalls = 4: D3Q19, 6: D3Q27)."""
+    k, kp = _u32([seed & 0xffffffff, (seed >> 32) & 0xffffffff])
+    z = np.zeros(4 * ncalls)
+    lib().or_site_normals_n(kp, int(step), int(site), int(ncalls), _d(z))
+    return z
+
+
+def mode_basis27():
+    """(e [27 modes, 27 velocities], b [27], odd [27]) of the D3Q27 tensor-product basis."""
+    e = np.zeros((27, 27))
+    b = np.zeros(27)
+    odd = np.zeros(27, np.int32)
+    lib().or_mode_basis27(_d(e), _d(b), _i(odd))
+    return e, b, odd
 
 
 def collide_node_trt(tau, magic, rho0, g, F):

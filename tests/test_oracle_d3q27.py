@@ -2,7 +2,9 @@
 Section 4 proposes), against facts that do not come from the oracle itself: the set is all of
 {-1, 0, 1}^3 with the tensor-product weights of the one-dimensional three-speed lattice, its
 moments in exact arithmetic, conservation and Guo moments of the collision, brute-force
-streaming, shear-wave decay at nu = (tau - 1/2)/3, and the momentum ledger of a coupled run."""
+streaming, shear-wave decay at nu = (tau - 1/2)/3, the momentum ledger of a coupled run, and
+for the thermal noise: an exactly orthogonal moment basis, exact conservation, the
+fluctuation-dissipation variance of every mode, and equipartition."""
 import itertools
 from fractions import Fraction
 
@@ -171,9 +173,98 @@ def test_coupled_mass_and_momentum_ledger(O):
     assert np.abs(V).max() > 0
 
 
-def test_noise_and_unknown_sets_are_refused(O):
-    p = O.make_params(4, 0.8, kT=1e-4, velocity_set=27)
-    with pytest.raises(RuntimeError):
-        O.run(p, np.zeros(O.pop_shape(p)), *NO_ATOMS, None, 1)
+def test_unknown_sets_are_refused(O):
     with pytest.raises(ValueError):
         O.velocity_set(15)
+    p = O.make_params(4, 0.8, velocity_set=15)
+    with pytest.raises(RuntimeError):
+        O.run(p, np.zeros((19, 4, 4, 4)), *NO_ATOMS, None, 1)
+
+
+# ---------------------------------------------------------------- thermal noise on D3Q27
+
+def test_mode_basis_orthogonal_in_exact_arithmetic(O):
+    """The 27 modes: integer polynomials of c, orthogonal under the D3Q27 weights with norms
+    n_a n_b n_c (n = 1, 1/3, 2 for the factors 1, c, 3c^2 - 1), density and momentum first,
+    parity under c -> -c as published."""
+    e, b, odd = O.mode_basis27()
+    c, w = O.velocity_set(27)
+    wf = [Fraction(x).limit_denominator(1000) for x in w]
+    ei = np.rint(e).astype(int)
+    assert np.array_equal(ei, e)
+    assert (ei[0] == 1).all() and (ei[1:4] == c.T).all()
+    norms = set()
+    for k in range(27):
+        for l in range(27):
+            s = sum(wf[i] * int(ei[k, i]) * int(ei[l, i]) for i in range(27))
+            if k != l:
+                assert s == 0, (k, l)
+            else:
+                assert abs(float(s) - b[k]) < 1e-14 * float(s)
+                norms.add(s)
+        where = {tuple(int(v) for v in c[i]): i for i in range(27)}
+        flipped = [where[tuple(-int(v) for v in c[i])] for i in range(27)]
+        sign = -1 if odd[k] else 1
+        assert (ei[k, flipped] == sign * ei[k]).all(), k
+    # every norm is a product of three factors from {1, 1/3, 2}
+    f = [Fraction(1), Fraction(1, 3), Fraction(2)]
+    products = {a * bb * cc for a in f for bb in f for cc in f}
+    assert norms <= products
+    assert int(odd.sum()) == 13        # the modes with an odd number of c factors
+
+
+def test_normal_stream_extends_the_d3q19_one(O):
+    """D3Q27 draws six Philox calls per site and step; the first four are the D3Q19 draws."""
+    z16 = O.site_normals(77, 12, 345)
+    z24 = O.site_normals_n(77, 12, 345, 6)
+    np.testing.assert_array_equal(z24[:16], z16)
+    extra = np.concatenate([O.site_normals_n(5, 3, s, 6)[16:] for s in range(3000)])
+    assert abs(extra.mean()) < 4.0 / np.sqrt(extra.size)
+    assert abs(extra.var() - 1.0) < 4.0 * np.sqrt(2.0 / extra.size)
+
+
+@pytest.mark.parametrize("magic", [0.0, 0.1875])
+def test_noise_conserves_and_has_mode_variances(O, magic):
+    e, b, odd = O.mode_basis27()
+    c, w = O.velocity_set(27)
+    kT, tau, rho = 2e-4, 0.7, 1.1
+    xi = np.stack([O.site_noise(kT, tau, rho, 99, 5, s, trt_magic=magic, q=27) for s in range(4000)])
+    scale = np.abs(xi).max()
+    assert np.abs(xi.sum(1)).max() < 1e-15 * 27 * scale
+    assert np.abs(xi @ c).max() < 1e-15 * 27 * scale
+    m = xi @ e.T
+    om_p = 1.0 / tau
+    om_m = 1.0 / (0.5 + magic / (tau - 0.5)) if magic > 0 else om_p
+    om = np.where(odd == 1, om_m, om_p)
+    want = 3.0 * rho * kT * b * (1.0 - (1.0 - om) ** 2)
+    var = (m ** 2).mean(0)
+    assert np.all(var[:4] < 1e-25)
+    rel = var[4:] / want[4:]
+    tol = 4.0 * np.sqrt(2.0 / m.shape[0])
+    assert np.all(np.abs(rel - 1.0) < tol), rel
+
+
+def test_thermal_equipartition(O):
+    """<u^2> per component = kT (1 - 1/S) and <(rho - rho0)^2> = 3 kT (1 - 1/S) on an 8^3
+    lattice at kT = 1e-4, with mass and momentum exact."""
+    L, tau, kT = 8, 0.8, 1e-4
+    p = O.make_params(L, tau, kT=kT, seed=2027, velocity_set=27)
+    S = L ** 3
+    g = np.zeros(O.pop_shape(p))
+    X = np.zeros((0, 3))
+    u2, r2 = [], []
+    step, burn, every, total = 0, 150, 3, 1350
+    while step < total:
+        p.step0 = step
+        g, _, _ = O.run(p, g, X, X, X, np.zeros((0, 2), np.int32), None, every)
+        step += every
+        if step > burn:
+            rho, u = O.observables(p, g)
+            u2.append((u ** 2).mean())
+            r2.append(((rho - 1.0) ** 2).mean())
+    inv = O.invariants(p, g, X)
+    assert abs(inv[0] - S) < 1e-11 * S
+    assert np.abs(inv[1:4]).max() < 1e-13
+    u2m, r2m = np.mean(u2), np.mean(r2)
+    assert abs(u2m / (kT * (1 - 1 / S)) - 1.0) < 0.06, u2m
+    assert abs(r2m / (3 * kT * (1 - 1 / S)) - 1.0) < 0.06, r2m
