@@ -113,8 +113,8 @@ typedef struct {
   int32_t velocity_set;      /* lattice velocities: 19 (D3Q19, the set of Eq. 1; 0 also means
                                 19) or 27 (D3Q27, the higher-order set of the outlook in
                                 Section 4: same equilibrium, forcing and collision over its 27
-                                velocities).  With 27, kT must be 0 (the noise is defined on the
-                                D3Q19 moment basis) */
+                                velocities; its thermal noise uses the orthogonal basis of
+                                products of the one-dimensional polynomials 1, c, 3c^2 - 1) */
 } lb_params;
 
 /* The 19 lattice velocities c[i][0..2] and weights w[i] in the library's ordering:

@@ -124,7 +124,7 @@ __device__ __forceinline__ void collide_adjoint(float mu[Q], const float g[Q], f
   }
 }
 
-// per-site work shared by the tile pass and the sweep (thermal noise: Q = 19 only)
+// per-site work shared by the tile pass and the sweep
 template <int ST, int Q>
 __device__ __forceinline__ void adj_site(const AdjLatticeArgs& a, int s, bool hot, bool sweep,
                                          float& dom_p, float& dom_m) {
@@ -146,17 +146,15 @@ __device__ __forceinline__ void adj_site(const AdjLatticeArgs& a, int s, bool ho
     Fz += a.fcoup[2 * a.plane + s];
   }
   // the noise does not depend on F, so only the sweep needs its terms
-  const bool noise = Q == 19 && sweep && a.kT > 0.f;
+  const bool noise = sweep && a.kT > 0.f;
   float mpe = 0.f, mpo = 0.f;   // sum_i mu_i pe_i, sum_i mu_i po_i of the noise patterns
-  if constexpr (Q == 19) {
-    if (noise) {
-      float pe[19], po[19];
-      noise_patterns(a.seed0, a.seed1, a.step, s, pe, po);
+  if (noise) {
+    float pe[Q], po[Q];
+    noise_patterns<Q>(a.seed0, a.seed1, a.step, s, pe, po);
 #pragma unroll
-      for (int i = 0; i < 19; ++i) {
-        mpe += mu[i] * pe[i];
-        mpo += mu[i] * po[i];
-      }
+    for (int i = 0; i < Q; ++i) {
+      mpe += mu[i] * pe[i];
+      mpo += mu[i] * po[i];
     }
   }
   float phx, phy, phz, rho, jx, jy, jz;

@@ -131,9 +131,13 @@ __device__ __forceinline__ bool collide(float g[Q], float Fx, float Fy, float Fz
 // receives variance 3 rho kT b_k (1 - (1 - omega)^2), which keeps it at its equilibrium
 // fluctuation under the relaxation factor 1 - omega; mass and momentum get none.
 //
+// On the D3Q27 lattice the basis is the products P_a(c_x) P_b(c_y) P_c(c_z) of the
+// one-dimensional three-speed polynomials P_0 = 1, P_1 = c, P_2 = 3 c^2 - 1 (norms 1, 1/3, 2
+// under the weights 2/3, 1/6, 1/6): density and momentum, then 23 non-conserved modes.
+//
 // Normals: Philox4x32-10 (a counter-based generator) keyed by the seed, counter (site, step
-// low word, step high word, q) for q = 0..3; each 32-bit output w gives the uniform
-// ((w >> 8) + 1/2) 2^-24, and pairs of uniforms give Box-Muller normals.
+// low word, step high word, q) for q = 0..3 (D3Q19) or 0..5 (D3Q27); each 32-bit output w
+// gives the uniform ((w >> 8) + 1/2) 2^-24, and pairs of uniforms give Box-Muller normals.
 
 __device__ __forceinline__ void philox4x32_10(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
                                               uint32_t k0, uint32_t k1, uint32_t out[4]) {
@@ -187,11 +191,35 @@ constexpr float mode_inv_sqrt_norm(int k) {
                                                  : 0.7071067811865476f;    // b = 2 (k = 16)
 }
 
-// the 16 normals of one site and step
+// D3Q27 non-conserved modes k = 4..26 as codes a + 3 b + 9 c of their factor indices
+// (P_a(c_x) P_b(c_y) P_c(c_z)), in increasing code
+constexpr int MODE27_CODE[23] = {2, 4, 5, 6, 7, 8, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20,
+                                 21, 22, 23, 24, 25, 26};
+
+constexpr float poly3(int a, int c) { return a == 0 ? 1.f : (a == 1 ? (float)c : 3.f * c * c - 1.f); }
+// 1 / sqrt of the factor norms 1, 1/3, 2
+constexpr float inv_sqrt_norm3(int a) { return a == 0 ? 1.f : (a == 1 ? 1.7320508075688772f : 0.7071067811865476f); }
+
+// D3Q27 mode k (4..26) at velocity (cx, cy, cz), divided by sqrt(b_k); folded at compile time
+constexpr float mode27_scaled(int k, int cx, int cy, int cz) {
+  const int code = MODE27_CODE[k - 4];
+  const int a = code % 3, b = (code / 3) % 3, c = code / 9;
+  return poly3(a, cx) * poly3(b, cy) * poly3(c, cz) * inv_sqrt_norm3(a) * inv_sqrt_norm3(b) *
+         inv_sqrt_norm3(c);
+}
+
+// odd under c -> -c: an odd number of P_1 factors
+constexpr bool mode27_odd(int k) {
+  const int code = MODE27_CODE[k - 4];
+  return (((code % 3) == 1) + (((code / 3) % 3) == 1) + ((code / 9) == 1)) % 2 == 1;
+}
+
+// the 4 NC normals of one site and step (NC = 4 for D3Q19, 6 for D3Q27)
+template <int NC = 4>
 __device__ __forceinline__ void site_normals(uint32_t seed0, uint32_t seed1, int64_t step, int site,
-                                             float z[16]) {
+                                             float z[4 * NC]) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < NC; ++q) {
     uint32_t w[4];
     philox4x32_10((uint32_t)site, (uint32_t)((uint64_t)step & 0xffffffffu), (uint32_t)((uint64_t)step >> 32),
                   (uint32_t)q, seed0, seed1, w);
@@ -209,25 +237,29 @@ __device__ __forceinline__ void site_normals(uint32_t seed0, uint32_t seed1, int
 }
 
 // The unit-amplitude noise patterns of one site and step: pe from the modes even under
-// c -> -c, po from the odd ones (k = 10..15); the noise is A+ pe + A- po, with A- = A+ unless
-// the two-relaxation-time collision relaxes the odd modes at omega-.
+// c -> -c, po from the odd ones (D3Q19: k = 10..15); the noise is A+ pe + A- po, with
+// A- = A+ unless the two-relaxation-time collision relaxes the odd modes at omega-.
+template <int Q = 19>
 __device__ __forceinline__ void noise_patterns(uint32_t seed0, uint32_t seed1, int64_t step, int site,
-                                               float pe[19], float po[19]) {
-  float z[16];
-  site_normals(seed0, seed1, step, site, z);
+                                               float pe[Q], float po[Q]) {
+  constexpr int NC = Q == 27 ? 6 : 4;
+  float z[4 * NC];
+  site_normals<NC>(seed0, seed1, step, site, z);
 #pragma unroll
-  for (int i = 0; i < 19; ++i) {
+  for (int i = 0; i < Q; ++i) {
     float ae = 0.f, ao = 0.f;
 #pragma unroll
-    for (int k = 4; k < 19; ++k) {
-      const float e = mode_poly(k, CX[i], CY[i], CZ[i]) * mode_inv_sqrt_norm(k);
+    for (int k = 4; k < Q; ++k) {
+      const float e = Q == 27 ? mode27_scaled(k, CX[i], CY[i], CZ[i])
+                              : mode_poly(k, CX[i], CY[i], CZ[i]) * mode_inv_sqrt_norm(k);
+      const bool odd = Q == 27 ? mode27_odd(k) : (k >= 10 && k <= 15);
       if (e != 0.f) {
-        if (k >= 10 && k <= 15) ao += e * z[k - 4];
+        if (odd) ao += e * z[k - 4];
         else ae += e * z[k - 4];
       }
     }
-    pe[i] = WQ[i] * ae;
-    po[i] = WQ[i] * ao;
+    pe[i] = wq<Q>(i) * ae;
+    po[i] = wq<Q>(i) * ao;
   }
 }
 

@@ -43,10 +43,9 @@ struct SweepArgs {
   float omega_m;               // rate of the odd part (TRT instances only)
 };
 
-// Q velocities; the thermal noise is defined for Q = 19 only
+// Q velocities (19 or 27)
 template <int ST, bool NOISE, bool TRT, int Q>
 __device__ __forceinline__ void sweep_site(const SweepArgs& a, int s, bool hot) {
-  static_assert(!NOISE || Q == 19, "thermal noise needs the D3Q19 moment basis");
   using T = typename Store<ST>::T;
   const int x = s % a.nx;
   const int t = s / a.nx;
@@ -72,19 +71,19 @@ __device__ __forceinline__ void sweep_site(const SweepArgs& a, int s, bool hot) 
   if constexpr (NOISE) {
     rho = a.rho0;
 #pragma unroll
-    for (int i = 0; i < 19; ++i) rho += g[i];
+    for (int i = 0; i < Q; ++i) rho += g[i];
   }
   bool ok;
   if constexpr (TRT) ok = collide_trt<Q>(g, Fx, Fy, Fz, a.rho0, a.omega, a.omega_m);
   else ok = collide<Q>(g, Fx, Fy, Fz, a.rho0, a.omega, a.pref);
   if (!ok) atomicOr(a.err, kErrNonFinite);
   if constexpr (NOISE) {
-    float pe[19], po[19];
-    noise_patterns(a.seed0, a.seed1, a.step, s, pe, po);
+    float pe[Q], po[Q];
+    noise_patterns<Q>(a.seed0, a.seed1, a.step, s, pe, po);
     const float Ap = noise_amp(a.kT, rho, a.omega);
     const float Am = TRT ? noise_amp(a.kT, rho, a.omega_m) : Ap;
 #pragma unroll
-    for (int i = 0; i < 19; ++i) g[i] += Ap * pe[i] + Am * po[i];
+    for (int i = 0; i < Q; ++i) g[i] += Ap * pe[i] + Am * po[i];
   }
   T* out = reinterpret_cast<T*>(a.fout);
 #pragma unroll
@@ -103,8 +102,10 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
 template <int ST>
 void launch_sweep_st(int q, bool noise, bool trt, dim3 grid, dim3 block, hipStream_t st,
                      const SweepArgs& a) {
-  if (q == 27) {   // no noise (refused at initialisation)
-    if (trt) hipLaunchKernelGGL((k_sweep<ST, false, true, 27>), grid, block, 0, st, a);
+  if (q == 27) {
+    if (noise && trt) hipLaunchKernelGGL((k_sweep<ST, true, true, 27>), grid, block, 0, st, a);
+    else if (noise) hipLaunchKernelGGL((k_sweep<ST, true, false, 27>), grid, block, 0, st, a);
+    else if (trt) hipLaunchKernelGGL((k_sweep<ST, false, true, 27>), grid, block, 0, st, a);
     else hipLaunchKernelGGL((k_sweep<ST, false, false, 27>), grid, block, 0, st, a);
   } else if (noise && trt) hipLaunchKernelGGL((k_sweep<ST, true, true, 19>), grid, block, 0, st, a);
   else if (noise) hipLaunchKernelGGL((k_sweep<ST, true, false, 19>), grid, block, 0, st, a);

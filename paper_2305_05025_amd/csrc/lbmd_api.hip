@@ -111,8 +111,6 @@ static std::string validate(const lb_params* p) {
   if (!finite(p->trt_magic) || p->trt_magic < 0.0f) return "trt_magic must be finite and >= 0";
   if (p->velocity_set != 0 && p->velocity_set != 19 && p->velocity_set != 27)
     return "velocity_set must be 19 or 27 (0 means 19)";
-  if (p->velocity_set == 27 && p->kT > 0.0f)
-    return "thermal noise (kT > 0) is defined on the D3Q19 moment basis: use velocity_set 19";
   if (!finite(p->rho0) || !(p->rho0 > 0.0f)) return "rho0 must be finite and > 0";
   if (p->storage < LB_STORE_F32 || p->storage > LB_STORE_BF16) return "unknown storage format";
   if (p->bf_kind < LB_BF_NONE || p->bf_kind > LB_BF_FIELD) return "unknown body-force kind";

@@ -77,7 +77,6 @@ def test_workspace_bytes():
     (dict(n_atoms=0, n_bonds=3), "bonds"),
     (dict(n_atoms=-1), "n_atoms"),
     (dict(velocity_set=15), "velocity_set"),
-    (dict(velocity_set=27, kT=1e-4), "moment basis"),
 ])
 def test_invalid_parameters_rejected_before_device_work(kw, msg):
     p = _params(**kw)

@@ -2,8 +2,9 @@
 the oracle: the fused sweep from random states on ragged lattices (BGK and two relaxation
 times, every body-force kind), a shear wave with Kolmogorov forcing over 100 steps, the
 narrow storage formats' one-step bound, the population upload, coupled globules, one
-full-size sampled step at 256^3 with 200,000 atoms in the benchmarked schedule, and the
-adjoint against the oracle's exact derivatives."""
+full-size sampled step at 256^3 with 200,000 atoms in the benchmarked schedule, the adjoint
+against the oracle's exact derivatives, and the thermal noise on the 27-mode basis (parity,
+equipartition, adjoint)."""
 import numpy as np
 import pytest
 
@@ -169,3 +170,60 @@ def test_adjoint_linear_ball_two_relaxation_times(O):
     dfields = _dfields(rng, field.shape)
     outs, _ = _gpu_grads(w, field, D, 20, 7)
     _check(outs, _oracle_grads(O, w, field, D, 20, dfields), dfields, 2e-4)
+
+
+# ------------------------------------------------------------------ thermal noise on D3Q27
+
+@pytest.mark.parametrize("magic", [0.0, 0.1875])
+def test_thermal_fluid_parity(O, magic):
+    """The same Philox noise on the 27-mode basis as the oracle (BGK and two relaxation
+    times), 25 steps."""
+    w = _ball((20, 16, 12), seed=3, tau=0.8, steps=0, kT=1e-4, noise_seed=77, trt_magic=magic)
+    r = compare(gpu_run(w, 25), oracle_run(O, w, 25), w)
+    say("d3q27 thermal fluid", magic, r)
+    assert r["g"] < 1e-5 and r["u"] < 1e-5 and r["rho"] < 1e-5, r
+
+
+def test_thermal_coupled_parity(O):
+    w = _ball((24, 20, 18), 200, seed=8, tau=0.8, gamma=0.1, k_tether=0.05, mass=8.0, kT=1e-5,
+              noise_seed=5)
+    r = compare(gpu_run(w, 10), oracle_run(O, w, 10), w)
+    say("d3q27 thermal coupled ball", r)
+    assert max(r.values()) < 1e-5, r
+
+
+def test_equipartition_on_gpu():
+    """<u^2> = kT/rho0 per component and <(rho - rho0)^2> = 3 rho0 kT (times 1 - 1/S) on a
+    32^3 thermal lattice, within 2%; mass and momentum to FP32 round-off."""
+    from paper_2305_05025_amd.coupled import CoupledLB, make_params
+    L, kT = 32, 1e-4
+    sim = CoupledLB(make_params(L, 0.8, kT=kT, seed=31, velocity_set=27))
+    sim.step(400)
+    u2, r2 = [], []
+    for _ in range(150):
+        sim.step(20)
+        rho, u, _, _ = sim.read_fields()
+        u2.append(float((u.double() ** 2).mean()))
+        r2.append(float(((rho.double() - 1.0) ** 2).mean()))
+    inv = sim.invariants()
+    sim.close()
+    S = L ** 3
+    ru = np.mean(u2) / (kT * (1 - 1 / S))
+    rr = np.mean(r2) / (3 * kT * (1 - 1 / S))
+    say("d3q27 GPU equipartition: %.4f %.4f" % (ru, rr))
+    assert abs(ru - 1) < 0.02 and abs(rr - 1) < 0.02
+    assert abs(inv[0] - S) < 1e-7 * S and max(abs(x) for x in inv[1:4]) < 1e-7 * S
+
+
+def test_adjoint_with_noise(O):
+    from test_gpu_adjoint import _check, _dfields, _gpu_grads, _oracle_grads
+    from workloads import globule_workload
+    L = 10
+    w = globule_workload(L, 1, 60, seed=21, tau=0.7, gamma=0.15, kT=1e-5, noise_seed=123,
+                         velocity_set=27)
+    rng = np.random.default_rng(3)
+    field = rng.normal(0, 1e-5, size=(3, L, L, L))
+    D = np.array([0.6, -0.48, 0.64])
+    dfields = _dfields(rng, field.shape)
+    outs, _ = _gpu_grads(w, field, D, 12, 5)
+    _check(outs, _oracle_grads(O, w, field, D, 12, dfields), dfields, 1e-3)
