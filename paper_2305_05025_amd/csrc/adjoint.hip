@@ -59,6 +59,8 @@ struct AdjLatticeArgs {
   float kT;               // thermal noise of the forward step (0: none)
   uint32_t seed0, seed1;
   int64_t step;
+  FastDiv dnx, dny;
+  int narrow;             // the FP32 Lam planes (and so the population planes) take 32-bit byte offsets
 };
 
 // Adjoint of the collision at one site (Q = 19 or 27 velocities): from mu (adjoint of the
@@ -129,14 +131,18 @@ template <int ST, int Q>
 __device__ __forceinline__ void adj_site(const AdjLatticeArgs& a, int s, bool hot, bool sweep,
                                          float& dom_p, float& dom_m) {
   using T = typename Store<ST>::T;
-  const int x = s % a.nx;
-  const int t = s / a.nx;
-  const int y = t % a.ny;
-  const int z = t / a.ny;
+  int x, y, z;
+  site_xyz(s, a.nx, a.ny, a.dnx, a.dny, x, y, z);
   float g[Q], mu[Q];
-  gather<ST, Q>(reinterpret_cast<const T*>(a.P), a.plane, x, y, z, a.nx, a.ny, a.nz, g);
+  const bool narrow = a.narrow != 0;
+  gather<ST, Q>(reinterpret_cast<const T*>(a.P), a.plane, x, y, z, a.nx, a.ny, a.nz, narrow, g);
+  if (narrow) {
 #pragma unroll
-  for (int i = 0; i < Q; ++i) mu[i] = a.lam_in[(size_t)i * a.plane + s];
+    for (int i = 0; i < Q; ++i) mu[i] = *plane_at(a.lam_in, i, a.plane, 4u * (uint32_t)s);
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) mu[i] = a.lam_in[(size_t)i * a.plane + s];
+  }
   float Ex, Ey, Ez;
   external_force(a.bf_kind, a.fext_tab, a.fext_field, a.plane, s, y, Ex, Ey, Ez);
   float Fx = Ex, Fy = Ey, Fz = Ez;
@@ -201,13 +207,22 @@ __device__ __forceinline__ void adj_site(const AdjLatticeArgs& a, int s, bool ho
   const int ym = y == 0 ? a.ny - 1 : y - 1, yp = y == a.ny - 1 ? 0 : y + 1;
   const int zm = z == 0 ? a.nz - 1 : z - 1, zp = z == a.nz - 1 ? 0 : z + 1;
   const int nxy = a.nx * a.ny;
-  const int X3[3] = {xm, x, xp};
-  const int Y3[3] = {ym * a.nx, y * a.nx, yp * a.nx};
-  const int Z3[3] = {zm * nxy, z * nxy, zp * nxy};
+  if (narrow) {
+    const uint32_t X3[3] = {4u * xm, 4u * x, 4u * xp};
+    const uint32_t Y3[3] = {4u * a.nx * ym, 4u * a.nx * y, 4u * a.nx * yp};
+    const uint32_t Z3[3] = {4u * nxy * zm, 4u * nxy * z, 4u * nxy * zp};
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const int dst = X3[1 - CX[i]] + Y3[1 - CY[i]] + Z3[1 - CZ[i]];
-    a.lam_out[(size_t)i * a.plane + dst] = mu[i];
+    for (int i = 0; i < Q; ++i)
+      *plane_at(a.lam_out, i, a.plane, X3[1 - CX[i]] + Y3[1 - CY[i]] + Z3[1 - CZ[i]]) = mu[i];
+  } else {
+    const int X3[3] = {xm, x, xp};
+    const int Y3[3] = {ym * a.nx, y * a.nx, yp * a.nx};
+    const int Z3[3] = {zm * nxy, z * nxy, zp * nxy};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int dst = X3[1 - CX[i]] + Y3[1 - CY[i]] + Z3[1 - CZ[i]];
+      a.lam_out[(size_t)i * a.plane + dst] = mu[i];
+    }
   }
 }
 
@@ -507,6 +522,10 @@ static AdjLatticeArgs lattice_args(lb_ctx* c, const AdjointBuffers& b) {
   a.seed0 = c->p.seed[0];
   a.seed1 = c->p.seed[1];
   a.step = c->step;
+  a.dnx = c->geo.div_nx;
+  a.dny = c->geo.div_ny;
+  // the Lam planes are FP32 whatever the storage format
+  a.narrow = c->geo.narrow && (uint64_t)c->geo.S * 4u <= (1ull << 32) ? 1 : 0;
   return a;
 }
 

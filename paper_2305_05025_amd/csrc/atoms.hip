@@ -265,6 +265,8 @@ struct NodeArgs {
   const int* node_list;
   const int* node_count;
   float* uc;   // [3][plane]
+  FastDiv dnx, dny;
+  int narrow;  // planes take 32-bit byte offsets
 };
 
 // one thread per flagged node (persistent over the node list)
@@ -274,12 +276,11 @@ __global__ __launch_bounds__(256) void k_node_u(NodeArgs a) {
   const int n = *a.node_count;
   for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
     const int s = a.node_list[k];
-    const int x = s % a.nx;
-    const int t = s / a.nx;
-    const int y = t % a.ny;
-    const int z = t / a.ny;
+    int x, y, z;
+    site_xyz(s, a.nx, a.ny, a.dnx, a.dny, x, y, z);
     float g[Q];
-    gather<ST, Q>(reinterpret_cast<const T*>(a.f), a.plane, x, y, z, a.nx, a.ny, a.nz, g);
+    gather<ST, Q>(reinterpret_cast<const T*>(a.f), a.plane, x, y, z, a.nx, a.ny, a.nz,
+                  a.narrow != 0, g);
     float drho, jx, jy, jz, Fx, Fy, Fz;
     moments<Q>(g, drho, jx, jy, jz);
     external_force(a.bf_kind, a.fext_tab, a.fext_field, a.plane, s, y, Fx, Fy, Fz);
@@ -928,6 +929,9 @@ hipError_t launch_node_u(lb_ctx* c) {
   a.node_list = (const int*)(c->ws + c->lay.node_list[c->step & 1]);
   a.node_count = (const int*)(c->ws + c->lay.occ_count[c->step & 1]) + 2;
   a.uc = (float*)(c->ws + c->lay.uc);
+  a.dnx = g.div_nx;
+  a.dny = g.div_ny;
+  a.narrow = g.narrow ? 1 : 0;
   const dim3 grid(node_grid(c)), block(256);
   const bool q27 = c->geo.q == 27;
   switch (c->p.storage) {

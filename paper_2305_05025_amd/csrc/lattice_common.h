@@ -3,6 +3,8 @@
 // external force density.
 #pragma once
 
+#include <type_traits>
+
 #include "lbmd_internal.h"
 
 namespace lbmd {
@@ -14,16 +16,20 @@ struct Store;
 template <>
 struct Store<LB_STORE_F32> {
   using T = float;
-  static __device__ __forceinline__ float ld(const T* p) { return *p; }
-  static __device__ __forceinline__ void st(T* p, float v) { __builtin_nontemporal_store(v, p); }
+  template <class P>
+  static __device__ __forceinline__ float ld(const P* p) { return *p; }
+  template <class P>
+  static __device__ __forceinline__ void st(P* p, float v) { __builtin_nontemporal_store(v, p); }
 };
 
 template <>
 struct Store<LB_STORE_F16> {
   using T = _Float16;
-  static __device__ __forceinline__ float ld(const T* p) { return (float)*p; }
+  template <class P>
+  static __device__ __forceinline__ float ld(const P* p) { return (float)*p; }
   // conversion to binary16 rounds to nearest even; subnormals are kept
-  static __device__ __forceinline__ void st(T* p, float v) {
+  template <class P>
+  static __device__ __forceinline__ void st(P* p, float v) {
     __builtin_nontemporal_store((_Float16)v, p);
   }
 };
@@ -31,10 +37,12 @@ struct Store<LB_STORE_F16> {
 template <>
 struct Store<LB_STORE_BF16> {
   using T = uint16_t;
-  static __device__ __forceinline__ float ld(const T* p) {
+  template <class P>
+  static __device__ __forceinline__ float ld(const P* p) {
     return __uint_as_float((uint32_t)(*p) << 16);
   }
-  static __device__ __forceinline__ void st(T* p, float v) {
+  template <class P>
+  static __device__ __forceinline__ void st(P* p, float v) {
     uint32_t u = __float_as_uint(v);
     uint16_t h;
     if ((u & 0x7fffffffu) > 0x7f800000u) {
@@ -47,23 +55,63 @@ struct Store<LB_STORE_BF16> {
   }
 };
 
+// ---- site coordinates ------------------------------------------------------------------
+// s = x + nx (y + ny z) -> (x, y, z), by the invariant-divisor multiplications of FastDiv
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv d) {
+  return (__umulhi(n, d.m) + n) >> d.l;
+}
+__device__ __forceinline__ void site_xyz(int s, int nx, int ny, FastDiv dnx, FastDiv dny, int& x,
+                                         int& y, int& z) {
+  const uint32_t t = fdiv((uint32_t)s, dnx);
+  const uint32_t zz = fdiv(t, dny);
+  x = s - (int)t * nx;
+  y = (int)t - (int)zz * ny;
+  z = (int)zz;
+}
+
+// Element at byte offset `off` of population plane i, for lattices whose planes hold at
+// most 4 GiB of sites.  The plane's base is uniform across the launch; the empty asm statement
+// pins it to scalar registers as an opaque value, so every access takes the scalar-base +
+// 32-bit-lane-offset form.  (Without it the compiler folds the shared lane offset of a site's
+// Q stores into one 64-bit lane address and adds each plane's stride to it in 64-bit vector
+// arithmetic.)
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* plane_at(T* f, int i, long plane,
+                                                                       uint32_t off) {
+  uint64_t b = reinterpret_cast<uint64_t>(f + (size_t)i * plane);
+  asm("" : "+s"(b));
+  return (__attribute__((address_space(1))) T*)(b + off);
+}
+
 // ---- pull gather: pre-collision values at (x, y, z) -----------------------------------------
-// Q = 19 or 27 velocities (the default 19 is the D3Q19 set of Eq. 1)
+// Q = 19 or 27 velocities (the default 19 is the D3Q19 set of Eq. 1).  `narrow`: the
+// lattice's planes fit 32-bit byte offsets (uniform across the launch).
 template <int ST, int Q = 19>
 __device__ __forceinline__ void gather(const typename Store<ST>::T* __restrict__ f, long plane,
-                                       int x, int y, int z, int nx, int ny, int nz,
+                                       int x, int y, int z, int nx, int ny, int nz, bool narrow,
                                        float g[Q]) {
+  using T = typename Store<ST>::T;
   const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
   const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
   const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
   const int nxy = nx * ny;
-  const int X3[3] = {xm, x, xp};
-  const int Y3[3] = {ym * nx, y * nx, yp * nx};
-  const int Z3[3] = {zm * nxy, z * nxy, zp * nxy};
+  if (narrow) {
+    constexpr uint32_t E = sizeof(T);
+    const uint32_t X3[3] = {E * xm, E * x, E * xp};
+    const uint32_t Y3[3] = {E * nx * ym, E * nx * y, E * nx * yp};
+    const uint32_t Z3[3] = {E * nxy * zm, E * nxy * z, E * nxy * zp};
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const int src = X3[1 - CX[i]] + Y3[1 - CY[i]] + Z3[1 - CZ[i]];
-    g[i] = Store<ST>::ld(f + (size_t)i * plane + src);
+    for (int i = 0; i < Q; ++i)
+      g[i] = Store<ST>::ld(plane_at(f, i, plane, X3[1 - CX[i]] + Y3[1 - CY[i]] + Z3[1 - CZ[i]]));
+  } else {
+    const int X3[3] = {xm, x, xp};
+    const int Y3[3] = {ym * nx, y * nx, yp * nx};
+    const int Z3[3] = {zm * nxy, z * nxy, zp * nxy};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int src = X3[1 - CX[i]] + Y3[1 - CY[i]] + Z3[1 - CZ[i]];
+      g[i] = Store<ST>::ld(f + (size_t)i * plane + src);
+    }
   }
 }
 

@@ -41,18 +41,19 @@ struct SweepArgs {
   uint32_t seed0, seed1;
   int64_t step;
   float omega_m;               // rate of the odd part (TRT instances only)
+  FastDiv dnx, dny;
+  int narrow;                  // planes take 32-bit byte offsets
 };
 
 // Q velocities (19 or 27)
 template <int ST, bool NOISE, bool TRT, int Q>
 __device__ __forceinline__ void sweep_site(const SweepArgs& a, int s, bool hot) {
   using T = typename Store<ST>::T;
-  const int x = s % a.nx;
-  const int t = s / a.nx;
-  const int y = t % a.ny;
-  const int z = t / a.ny;
+  int x, y, z;
+  site_xyz(s, a.nx, a.ny, a.dnx, a.dny, x, y, z);
   float g[Q];
-  gather<ST, Q>(reinterpret_cast<const T*>(a.fin), a.plane, x, y, z, a.nx, a.ny, a.nz, g);
+  gather<ST, Q>(reinterpret_cast<const T*>(a.fin), a.plane, x, y, z, a.nx, a.ny, a.nz,
+                a.narrow != 0, g);
   float Fx, Fy, Fz;
   external_force(a.bf_kind, a.fext_tab, a.fext_field, a.plane, s, y, Fx, Fy, Fz);
   if (hot) {
@@ -86,13 +87,21 @@ __device__ __forceinline__ void sweep_site(const SweepArgs& a, int s, bool hot) 
     for (int i = 0; i < Q; ++i) g[i] += Ap * pe[i] + Am * po[i];
   }
   T* out = reinterpret_cast<T*>(a.fout);
+  if (a.narrow) {
+    const uint32_t so = (uint32_t)s * (uint32_t)sizeof(T);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) Store<ST>::st(out + (size_t)i * a.plane + s, g[i]);
+    for (int i = 0; i < Q; ++i) Store<ST>::st(plane_at(out, i, a.plane, so), g[i]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) Store<ST>::st(out + (size_t)i * a.plane + s, g[i]);
+  }
 }
 
-// One thread per site, in site order.
+// One thread per site, in site order.  The instances without noise are held to 64 VGPRs (8
+// wavefronts per SIMD) except the D3Q27 TRT one, which would spill there.
 template <int ST, bool NOISE, bool TRT, int Q>
-__global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
+__global__ __launch_bounds__(kSweepBlock)
+__attribute__((amdgpu_waves_per_eu(NOISE || (TRT && Q == 27) ? 1 : 8))) void k_sweep(SweepArgs a) {
   const int s = blockIdx.x * kSweepBlock + threadIdx.x;
   if (s >= a.S) return;
   const bool hot = a.tile_flag != nullptr && a.tile_flag[s >> kTileShift] != 0u;
@@ -157,7 +166,7 @@ __global__ __launch_bounds__(256) void k_read(ReadArgs a) {
   const int y = t % a.ny;
   const int z = t / a.ny;
   float g[Q];
-  gather<ST, Q>(reinterpret_cast<const T*>(a.f), a.plane, x, y, z, a.nx, a.ny, a.nz, g);
+  gather<ST, Q>(reinterpret_cast<const T*>(a.f), a.plane, x, y, z, a.nx, a.ny, a.nz, false, g);
   if (a.pops) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) a.pops[(size_t)i * a.S + s] = g[i];
@@ -393,6 +402,9 @@ hipError_t launch_sweep(lb_ctx* c, const void* fin, void* fout, hipStream_t st) 
   a.seed1 = c->p.seed[1];
   a.step = c->step;
   a.omega_m = c->omega_m;
+  a.dnx = g.div_nx;
+  a.dny = g.div_ny;
+  a.narrow = g.narrow ? 1 : 0;
   const dim3 block(kSweepBlock), grid(g.nblocks);
   const bool noise = c->p.kT > 0.0f, trt = c->p.trt_magic > 0.0f;
   switch (c->p.storage) {

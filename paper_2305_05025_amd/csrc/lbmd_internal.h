@@ -84,6 +84,22 @@ struct Layout {
   size_t total;
 };
 
+// Division by a run-time invariant divisor d >= 1 with a multiply-high, an add and a shift
+// (Granlund and Montgomery, "Division by invariant integers using multiplication", PLDI 1994,
+// Section 4): with l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d) + 1,
+// floor(n / d) = (mulhi(n, m) + n) >> l for every 0 <= n < 2^32 whose sum does not overflow,
+// so for all n < 2^31 (site indices).
+struct FastDiv {
+  uint32_t m;
+  uint32_t l;
+};
+inline FastDiv make_fastdiv(uint32_t d) {
+  uint32_t l = 0;
+  while ((1ull << l) < d) ++l;
+  const uint64_t m = ((1ull << 32) * ((1ull << l) - d)) / d + 1;
+  return {(uint32_t)m, l};
+}
+
 constexpr int kRedBlocks = 1024;
 constexpr int kTimedEvents = 8;
 
@@ -98,6 +114,12 @@ struct Geometry {
   long ncell;
   float inv_cw[3];   // 1 / cell width
   size_t elem;       // bytes per stored population value
+  FastDiv div_nx, div_ny;  // site index -> (x, y, z)
+  // Every population plane's sites fit in 4 GiB (S * elem <= 2^32): the lattice kernels then
+  // address a plane by a scalar base and a 32-bit lane byte offset.  Setting the environment
+  // variable LBMD_WIDE_OFFSETS (any value) at context creation keeps the 64-bit addressing
+  // that larger lattices take, so both forms can be compared on small ones.
+  bool narrow;
 };
 
 bool geometry(const lb_params* p, Geometry* g);
