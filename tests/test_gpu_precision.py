@@ -58,3 +58,52 @@ def test_storage_formats_coupled_globule(O):
         assert rows["gpu-f32"][k] < max(50 * floor[k], 1e-5), (k, rows)
     assert rows["gpu-f16"]["u"] < 5e-2
     assert rows["gpu-bf16"]["u"] < 2e-1
+
+
+def test_storage_formats_full_size_500_steps():
+    """The 256^3 / 200,000-atom workload at its full size, read after 50 and after 500 steps.
+    The oracle cannot run this (its Lennard-Jones term is O(N^2)), so the narrow formats are
+    compared with the GPU's FP32 path, whose parity with the oracle is checked on smaller
+    cases and on one full-size step.  An FP32 run whose initial velocities differ by one ulp
+    gives the spread that the chaotic atom dynamics alone produce.  After 500 steps that
+    spread is of order one and the formats' differences lie within it (gate: 1.3x the spread
+    for FP16, 2x for BF16); after 50 steps the spread is still small and the formats' own
+    error shows (gate: u within 1e-3 for FP16, 1e-2 for BF16; measured 2.4e-4 and 1.7e-3)."""
+    import torch
+    from paper_2305_05025_amd.coupled import CoupledLB, params_from_workload
+    from workloads import make_workload
+    w = make_workload(2)
+    marks = (50, 500)
+
+    def run(fmt, v0=None):
+        say("full-size", fmt, marks, "(v0 + 1 ulp)" if v0 is not None else "")
+        if v0 is None:
+            sim = CoupledLB.from_workload(w, storage=fmt, device="cuda:0")
+        else:
+            sim = CoupledLB(params_from_workload(w, fmt), w.x0, v0, w.bonds, None, charges=w.charges)
+        outs, done = {}, 0
+        for m in marks:
+            sim.step(m - done)
+            done = m
+            _, u, _, v = sim.read_fields()
+            outs[m] = dict(u=u.double().cpu().numpy(), disp=sim.displacement().double().cpu().numpy(),
+                           v=v.double().cpu().numpy())
+        sim.close()
+        torch.cuda.empty_cache()
+        return outs
+
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    ref = run("f32")
+    runs = {"f32, v0 + 1 ulp": run("f32", v0=np.nextafter(w.v0.astype(np.float32), np.float32(np.inf)))}
+    for fmt in ("f16", "bf16"):
+        runs[fmt] = run(fmt)
+    rows = {m: {k: {q: rel(r[m][q], ref[m][q]) for q in ("u", "disp", "v")} for k, r in runs.items()}
+            for m in marks}
+    for m in marks:
+        say("256^3, 200,000 atoms, %d steps: rel. L2 against the GPU's FP32 run" % m)
+        for k, r in rows[m].items():
+            say("  %-16s" % k + "".join("  %s %.3e" % (q, r[q]) for q in ("u", "disp", "v")))
+    spread = rows[500]["f32, v0 + 1 ulp"]
+    for q in ("u", "disp", "v"):
+        assert rows[500]["f16"][q] < 1.3 * spread[q] and rows[500]["bf16"][q] < 2.0 * spread[q], rows
+    assert rows[50]["f16"]["u"] < 1e-3 and rows[50]["bf16"]["u"] < 1e-2, rows
