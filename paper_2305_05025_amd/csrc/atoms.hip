@@ -600,9 +600,15 @@ __global__ __launch_bounds__(256) void k_forces_cells(ForceArgs a) {
   const float eps24_u = a.lj_eps24 * (kAdj ? 1.0f : 16777216.0f);  // 2^24
   const float coul2_u = a.coul2 * (kAdj ? 1.0f : 4722366482869645213696.0f);   // 2^72
   const int nc0 = a.g.nc[0], nc1 = a.g.nc[1], nc2 = a.g.nc[2];
-  const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6, nwave = gridDim.x * 4;
+  // XCD x takes the x-th contiguous eighth of the occupied-cell list (the list runs in cell
+  // order, so neighbouring cells are near each other in it), interleaved over its own
+  // waves: the 27-cell neighbourhoods it stages then overlap in that XCD's L2.  The grid is
+  // a multiple of 8 workgroups.
   const int nocc = *a.occ_count;
-  for (int k = wave; k < nocc; k += nwave) {
+  const int chunk = (nocc + 7) >> 3;
+  const int k0 = (int)(blockIdx.x & 7u) * chunk, k1 = min(k0 + chunk, nocc);
+  const int lwave = (int)(blockIdx.x >> 3) * 4 + wid, nlwave = (int)(gridDim.x >> 3) * 4;
+  for (int k = k0 + lwave; k < k1; k += nlwave) {
     const int cell = a.occ_cells[k];
     int nh = a.cell_count[cell];
     nh = nh > kCellCap ? kCellCap : nh;
