@@ -206,6 +206,25 @@ def test_determinism_and_checkpoint(O):
     b.close()
 
 
+def test_call_chunking_is_bitwise_identical(O):
+    """30 steps in one lb_couple_step call and the same 30 in calls of 1, 1, 1, 7 and 20 steps
+    give identical bits (each call starts by binning its first step; within a call the next
+    binning overlaps the sweep)."""
+    from paper_2305_05025_amd.coupled import CoupledLB
+    w = _globule(n=1000, L=(32, 30, 28))
+    a = CoupledLB.from_workload(w)
+    b = CoupledLB.from_workload(w)
+    a.step(30)
+    for n in (1, 1, 1, 7, 20):
+        b.step(n)
+    assert a.step_count == b.step_count == 30
+    _, _, xa, va = a.read_fields()
+    _, _, xb, vb = b.read_fields()
+    assert (a.populations() == b.populations()).all() and (xa == xb).all() and (va == vb).all()
+    a.close()
+    b.close()
+
+
 def test_single_stream_schedule_is_bitwise_identical(O):
     """The overlapped three-stream schedule and the single-stream one give identical bits."""
     from paper_2305_05025_amd import _abi as A
