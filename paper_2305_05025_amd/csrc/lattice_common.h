@@ -275,9 +275,11 @@ __device__ __forceinline__ void site_normals(uint32_t seed0, uint32_t seed1, int
     for (int t = 0; t < 2; ++t) {
       const float ua = ((float)(w[2 * t] >> 8) + 0.5f) * (1.0f / 16777216.0f);
       const float ub = ((float)(w[2 * t + 1] >> 8) + 0.5f) * (1.0f / 16777216.0f);
-      const float r = sqrtf(-2.0f * logf(ua));
-      float sn, cs;
-      sincospif(2.0f * ub, &sn, &cs);
+      // the hardware's transcendental units: v_log_f32 gives log2 (ua >= 2^-25 is a normal
+      // number), v_sin_f32 / v_cos_f32 take the angle in turns, so 2 pi ub is ub itself
+      // (each within about 2 ulp of the exact value)
+      const float r = sqrtf(-2.0f * 0.693147180559945f * __builtin_amdgcn_logf(ua));
+      const float sn = __builtin_amdgcn_sinf(ub), cs = __builtin_amdgcn_cosf(ub);
       z[4 * q + 2 * t] = r * cs;
       z[4 * q + 2 * t + 1] = r * sn;
     }
