@@ -248,7 +248,7 @@ def run(args):
         "data": "synthetic",
         "config": {"workload": w.name, "lattice": list(w.L), "atoms": w.n_atoms,
                    "storage": args.storage, "tau": w.tau, "steps_per_call": args.steps,
-                   "streams": 1 if args.single_stream else 3},
+                   "streams": 1 if args.single_stream else 2},
         "hbm_gbs_step": round(step_gbs, 1),
         "hbm_frac_step": round(step_gbs / HBM_PEAK_GBS, 4),
         # summed durations of the atom-side kernel chains (binning, coupling, cell sort +

@@ -79,7 +79,7 @@ typedef enum {
 #define LB_FLAG_CHECK_FINITE 0x1u  /* lb_couple_step also checks for NaN/Inf every step */
 #define LB_FLAG_SINGLE_STREAM 0x2u /* queue every kernel on the caller's stream; by default the
                                       library runs the force field, the integration and the
-                                      next step's binning on two streams of its own, where
+                                      next step's binning on a stream of its own, where
                                       they overlap the lattice sweep.  Both give identical
                                       bits.  For lattices of about 32^3 sites and below the
                                       step is bound by the host's launch and event calls,

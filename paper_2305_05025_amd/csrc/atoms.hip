@@ -896,7 +896,7 @@ hipError_t launch_cell_sort(lb_ctx* c) {
   a.cell_count = (const int*)(c->ws + c->lay.cell_count);
   a.cell_rec = (int4*)(c->ws + c->lay.cell_rec);
   hipLaunchKernelGGL(k_cell_sort, dim3(persistent_grid(std::min(c->geo.ncell, (long)c->p.n_atoms))),
-                     dim3(256), 0, c->fstream, a);
+                     dim3(256), 0, c->astream, a);
   return hipGetLastError();
 }
 
@@ -1038,11 +1038,11 @@ hipError_t launch_forces(lb_ctx* c) {
   const ForceArgs a = force_args(c);
   const dim3 grid(std::min(persistent_grid(std::min(a.ncell, (long)a.N)), kForceGridCap));
   if (a.ncell > 0 && a.coul2 != 0.f)
-    hipLaunchKernelGGL((k_forces_cells<false, true>), grid, dim3(256), 0, c->fstream, a);
+    hipLaunchKernelGGL((k_forces_cells<false, true>), grid, dim3(256), 0, c->astream, a);
   else if (a.ncell > 0)
-    hipLaunchKernelGGL((k_forces_cells<false, false>), grid, dim3(256), 0, c->fstream, a);
+    hipLaunchKernelGGL((k_forces_cells<false, false>), grid, dim3(256), 0, c->astream, a);
   else
-    hipLaunchKernelGGL(k_bonded_forces<false>, dim3(blocks(a.N, 256)), dim3(256), 0, c->fstream, a);
+    hipLaunchKernelGGL(k_bonded_forces<false>, dim3(blocks(a.N, 256)), dim3(256), 0, c->astream, a);
   return hipGetLastError();
 }
 

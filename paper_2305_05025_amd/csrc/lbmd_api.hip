@@ -335,16 +335,14 @@ lb_status lb_init(const lb_params* p, void* workspace, size_t workspace_bytes, c
     delete c;
     return hip_fail(nullptr, e, "synchronising after set-up");
   }
-  c->astream = c->fstream = st;
+  c->astream = st;
   if (N > 0 && !(p->flags & LB_FLAG_SINGLE_STREAM)) {
-    // atom work that overlaps the sweep runs on two more streams (default priority).  The
+    // atom work that overlaps the sweep runs on one more stream (default priority).  The
     // events inside a step are waited on only by this device's kernels, so they release at
     // device scope (no system-scope fence; about 4 us less per step); the fork and join with
     // the caller's stream keep the default.
     const unsigned dev_ev = hipEventDisableTiming | hipEventDisableSystemFence;
     if ((e = hipStreamCreateWithFlags(&c->astream, hipStreamNonBlocking)) != hipSuccess ||
-        (e = hipStreamCreateWithFlags(&c->fstream, hipStreamNonBlocking)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&c->ev_forces, dev_ev)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&c->ev_bin, dev_ev)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&c->ev_spread, dev_ev)) != hipSuccess ||
@@ -363,17 +361,15 @@ lb_status lb_couple_step(lb_ctx* c, int32_t n_steps) {
   if (n_steps == 0) return LB_OK;
   const bool atoms = c->p.n_atoms > 0;
   hipError_t e;
-  // Three streams (the caller's "main" stream, "atoms" and "forces").  Step n:
+  // Two streams (the caller's "main" stream and "atoms").  Step n:
   //   main:   wait ev_bin(n); node u_c, couple, spread -> ev_spread; sweep
-  //   forces: wait ev_bin(n); cell sort, force field at X^n -> ev_forces
-  //   atoms:  wait ev_spread, ev_forces; integration; then, for step n + 1:
-  //           prep, bin/mark, compaction -> ev_bin(n + 1)
+  //   atoms:  (after the binning of step n) cell sort, force field at X^n; wait ev_spread;
+  //           integration; then, for step n + 1: prep, bin/mark, compaction -> ev_bin(n + 1)
   // The coupling and the sweep run back to back on one stream; the force field (which
   // needs only X^n) overlaps both, and the integration and the next step's binning overlap
-  // the sweep.  The atom stream first waits for
-  // everything already queued on the caller's stream, and the caller's stream finally waits
-  // for the atom stream (which has waited for the force stream), so the call behaves as if
-  // it had been queued on the caller's stream alone.  With LB_FLAG_SINGLE_STREAM every
+  // the sweep.  The atom stream first waits for everything already queued on the caller's
+  // stream, and the caller's stream finally waits for the atom stream, so the call behaves
+  // as if it had been queued on the caller's stream alone.  With LB_FLAG_SINGLE_STREAM every
   // launch goes to the caller's stream in the same order.
   const bool multi = atoms && c->astream != c->stream;
   auto rec = [&](hipEvent_t* ev, int k, hipStream_t st) {
@@ -405,14 +401,14 @@ lb_status lb_couple_step(lb_ctx* c, int32_t n_steps) {
     void* fout = c->popbuf[c->cur ^ 1];
     if (atoms) {
       if ((n == 0 || !multi) && (st = binning(ev)) != LB_OK) return st;
-      if (multi && ((e = hipStreamWaitEvent(c->stream, c->ev_bin, 0)) != hipSuccess ||
-                    (e = hipStreamWaitEvent(c->fstream, c->ev_bin, 0)) != hipSuccess))
+      // the force field follows the binning on the atom stream, which otherwise waits there
+      // for the spread: it needs only X^n
+      if (multi && (e = hipStreamWaitEvent(c->stream, c->ev_bin, 0)) != hipSuccess)
         return hip_fail(c, e, "binning wait");
       if (c->geo.ncell > 0 && (e = launch_cell_sort(c)) != hipSuccess) return hip_fail(c, e, "cell sort launch");
-      rec(ev, 6, c->fstream);
+      rec(ev, 6, c->astream);
       if ((e = launch_forces(c)) != hipSuccess) return hip_fail(c, e, "force launch");
-      rec(ev, 7, c->fstream);
-      if (multi && (e = hipEventRecord(c->ev_forces, c->fstream)) != hipSuccess) return hip_fail(c, e, "force event");
+      rec(ev, 7, c->astream);
       rec(ev, 0, c->stream);
       if ((e = launch_node_u(c)) != hipSuccess) return hip_fail(c, e, "node velocity launch");
       if ((e = launch_couple(c)) != hipSuccess) return hip_fail(c, e, "coupling launch");
@@ -424,9 +420,8 @@ lb_status lb_couple_step(lb_ctx* c, int32_t n_steps) {
     if ((e = launch_sweep(c, fin, fout, c->stream)) != hipSuccess) return hip_fail(c, e, "sweep launch");
     rec(ev, 3, c->stream);
     if (atoms) {
-      if (multi && ((e = hipStreamWaitEvent(c->astream, c->ev_spread, 0)) != hipSuccess ||
-                    (e = hipStreamWaitEvent(c->astream, c->ev_forces, 0)) != hipSuccess))
-        return hip_fail(c, e, "spread/force wait");
+      if (multi && (e = hipStreamWaitEvent(c->astream, c->ev_spread, 0)) != hipSuccess)
+        return hip_fail(c, e, "spread wait");
       if ((e = launch_integrate(c)) != hipSuccess) return hip_fail(c, e, "integration launch");
     }
     c->cur ^= 1;
@@ -696,12 +691,12 @@ lb_status lb_backward(lb_ctx* c, const void* ckpts, int32_t n_steps, int32_t k, 
   const size_t N3 = 3 * (size_t)c->p.n_atoms;
   const size_t aoff = state_atom_offset(c), abytes = round_up(12 * (size_t)c->p.n_atoms, 256);
   auto slot = [&](int q) { return A + L.slots + (size_t)q * sb; };
-  const hipStream_t as = c->astream, fs = c->fstream;
+  const hipStream_t as = c->astream;
   char* pb0 = c->popbuf[0];
   char* pb1 = c->popbuf[1];
   lb_status st = LB_OK;
   // every kernel of the backward pass runs in order on the caller's stream
-  c->astream = c->fstream = c->stream;
+  c->astream = c->stream;
   if ((st = lb_state_save(c, A + L.final_state)) != LB_OK) goto restore;
   if ((e = launch_zero(A + L.lam[0], (size_t)c->geo.q * c->geo.plane * 4, c->stream)) != hipSuccess ||
       (e = launch_zero(A + L.acc, 24, c->stream)) != hipSuccess ||
@@ -812,7 +807,6 @@ restore:
   {
     const lb_status s2 = lb_state_load(c, A + L.final_state);
     c->astream = as;
-    c->fstream = fs;
     if (st == LB_OK) st = s2;
   }
   if (st == LB_OK) st = lb_status_check(c);
@@ -822,12 +816,12 @@ restore:
 lb_status lb_destroy(lb_ctx* c) {
   if (!c) return fail(nullptr, LB_EINVAL, "context is NULL");
   free_events(c);
-  for (hipStream_t s : {c->fstream, c->astream})
+  for (hipStream_t s : {c->astream})
     if (s && s != c->stream) {
       (void)hipStreamSynchronize(s);
       (void)hipStreamDestroy(s);
     }
-  for (hipEvent_t e : {c->ev_fork, c->ev_bin, c->ev_spread, c->ev_join, c->ev_forces})
+  for (hipEvent_t e : {c->ev_fork, c->ev_bin, c->ev_spread, c->ev_join})
     if (e) (void)hipEventDestroy(e);
   delete c;
   return LB_OK;

@@ -143,9 +143,7 @@ struct lb_ctx {
   std::string err;
   // second stream for the atom work that overlaps the sweep, and its fork/join events
   hipStream_t astream = nullptr;  // atom stream (the caller's stream when single-stream)
-  hipStream_t fstream = nullptr;  // force-field stream (likewise)
-  hipEvent_t ev_fork = nullptr, ev_bin = nullptr, ev_spread = nullptr;
-  hipEvent_t ev_forces = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_bin = nullptr, ev_spread = nullptr, ev_join = nullptr;
   // optional per-phase event timing (lb_timing_begin / lb_timing_end)
   std::vector<hipEvent_t> ev;  // kTimedEvents per timed step
   int timed_cap = 0;

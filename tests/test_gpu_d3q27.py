@@ -99,7 +99,7 @@ def test_globule_short_horizon(O, magic):
 
 
 def test_one_step_full_size_sampled(O):
-    """256^3 with 200,000 atoms in ten globules, three streams: one step from a seeded random
+    """256^3 with 200,000 atoms in ten globules, two streams: one step from a seeded random
     lattice state, compared on sampled sites (half of them on atom stencils) and atoms."""
     import torch
     from paper_2305_05025_amd.coupled import CoupledLB

@@ -226,7 +226,7 @@ def test_call_chunking_is_bitwise_identical(O):
 
 
 def test_single_stream_schedule_is_bitwise_identical(O):
-    """The overlapped three-stream schedule and the single-stream one give identical bits."""
+    """The overlapped two-stream schedule and the single-stream one give identical bits."""
     from paper_2305_05025_amd import _abi as A
     from paper_2305_05025_amd.coupled import CoupledLB
     w = _globule(n=1200, L=(36, 32, 40))
