@@ -41,17 +41,10 @@ struct Store<LB_STORE_BF16> {
   static __device__ __forceinline__ float ld(const P* p) {
     return __uint_as_float((uint32_t)(*p) << 16);
   }
+  // conversion by the hardware (v_cvt_pk_bf16_f32): round to nearest even, NaN stays NaN
   template <class P>
   static __device__ __forceinline__ void st(P* p, float v) {
-    uint32_t u = __float_as_uint(v);
-    uint16_t h;
-    if ((u & 0x7fffffffu) > 0x7f800000u) {
-      h = (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
-    } else {
-      u += 0x7fffu + ((u >> 16) & 1u);    // round to nearest, ties to even
-      h = (uint16_t)(u >> 16);
-    }
-    __builtin_nontemporal_store(h, p);
+    __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, (__bf16)v), p);
   }
 };
 
