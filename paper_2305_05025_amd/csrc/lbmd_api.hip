@@ -30,6 +30,10 @@ bool geometry(const lb_params* p, Geometry* g) {
   g->div_nx = make_fastdiv((uint32_t)g->nx);
   g->div_ny = make_fastdiv((uint32_t)g->ny);
   g->narrow = (uint64_t)g->S * g->elem <= (1ull << 32) && std::getenv("LBMD_WIDE_OFFSETS") == nullptr;
+  // the sweep's population bytes per step (every value read and written once) per atom
+  const double sweep_bytes = (double)g->S * 2.0 * g->q * (double)g->elem;
+  g->late_forces = std::getenv("LBMD_LATE_FORCES") != nullptr ||
+                   (g->S >= (1L << 23) && sweep_bytes >= 7168.0 * (double)p->n_atoms);
   g->ncell = 0;
   for (int k = 0; k < 3; ++k) {
     g->nc[k] = 0;
@@ -346,6 +350,7 @@ lb_status lb_init(const lb_params* p, void* workspace, size_t workspace_bytes, c
         (e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&c->ev_bin, dev_ev)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&c->ev_spread, dev_ev)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&c->ev_couple, dev_ev)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming)) != hipSuccess) {
       lb_destroy(c);
       return hip_fail(nullptr, e, "creating the atom stream");
@@ -362,16 +367,24 @@ lb_status lb_couple_step(lb_ctx* c, int32_t n_steps) {
   const bool atoms = c->p.n_atoms > 0;
   hipError_t e;
   // Two streams (the caller's "main" stream and "atoms").  Step n:
-  //   main:   wait ev_bin(n); node u_c, couple, spread -> ev_spread; sweep
-  //   atoms:  (after the binning of step n) cell sort, force field at X^n; wait ev_spread;
-  //           integration; then, for step n + 1: prep, bin/mark, compaction -> ev_bin(n + 1)
+  //   main:   wait ev_bin(n); node u_c, couple (-> ev_couple); spread -> ev_spread; sweep
+  //   atoms:  (after the binning of step n) cell sort, (wait ev_couple,) force field at X^n;
+  //           wait ev_spread; integration; then, for step n + 1: prep, bin/mark, compaction
+  //           -> ev_bin(n + 1)
   // The coupling and the sweep run back to back on one stream; the force field (which
-  // needs only X^n) overlaps both, and the integration and the next step's binning overlap
+  // needs only X^n) overlaps them, and the integration and the next step's binning overlap
   // the sweep.  The atom stream first waits for everything already queued on the caller's
   // stream, and the caller's stream finally waits for the atom stream, so the call behaves
   // as if it had been queued on the caller's stream alone.  With LB_FLAG_SINGLE_STREAM every
   // launch goes to the caller's stream in the same order.
   const bool multi = atoms && c->astream != c->stream;
+  // With a long sweep the force field waits for the coupling kernels (ev_couple), so that u_c
+  // and the interpolation run without it beside them; it still takes its workgroup slots
+  // before the sweep is launched.  Otherwise it starts right after the cell sort: on small
+  // lattices the step is bound by the host's enqueue time and the extra event costs more than
+  // it saves, and with a short sweep (16-bit storage) the atom loop is the longer cycle and
+  // must not start later.  Both orders give identical bits.
+  const bool late_forces = multi && c->geo.late_forces;
   auto rec = [&](hipEvent_t* ev, int k, hipStream_t st) {
     if (ev) (void)hipEventRecord(ev[k], st);
   };
@@ -401,17 +414,28 @@ lb_status lb_couple_step(lb_ctx* c, int32_t n_steps) {
     void* fout = c->popbuf[c->cur ^ 1];
     if (atoms) {
       if ((n == 0 || !multi) && (st = binning(ev)) != LB_OK) return st;
-      // the force field follows the binning on the atom stream, which otherwise waits there
-      // for the spread: it needs only X^n
       if (multi && (e = hipStreamWaitEvent(c->stream, c->ev_bin, 0)) != hipSuccess)
         return hip_fail(c, e, "binning wait");
+      // the cell sort and the force field (which needs only X^n) follow the binning on the
+      // atom stream; see late_forces for where the force field starts.  (An event's record is
+      // queued before the wait that refers to it.)
       if (c->geo.ncell > 0 && (e = launch_cell_sort(c)) != hipSuccess) return hip_fail(c, e, "cell sort launch");
-      rec(ev, 6, c->astream);
-      if ((e = launch_forces(c)) != hipSuccess) return hip_fail(c, e, "force launch");
-      rec(ev, 7, c->astream);
+      auto forces = [&]() -> lb_status {
+        rec(ev, 6, c->astream);
+        if ((e = launch_forces(c)) != hipSuccess) return hip_fail(c, e, "force launch");
+        rec(ev, 7, c->astream);
+        return LB_OK;
+      };
+      if (!late_forces && (st = forces()) != LB_OK) return st;
       rec(ev, 0, c->stream);
       if ((e = launch_node_u(c)) != hipSuccess) return hip_fail(c, e, "node velocity launch");
       if ((e = launch_couple(c)) != hipSuccess) return hip_fail(c, e, "coupling launch");
+      if (late_forces) {
+        if ((e = hipEventRecord(c->ev_couple, c->stream)) != hipSuccess ||
+            (e = hipStreamWaitEvent(c->astream, c->ev_couple, 0)) != hipSuccess)
+          return hip_fail(c, e, "coupling event");
+        if ((st = forces()) != LB_OK) return st;
+      }
       if ((e = launch_spread(c)) != hipSuccess) return hip_fail(c, e, "spread launch");
       rec(ev, 1, c->stream);
       if (multi && (e = hipEventRecord(c->ev_spread, c->stream)) != hipSuccess) return hip_fail(c, e, "spread event");
@@ -821,7 +845,7 @@ lb_status lb_destroy(lb_ctx* c) {
       (void)hipStreamSynchronize(s);
       (void)hipStreamDestroy(s);
     }
-  for (hipEvent_t e : {c->ev_fork, c->ev_bin, c->ev_spread, c->ev_join})
+  for (hipEvent_t e : {c->ev_fork, c->ev_bin, c->ev_couple, c->ev_spread, c->ev_join})
     if (e) (void)hipEventDestroy(e);
   delete c;
   return LB_OK;

@@ -120,6 +120,13 @@ struct Geometry {
   // variable LBMD_WIDE_OFFSETS (any value) at context creation keeps the 64-bit addressing
   // that larger lattices take, so both forms can be compared on small ones.
   bool narrow;
+  // In the two-stream step, the force field waits for the coupling kernels when the sweep is
+  // long: at least 2^23 sites, and at least 7 KiB of population traffic per step and atom
+  // (FP32 D3Q19 at 256^3 with 200k atoms moves 12.5 KiB, at 384^3 with 1M atoms 8.4 KiB; FP16
+  // at 256^3 with 200k atoms 6.2 KiB).  Otherwise it starts right after the cell sort.  The
+  // environment variable LBMD_LATE_FORCES (any value) at context creation takes the late start
+  // on any lattice, so both orders can be compared on small ones.
+  bool late_forces;
 };
 
 bool geometry(const lb_params* p, Geometry* g);
@@ -143,7 +150,7 @@ struct lb_ctx {
   std::string err;
   // second stream for the atom work that overlaps the sweep, and its fork/join events
   hipStream_t astream = nullptr;  // atom stream (the caller's stream when single-stream)
-  hipEvent_t ev_fork = nullptr, ev_bin = nullptr, ev_spread = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_bin = nullptr, ev_couple = nullptr, ev_spread = nullptr, ev_join = nullptr;
   // optional per-phase event timing (lb_timing_begin / lb_timing_end)
   std::vector<hipEvent_t> ev;  // kTimedEvents per timed step
   int timed_cap = 0;

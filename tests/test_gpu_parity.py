@@ -226,13 +226,20 @@ def test_call_chunking_is_bitwise_identical(O):
 
 
 def test_single_stream_schedule_is_bitwise_identical(O):
-    """The overlapped two-stream schedule and the single-stream one give identical bits."""
+    """The overlapped two-stream schedule, with the force field started early or after the
+    coupling kernels (LBMD_LATE_FORCES), and the single-stream one give identical bits."""
+    import os
     from paper_2305_05025_amd import _abi as A
     from paper_2305_05025_amd.coupled import CoupledLB
     w = _globule(n=1200, L=(36, 32, 40))
     outs = []
-    for flags in (0, A.LB_FLAG_SINGLE_STREAM):
-        sim = CoupledLB.from_workload(w, flags=flags)
+    for flags, late in ((0, False), (0, True), (A.LB_FLAG_SINGLE_STREAM, False)):
+        if late:
+            os.environ["LBMD_LATE_FORCES"] = "1"
+        try:
+            sim = CoupledLB.from_workload(w, flags=flags)
+        finally:
+            os.environ.pop("LBMD_LATE_FORCES", None)
         sim.step(12)
         g = sim.populations()
         _, _, x, v = sim.read_fields()
