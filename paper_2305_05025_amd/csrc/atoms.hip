@@ -1029,14 +1029,21 @@ static ForceArgs force_args(lb_ctx* c) {
   return a;
 }
 
-// The force field runs beside the coupling kernels and the sweep: at most 512 workgroups (2
-// wavefronts per SIMD) leave those kernels room.  Measured per step: the same as 768 or 1024
-// at 256^3 with 200k atoms, 2.5% faster than 1024 at 384^3 with 1M atoms.
-constexpr unsigned kForceGridCap = 512;
+// Workgroups of the force field.  Started after the coupling kernels, it runs beside the spread
+// and the sweep, and 512 (2 wavefronts per SIMD) leave the sweep room: per step at 256^3 with
+// 200k atoms 0.557 ms against 0.566 (768), 0.599 (1024) and 0.635 (256); at 384^3 with 1M atoms
+// 2.085 ms against 2.125, 2.259 and 2.492.  Started right after the cell sort beside a short
+// 16-bit sweep, it is on the longer cycle, and 768 gain about 1% (FP16 at 256^3: 0.361 against
+// 0.365 ms; at 384^3: 1.428 against 1.447).  Alone on one stream it takes the whole persistent
+// grid (2048 at most).
+static unsigned force_grid_cap(const lb_ctx* c) {
+  if (c->astream == c->stream) return 2048u;
+  return c->geo.late_forces ? 512u : 768u;
+}
 
 hipError_t launch_forces(lb_ctx* c) {
   const ForceArgs a = force_args(c);
-  const dim3 grid(std::min(persistent_grid(std::min(a.ncell, (long)a.N)), kForceGridCap));
+  const dim3 grid(std::min(persistent_grid(std::min(a.ncell, (long)a.N)), force_grid_cap(c)));
   if (a.ncell > 0 && a.coul2 != 0.f)
     hipLaunchKernelGGL((k_forces_cells<false, true>), grid, dim3(256), 0, c->astream, a);
   else if (a.ncell > 0)
