@@ -227,11 +227,13 @@ def test_call_chunking_is_bitwise_identical(O):
 
 def test_single_stream_schedule_is_bitwise_identical(O):
     """The overlapped two-stream schedule, with the force field started early or after the
-    coupling kernels (LBMD_LATE_FORCES), and the single-stream one give identical bits."""
+    coupling kernels (LBMD_LATE_FORCES), and the single-stream one give identical bits.  With
+    4000 atoms (and more neighbour cells than that) the three launch the force field on
+    different grids (768, 512 and 1000 workgroups)."""
     import os
     from paper_2305_05025_amd import _abi as A
     from paper_2305_05025_amd.coupled import CoupledLB
-    w = _globule(n=1200, L=(36, 32, 40))
+    w = _globule(n=4000, L=(48, 44, 40))
     outs = []
     for flags, late in ((0, False), (0, True), (A.LB_FLAG_SINGLE_STREAM, False)):
         if late:
