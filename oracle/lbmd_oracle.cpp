@@ -55,6 +55,7 @@
 #include <cstring>
 #include <vector>
 #include <algorithm>
+#include <array>
 
 namespace {
 
@@ -126,6 +127,7 @@ struct Model {
   int Q = 19;                                // velocity set: 19 or 27
   int L[3];
   long S;
+  long P;                                    // plane stride of the population arrays held here
   T tau, rho0, gamma, mass, k_tether, k_bond, r0_bond, lj_eps, lj_sigma, lj_rc;
   T coul_k;                                  // implicit-solvent Coulomb prefactor (0: off)
   T trt_magic;                               // two-relaxation-time magic parameter (0: BGK)
@@ -143,12 +145,39 @@ struct Model {
 template <class T>
 struct State {
   int64_t step = 0;   // step index (counts the noise)
-  std::vector<T> g;   // pre-collision populations, deviation form, [Q][S]
+  std::vector<T> g;   // pre-collision populations, deviation form, [Q][P] (sites 0..S-1 used)
   std::vector<T> X;   // unwrapped positions [N][3]
   std::vector<T> V;   // velocities [N][3]
 };
 
 inline long site_index(const int L[3], long x, long y, long z) { return x + L[0] * (y + (long)L[1] * z); }
+
+// Population arrays held by the oracle keep their Q planes a few cache lines more than S
+// apart: with a power-of-two S every site's Q values would otherwise share one cache set
+// and the site loops run an order of magnitude slower.  Storage only; the values are those
+// of the caller's [Q][S] arrays.
+inline long plane_stride(long S) { return S + 8; }
+
+template <class T>
+void set_geometry(int Q, const int32_t* L, Model<T>& m) {
+  m.Q = Q;
+  for (int a = 0; a < 3; ++a) m.L[a] = L[a];
+  m.S = (long)L[0] * L[1] * L[2];
+  m.P = plane_stride(m.S);
+}
+
+// caller [Q][S] <-> oracle [Q][P]
+template <class T>
+void load_pops(const Model<T>& m, const double* g, std::vector<T>& out) {
+  out.assign((size_t)m.Q * m.P, T(0.0));
+  for (int i = 0; i < m.Q; ++i)
+    for (long x = 0; x < m.S; ++x) out[i * m.P + x] = T(g[i * m.S + x]);
+}
+template <class T>
+void store_pops(const Model<T>& m, const std::vector<T>& in, double* g) {
+  for (int i = 0; i < m.Q; ++i)
+    for (long x = 0; x < m.S; ++x) g[i * m.S + x] = val(in[i * m.P + x]);
+}
 
 inline long wrap(long a, int n) {
   long r = a % n;
@@ -161,7 +190,7 @@ void moments_at(const Model<T>& m, const std::vector<T>& g, long s, T& drho, T j
   drho = T(0.0);
   j[0] = j[1] = j[2] = T(0.0);
   for (int i = 0; i < m.Q; ++i) {
-    T gi = g[i * m.S + s];
+    T gi = g[i * m.P + s];
     drho += gi;
     j[0] += T((double)CV[i][0]) * gi;
     j[1] += T((double)CV[i][1]) * gi;
@@ -241,13 +270,14 @@ template <class T>
 void stream(const Model<T>& m, const std::vector<T>& post, std::vector<T>& pre) {
   const int* L = m.L;
   for (int i = 0; i < m.Q; ++i)
+#pragma omp parallel for schedule(static)
     for (long z = 0; z < L[2]; ++z)
       for (long y = 0; y < L[1]; ++y)
         for (long x = 0; x < L[0]; ++x) {
           long src = site_index(L, x, y, z);
           long dst = site_index(L, wrap(x + CV[i][0], L[0]), wrap(y + CV[i][1], L[1]),
                                 wrap(z + CV[i][2], L[2]));
-          pre[i * m.S + dst] = post[i * m.S + src];
+          pre[i * m.P + dst] = post[i * m.P + src];
         }
 }
 
@@ -378,14 +408,17 @@ double mode_poly(int k, const int c[3]) {
   }
 }
 
+// (the tables below are built once, on first use, by thread-safe static initialisation)
 double mode_norm(int k) {
-  static double b[19] = {-1.0};
-  if (b[0] < 0.0)
+  static const std::array<double, 19> b = [] {
+    std::array<double, 19> t{};
     for (int q = 0; q < 19; ++q) {
       double acc = 0.0;
       for (int i = 0; i < 19; ++i) acc += WV(i) * mode_poly(q, CV[i]) * mode_poly(q, CV[i]);
-      b[q] = acc;
+      t[q] = acc;
     }
+    return t;
+  }();
   return b[k];
 }
 
@@ -396,23 +429,22 @@ double mode_norm(int k) {
 // (0,1,0), (0,0,1); then the other 23 triples by increasing a + 3 b + 9 c.  A mode is odd
 // under c -> -c when an odd number of its factors are P_1.
 void mode27_triple(int k, int abc[3]) {
-  static int tab[27][3];
-  static bool ready = false;
-  if (!ready) {
+  static const std::array<std::array<int, 3>, 27> tab = [] {
+    std::array<std::array<int, 3>, 27> t{};
     const int first[4][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
     for (int q = 0; q < 4; ++q)
-      for (int d = 0; d < 3; ++d) tab[q][d] = first[q][d];
+      for (int d = 0; d < 3; ++d) t[q][d] = first[q][d];
     int n = 4;
     for (int code = 0; code < 27; ++code) {
       const int a = code % 3, b = (code / 3) % 3, c = code / 9;
       if (a + b + c <= 1) continue;   // the four conserved modes above
-      tab[n][0] = a;
-      tab[n][1] = b;
-      tab[n][2] = c;
+      t[n][0] = a;
+      t[n][1] = b;
+      t[n][2] = c;
       ++n;
     }
-    ready = true;
-  }
+    return t;
+  }();
   for (int d = 0; d < 3; ++d) abc[d] = tab[k][d];
 }
 
@@ -431,13 +463,15 @@ bool mode27_odd(int k) {
 }
 
 double mode27_norm(int k) {
-  static double b[27] = {-1.0};
-  if (b[0] < 0.0)
+  static const std::array<double, 27> b = [] {
+    std::array<double, 27> t{};
     for (int q = 0; q < 27; ++q) {
       double acc = 0.0;
       for (int i = 0; i < 27; ++i) acc += WV27[i] * mode27_poly(q, CV[i]) * mode27_poly(q, CV[i]);
-      b[q] = acc;
+      t[q] = acc;
     }
+    return t;
+  }();
   return b[k];
 }
 
@@ -552,9 +586,15 @@ void atom_forces(const Model<T>& m, const std::vector<T>& X, std::vector<T>& F) 
   }
 }
 
-// The same force field evaluated for one atom i only (all partners scanned).
+// The same force field evaluated for one atom i only.  The pair partners are scanned in
+// ascending index: all atoms, or (cand != NULL) the candidate list of i from pair_candidates,
+// which holds every atom closer than r_c in ascending order, so the sum has the same terms in
+// the same order.  Each partner's contribution is added to atom i's force in the order that
+// the pairwise loop of atom_forces adds it (tether, bonds in list order, pairs by ascending
+// partner), with the pair vector negated exactly, so the two give the same bits.
 template <class T>
-void atom_force_one(const Model<T>& m, const std::vector<T>& X, int i, T F[3]) {
+void atom_force_one(const Model<T>& m, const std::vector<T>& X, int i, T F[3],
+                    const std::vector<int>* cand = nullptr) {
   F[0] = F[1] = F[2] = T(0.0);
   for (int c = 0; c < 3; ++c) F[c] -= m.k_tether * (X[3 * i + c] - m.anchor[3 * i + c]);
   for (int b = 0; b < m.n_bonds; ++b) {
@@ -568,7 +608,8 @@ void atom_force_one(const Model<T>& m, const std::vector<T>& X, int i, T F[3]) {
     for (int c = 0; c < 3; ++c) F[c] += fmag * r[c];
   }
   if (pair_terms_on(m))
-    for (int j = 0; j < m.n_atoms; ++j) {
+    for (int k = 0, n = cand ? (int)cand->size() : m.n_atoms; k < n; ++k) {
+      const int j = cand ? (*cand)[k] : k;
       if (j == i) continue;
       T r[3];
       for (int c = 0; c < 3; ++c) r[c] = min_image(X[3 * i + c] - X[3 * j + c], m.L[c]);
@@ -578,6 +619,78 @@ void atom_force_one(const Model<T>& m, const std::vector<T>& X, int i, T F[3]) {
       T fmag = pair_force_over_r(m, i, j, r2);
       for (int c = 0; c < 3; ++c) F[c] += fmag * r[c];
     }
+}
+
+// Pair candidates.  The pair terms act only below the cut-off r_c (minimum image).  Put the
+// atoms into a periodic grid of cells at least 1.001 r_c wide (3 or more along every axis):
+// any two atoms closer than r_c then sit in the same or in neighbouring cells (the margin
+// exceeds the rounding of the cell index), so the atoms of the 3 x 3 x 3 cells around an
+// atom's own, in ascending index, hold all of its partners in the order a scan of every atom
+// meets them.  Returns false (scan every atom) when an axis has fewer than 3 cells, where
+// neighbouring cells would repeat.
+struct CellGrid {
+  int nc[3] = {0, 0, 0};
+  std::vector<std::vector<int>> atoms;   // per cell, ascending atom index
+  std::vector<int> cell_of;              // per atom
+};
+
+template <class T>
+bool build_cells(const Model<T>& m, const std::vector<T>& X, CellGrid& g) {
+  const double rc = val(m.lj_rc);
+  for (int a = 0; a < 3; ++a) {
+    g.nc[a] = (int)std::floor((double)m.L[a] / (rc * 1.001));
+    if (g.nc[a] < 3) return false;
+  }
+  g.atoms.assign((size_t)g.nc[0] * g.nc[1] * g.nc[2], {});
+  g.cell_of.resize(m.n_atoms);
+  for (int i = 0; i < m.n_atoms; ++i) {
+    int q[3];
+    for (int a = 0; a < 3; ++a) {
+      const double x = val(X[3 * i + a]);
+      const double y = x - m.L[a] * std::floor(x / m.L[a]);   // into [0, L)
+      const int k = (int)std::floor(y * g.nc[a] / m.L[a]);
+      q[a] = k < 0 ? 0 : (k >= g.nc[a] ? g.nc[a] - 1 : k);
+    }
+    const int c = q[0] + g.nc[0] * (q[1] + g.nc[1] * q[2]);
+    g.atoms[c].push_back(i);   // i ascends, so each cell's list is sorted
+    g.cell_of[i] = c;
+  }
+  return true;
+}
+
+// the atoms of the 27 cells around atom i's cell, ascending
+inline void pair_candidates(const CellGrid& g, int i, std::vector<int>& out) {
+  out.clear();
+  const int c = g.cell_of[i];
+  const int q[3] = {c % g.nc[0], (c / g.nc[0]) % g.nc[1], c / (g.nc[0] * g.nc[1])};
+  for (int dz = -1; dz <= 1; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int x = (q[0] + dx + g.nc[0]) % g.nc[0], y = (q[1] + dy + g.nc[1]) % g.nc[1],
+                  z = (q[2] + dz + g.nc[2]) % g.nc[2];
+        const std::vector<int>& v = g.atoms[x + g.nc[0] * (y + g.nc[1] * z)];
+        out.insert(out.end(), v.begin(), v.end());
+      }
+  std::sort(out.begin(), out.end());
+}
+
+// The force field at X evaluated atom by atom (atom_force_one, in parallel over atoms): the
+// same values, bit for bit, as the pairwise loop of atom_forces.
+template <class T>
+void atom_forces_by_atom(const Model<T>& m, const std::vector<T>& X, std::vector<T>& F) {
+  CellGrid g;
+  const bool cells = pair_terms_on(m) && build_cells(m, X, g);
+#pragma omp parallel
+  {
+    std::vector<int> cand;
+#pragma omp for schedule(dynamic, 64)
+    for (int i = 0; i < m.n_atoms; ++i) {
+      if (cells) pair_candidates(g, i, cand);
+      T f[3];
+      atom_force_one(m, X, i, f, cells ? &cand : nullptr);
+      for (int c = 0; c < 3; ++c) F[3 * i + c] = f[c];
+    }
+  }
 }
 
 template <class T>
@@ -619,37 +732,59 @@ T atom_energy(const Model<T>& m, const std::vector<T>& X) {
 //  7 streaming
 //  8 stand-in force field at X^n
 //  9 symplectic Euler: v^{n+1} = v^n + (F_ff + F_c)/m, X^{n+1} = X^n + v^{n+1}
-// Steps 1-5: friction force on every atom (Fc) and total force density on every node (Ftot).
+// Arrays of a step, kept from step to step (allocating lattice-sized arrays anew every step
+// costs more than the step's arithmetic on some hosts).
 template <class T>
-void coupling_forces(const Model<T>& m, const State<T>& s, std::vector<T>& Fc, std::vector<T>& Ftot) {
+struct Work {
+  std::vector<T> post;      // post-collision populations [Q][P]
+  std::vector<T> uc;        // coupling velocity [3][S]
+  std::vector<T> Fspread;   // spread friction force [3][S]
+  std::vector<T> Ftot;      // total force density [3][S]
+  std::vector<T> U, Fc, Fff;  // per atom [N][3]: interpolated velocity, friction, force field
+  void size(const Model<T>& m) {
+    post.resize((size_t)m.Q * m.P);
+    uc.resize(3 * (size_t)m.S);
+    Fspread.resize(3 * (size_t)m.S);
+    Ftot.resize(3 * (size_t)m.S);
+    U.resize(3 * (size_t)m.n_atoms);
+    Fc.resize(3 * (size_t)m.n_atoms);
+    Fff.resize(3 * (size_t)m.n_atoms);
+  }
+};
+
+// Steps 1-5: friction force on every atom (w.Fc) and total force density on every node
+// (w.Ftot).
+template <class T>
+void coupling_forces(const Model<T>& m, const State<T>& s, Work<T>& w) {
   const long S = m.S;
   const int N = m.n_atoms;
-  std::vector<T> uc(3 * S);
+  std::vector<T>& uc = w.uc;
+#pragma omp parallel for schedule(static)
   for (long x = 0; x < S; ++x) {
     T dr, j[3];
     moments_at(m, s.g, x, dr, j);
     T rho = m.rho0 + dr;
     for (int c = 0; c < 3; ++c) uc[c * S + x] = (j[c] + T(0.5) * m.fext[c * S + x]) / rho;
   }
-  std::vector<T> U(3 * N);
-  Fc.assign(3 * N, T(0.0));
-  interpolate(m.L, S, uc, N, s.X.data(), U.data());
-  for (int k = 0; k < 3 * N; ++k) Fc[k] = m.gamma * (U[k] - s.V[k]);
-  Ftot = m.fext;
-  std::vector<T> Fspread(3 * S, T(0.0));
-  spread(m.L, S, N, s.X.data(), Fc.data(), Fspread);
-  for (long k = 0; k < 3 * S; ++k) Ftot[k] -= Fspread[k];
+  interpolate(m.L, S, uc, N, s.X.data(), w.U.data());
+  for (int k = 0; k < 3 * N; ++k) w.Fc[k] = m.gamma * (w.U[k] - s.V[k]);
+  std::fill(w.Fspread.begin(), w.Fspread.end(), T(0.0));
+  spread(m.L, S, N, s.X.data(), w.Fc.data(), w.Fspread);
+#pragma omp parallel for schedule(static)
+  for (long k = 0; k < 3 * S; ++k) w.Ftot[k] = m.fext[k] - w.Fspread[k];
 }
 
 template <class T>
-void coupled_step(const Model<T>& m, State<T>& s, std::vector<T>& scratch_post) {
+void coupled_step(const Model<T>& m, State<T>& s, Work<T>& w) {
   const long S = m.S;
   const int N = m.n_atoms;
-  std::vector<T> Fc, Ftot;
-  coupling_forces(m, s, Fc, Ftot);
+  coupling_forces(m, s, w);
+  std::vector<T>& Ftot = w.Ftot;
+  std::vector<T>& scratch_post = w.post;
+#pragma omp parallel for schedule(static)
   for (long x = 0; x < S; ++x) {
     T gin[QMAX], gout[QMAX], F[3];
-    for (int i = 0; i < m.Q; ++i) gin[i] = s.g[i * S + x];
+    for (int i = 0; i < m.Q; ++i) gin[i] = s.g[i * m.P + x];
     for (int c = 0; c < 3; ++c) F[c] = Ftot[c * S + x];
     collide_node(m.Q, m.tau, m.rho0, gin, F, gout, m.trt_magic);
     if (m.kT > 0.0) {
@@ -659,13 +794,12 @@ void coupled_step(const Model<T>& m, State<T>& s, std::vector<T>& scratch_post) 
       site_noise(m.Q, m.kT, m.tau, rho, m.seed, s.step, x, xi, m.trt_magic);
       for (int i = 0; i < m.Q; ++i) gout[i] += xi[i];
     }
-    for (int i = 0; i < m.Q; ++i) scratch_post[i * S + x] = gout[i];
+    for (int i = 0; i < m.Q; ++i) scratch_post[i * m.P + x] = gout[i];
   }
   stream(m, scratch_post, s.g);
-  std::vector<T> Fff(3 * N);
-  atom_forces(m, s.X, Fff);
+  atom_forces_by_atom(m, s.X, w.Fff);
   for (int k = 0; k < 3 * N; ++k) {
-    s.V[k] = s.V[k] + (Fff[k] + Fc[k]) / m.mass;
+    s.V[k] = s.V[k] + (w.Fff[k] + w.Fc[k]) / m.mass;
     s.X[k] = s.X[k] + s.V[k];
   }
   s.step++;
@@ -735,9 +869,7 @@ void external_force(const or_params* p, const double* field, std::vector<T>& fex
 template <class T>
 void build_model(const or_params* p, const double* X0, const int32_t* bonds, const double* field,
                  Model<T>& m) {
-  m.Q = p->velocity_set == 27 ? 27 : 19;
-  for (int a = 0; a < 3; ++a) m.L[a] = p->L[a];
-  m.S = (long)p->L[0] * p->L[1] * p->L[2];
+  set_geometry(p->velocity_set == 27 ? 27 : 19, p->L, m);
   m.tau = T(p->tau);
   m.rho0 = T(p->rho0);
   m.gamma = T(p->gamma);
@@ -781,17 +913,17 @@ int run_impl(const or_params* p, double* g, double* X, double* V, const double* 
   build_model<T>(p, X0, bonds, field, m);
   State<T> s;
   s.step = p->step0;
-  s.g.resize(m.Q * m.S);
+  load_pops(m, g, s.g);
   s.X.resize(3 * (size_t)m.n_atoms);
   s.V.resize(3 * (size_t)m.n_atoms);
-  for (long k = 0; k < m.Q * m.S; ++k) s.g[k] = T(g[k]);
   for (long k = 0; k < 3L * m.n_atoms; ++k) {
     s.X[k] = T(X[k]);
     s.V[k] = T(V[k]);
   }
-  std::vector<T> post(m.Q * m.S);
-  for (int n = 0; n < n_steps; ++n) coupled_step(m, s, post);
-  for (long k = 0; k < m.Q * m.S; ++k) g[k] = val(s.g[k]);
+  Work<T> w;
+  w.size(m);
+  for (int n = 0; n < n_steps; ++n) coupled_step(m, s, w);
+  store_pops(m, s.g, g);
   for (long k = 0; k < 3L * m.n_atoms; ++k) {
     X[k] = val(s.X[k]);
     V[k] = val(s.V[k]);
@@ -881,12 +1013,11 @@ void or_collide_node_trt(double tau, double magic, double rho0, const double* g,
 // Streaming of a [Q][S] population array (post-collision in, pre-collision out).
 void or_stream_q(int32_t q, const int32_t* L, const double* post, double* pre) {
   Model<double> m;
-  m.Q = q == 27 ? 27 : 19;
-  for (int a = 0; a < 3; ++a) m.L[a] = L[a];
-  m.S = (long)L[0] * L[1] * L[2];
-  std::vector<double> in(post, post + m.Q * m.S), out(m.Q * m.S);
+  set_geometry(q == 27 ? 27 : 19, L, m);
+  std::vector<double> in, out((size_t)m.Q * m.P);
+  load_pops(m, post, in);
   stream(m, in, out);
-  std::memcpy(pre, out.data(), sizeof(double) * m.Q * m.S);
+  store_pops(m, out, pre);
 }
 
 void or_stream(const int32_t* L, const double* post, double* pre) { or_stream_q(19, L, post, pre); }
@@ -918,6 +1049,17 @@ void or_forces(const or_params* p, const double* X, const double* X0, const int3
   std::memcpy(F, Fv.data(), sizeof(double) * 3 * p->n_atoms);
 }
 
+// The same force field evaluated atom by atom over cell-list candidates (the form the coupled
+// step uses); equal to or_forces bit for bit.
+void or_forces_by_atom(const or_params* p, const double* X, const double* X0, const int32_t* bonds,
+                       double* F) {
+  Model<double> m;
+  build_model<double>(p, X0, bonds, nullptr, m);
+  std::vector<double> Xv(X, X + 3 * (size_t)p->n_atoms), Fv(3 * (size_t)p->n_atoms);
+  atom_forces_by_atom(m, Xv, Fv);
+  std::memcpy(F, Fv.data(), sizeof(double) * 3 * p->n_atoms);
+}
+
 double or_energy(const or_params* p, const double* X, const double* X0, const int32_t* bonds) {
   Model<double> m;
   build_model<double>(p, X0, bonds, nullptr, m);
@@ -937,12 +1079,11 @@ void or_external_force(const or_params* p, const double* field, double* out) {
 void or_observables(const or_params* p, const double* g, const double* field, double* rho,
                     double* u) {
   Model<double> m;
-  m.Q = q_of(p);
-  for (int a = 0; a < 3; ++a) m.L[a] = p->L[a];
-  m.S = (long)p->L[0] * p->L[1] * p->L[2];
+  set_geometry(q_of(p), p->L, m);
   std::vector<double> fext;
   external_force<double>(p, field, fext, m.S);
-  std::vector<double> gv(g, g + m.Q * m.S);
+  std::vector<double> gv;
+  load_pops(m, g, gv);
   for (long x = 0; x < m.S; ++x) {
     double dr, j[3];
     moments_at(m, gv, x, dr, j);
@@ -1005,16 +1146,16 @@ int or_loss_derivative(const or_params* p, const double* g, const double* X, con
   }
   State<Dual> s;
   s.step = p->step0;
-  s.g.resize(m.Q * m.S);
+  load_pops(m, g, s.g);
   s.X.resize(3 * (size_t)m.n_atoms);
   s.V.resize(3 * (size_t)m.n_atoms);
-  for (long k = 0; k < m.Q * m.S; ++k) s.g[k] = Dual(g[k]);
   for (long k = 0; k < 3L * m.n_atoms; ++k) {
     s.X[k] = Dual(X[k]);
     s.V[k] = Dual(V[k]);
   }
-  std::vector<Dual> post(m.Q * m.S);
-  for (int n = 0; n < n_steps; ++n) coupled_step(m, s, post);
+  Work<Dual> w;
+  w.size(m);
+  for (int n = 0; n < n_steps; ++n) coupled_step(m, s, w);
   Dual acc(0.0);
   for (int a = 0; a < m.n_atoms; ++a)
     for (int c = 0; c < 3; ++c) {
@@ -1040,11 +1181,14 @@ int or_step_sampled(const or_params* p, const double* g, const double* X, const 
   build_model<double>(p, X0, bonds, field, m);
   State<double> s;
   s.step = p->step0;
-  s.g.assign(g, g + m.Q * m.S);
+  load_pops(m, g, s.g);
   s.X.assign(X, X + 3 * (size_t)m.n_atoms);
   s.V.assign(V, V + 3 * (size_t)m.n_atoms);
-  std::vector<double> Fc, Ftot;
-  coupling_forces(m, s, Fc, Ftot);
+  Work<double> w;
+  w.size(m);
+  coupling_forces(m, s, w);
+  const std::vector<double>& Fc = w.Fc;
+  const std::vector<double>& Ftot = w.Ftot;
   const int* L = m.L;
   for (int k = 0; k < n_sites; ++k) {
     long xs = site_idx[k];
@@ -1052,7 +1196,7 @@ int or_step_sampled(const or_params* p, const double* g, const double* X, const 
     for (int i = 0; i < m.Q; ++i) {
       long src = site_index(L, wrap(x - CV[i][0], L[0]), wrap(y - CV[i][1], L[1]), wrap(z - CV[i][2], L[2]));
       double gin[QMAX], gout[QMAX], F[3];
-      for (int q = 0; q < m.Q; ++q) gin[q] = s.g[q * m.S + src];
+      for (int q = 0; q < m.Q; ++q) gin[q] = s.g[q * m.P + src];
       for (int c = 0; c < 3; ++c) F[c] = Ftot[c * m.S + src];
       collide_node(m.Q, m.tau, m.rho0, gin, F, gout, m.trt_magic);
       if (m.kT > 0.0) {

@@ -22,7 +22,10 @@ LIB = os.path.join(HERE, "liblbmd_oracle.so")
 # The oracle is compiled without target-specific flags so that the same binary runs on any
 # x86-64 host, and without floating-point contraction so that it evaluates exactly the
 # expressions as written.
-CXXFLAGS = ["-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math"]
+CXXFLAGS = ["-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+            # independent site and atom loops run on the host's cores (every value is computed
+            # by the same expression whatever the thread count)
+            "-fopenmp"]
 
 
 def build(force: bool = True) -> str:
@@ -82,6 +85,7 @@ def lib():
         L.or_interpolate.argtypes = [ip, dp, ctypes.c_int32, dp, dp]
         L.or_spread.argtypes = [ip, ctypes.c_int32, dp, dp, dp]
         L.or_forces.argtypes = [pp, dp, dp, ip, dp]
+        L.or_forces_by_atom.argtypes = [pp, dp, dp, ip, dp]
         L.or_energy.argtypes = [pp, dp, dp, ip]
         L.or_energy.restype = ctypes.c_double
         L.or_external_force.argtypes = [pp, dp, dp]
@@ -240,6 +244,15 @@ def forces(p: OrParams, X, X0, bonds):
     X = f64(X)
     F = np.zeros_like(X)
     lib().or_forces(ctypes.byref(p), _d(X), _d(f64(X0)), _i(i32(bonds).reshape(-1, 2)), _d(F))
+    return F
+
+
+def forces_by_atom(p: OrParams, X, X0, bonds):
+    """The force field evaluated atom by atom over cell-list candidates (the coupled step's
+    form); equal to forces() bit for bit."""
+    X = f64(X)
+    F = np.zeros_like(X)
+    lib().or_forces_by_atom(ctypes.byref(p), _d(X), _d(f64(X0)), _i(i32(bonds).reshape(-1, 2)), _d(F))
     return F
 
 
