@@ -10,7 +10,10 @@
  *   returned to the lattice through the forcing term S_i of Eq. (1) (Guo scheme) with the
  *   same weights; lattice and atoms advanced in lock-step, one step each.
  *   The atoms' own force field is a stand-in: harmonic tethers to the initial positions,
- *   harmonic bonds, and Lennard-Jones truncated at r_c with minimum image.
+ *   harmonic bonds, and Lennard-Jones cut off at r_c with minimum image, shifted so that its
+ *   force falls continuously to zero at r_c: with the plain term F_i = g0(r^2) r, the force is
+ *   (g0(r^2) - g0(r_c^2)) r below r_c and zero beyond (the paper's runs give a cut-off distance
+ *   only).
  *
  * Units are lattice units: dx = dt = 1, rest density rho0.  Nodes sit at integer
  * coordinates; positions are continuous.
@@ -97,7 +100,8 @@ typedef struct {
   int32_t n_bonds;           /* >= 0 */
   float k_bond, r0_bond;     /* harmonic bond U = k/2 (r - r0)^2 */
   float lj_eps, lj_sigma;    /* Lennard-Jones; lj_eps = 0 turns it off */
-  float lj_rc;               /* cut-off (truncated, not shifted); box >= 3 rc per axis */
+  float lj_rc;               /* cut-off of the pair terms (force-shifted to zero there);
+                                box >= 3 rc per axis */
   int32_t lj_exclude_bonded; /* 1: no LJ between bonded pairs */
   int32_t bf_kind;           /* lb_body_force */
   float bf_amp;
@@ -107,7 +111,7 @@ typedef struct {
   uint32_t seed[2];          /* key of the counter-based (Philox4x32-10) noise generator */
   float coul_k;              /* implicit-solvent Coulomb between atoms (Section 2.2: direct sum,
                                 permittivity growing with r): U = coul_k q_i q_j / r^2 under the
-                                Lennard-Jones cut-off and exclusions; charges from
+                                Lennard-Jones cut-off, shift and exclusions; charges from
                                 lb_set_charges (zero until set); 0 = off */
   float trt_magic;           /* collision variant: 0 = BGK (Eq. 1); > 0 = two relaxation times,
                                 the part of f - f_eq odd under c -> -c relaxing at omega- with

@@ -31,10 +31,10 @@
 //
 // The atom force field of the paper (CHARMM36 + implicit-solvent Coulomb) is replaced by
 // a stand-in: harmonic tethers to the initial positions, harmonic chain bonds, a
-// Lennard-Jones pair term truncated (not shifted) at r_c with minimum image, bonded pairs
-// optionally excluded, and the paper's implicit-solvent Coulomb term (direct summation with
-// a distance-dependent permittivity, i.e. one more 1/r: U = k_C q_i q_j / r^2) under the same
-// cut-off and exclusions.  Atom update: symplectic Euler, v += F/m then x += v (dt = 1).
+// Lennard-Jones pair term cut off at r_c with minimum image and shifted so that its force
+// vanishes continuously at r_c, bonded pairs optionally excluded, and the paper's
+// implicit-solvent Coulomb term (direct summation with a distance-dependent permittivity, i.e.
+// one more 1/r: U = k_C q_i q_j / r^2) under the same cut-off, shift and exclusions.  Atom update: symplectic Euler, v += F/m then x += v (dt = 1).
 //
 // Populations are kept as deviations g_i = f_i - w_i rho0 (exactly the same scheme,
 // written around the rest state).  All arithmetic is in the template scalar T:
@@ -520,32 +520,55 @@ bool pair_terms_on(const Model<T>& m) {
   return val(m.lj_eps) != 0.0 || val(m.coul_k) != 0.0;
 }
 
-// |F_i| / |r| of the pair terms at squared distance r2 (force on i along r = X_i - X_j):
-//   LJ: 24 eps / r^2 [2 (s/r)^12 - (s/r)^6];  Coulomb with permittivity ~ r: 2 k_C q_i q_j / r^4
+// The pair terms act below the cut-off r_c and are shifted so that the force falls to zero
+// continuously there (the paper gives its runs a cut-off distance only, Section 2.2; an
+// unshifted truncation makes the force jump at r_c, and then whether a pair within rounding of
+// r_c counts decides a finite force difference).  With the unshifted terms written as
+// F_i = g0(r^2) r (r = X_i - X_j):
+//   LJ: U0 = 4 eps [(s/r)^12 - (s/r)^6],  g0 = 24 eps / r^2 [2 (s/r)^12 - (s/r)^6];
+//   implicit-solvent Coulomb (permittivity ~ r): U0 = k_C q_i q_j / r^2,  g0 = 2 k_C q_i q_j / r^4;
+// each term below r_c is
+//   g(r^2) = g0(r^2) - g0(r_c^2),   U(r^2) = U0(r^2) - U0(r_c^2) + g0(r_c^2) (r^2 - r_c^2) / 2,
+// so that F = -grad U, and F and U are continuous and zero at r_c.
+template <class T>
+T lj_g0(const Model<T>& m, T r2) {
+  T sr2 = m.lj_sigma * m.lj_sigma / r2;
+  T sr6 = sr2 * sr2 * sr2;
+  return T(24.0) * m.lj_eps * (T(2.0) * sr6 * sr6 - sr6) / r2;
+}
+
+template <class T>
+T lj_u0(const Model<T>& m, T r2) {
+  T sr6 = (m.lj_sigma * m.lj_sigma / r2) * (m.lj_sigma * m.lj_sigma / r2) * (m.lj_sigma * m.lj_sigma / r2);
+  return T(4.0) * m.lj_eps * (sr6 * sr6 - sr6);
+}
+
+// |F_i| / |r| of the pair terms at squared distance r2 < r_c^2 (force on i along r)
 template <class T>
 T pair_force_over_r(const Model<T>& m, int i, int j, T r2) {
+  const T rc2 = m.lj_rc * m.lj_rc;
   T f = T(0.0);
-  if (val(m.lj_eps) != 0.0) {
-    T sr2 = m.lj_sigma * m.lj_sigma / r2;
-    T sr6 = sr2 * sr2 * sr2;
-    f += T(24.0) * m.lj_eps * (T(2.0) * sr6 * sr6 - sr6) / r2;
+  if (val(m.lj_eps) != 0.0) f += lj_g0(m, r2) - lj_g0(m, rc2);
+  if (val(m.coul_k) != 0.0) {
+    const T kqq2 = T(2.0) * m.coul_k * m.charge[i] * m.charge[j];
+    f += kqq2 / (r2 * r2) - kqq2 / (rc2 * rc2);
   }
-  if (val(m.coul_k) != 0.0) f += T(2.0) * m.coul_k * m.charge[i] * m.charge[j] / (r2 * r2);
   return f;
 }
 
 template <class T>
 T pair_energy(const Model<T>& m, int i, int j, T r2) {
+  const T rc2 = m.lj_rc * m.lj_rc;
   T e = T(0.0);
-  if (val(m.lj_eps) != 0.0) {
-    T sr6 = (m.lj_sigma * m.lj_sigma / r2) * (m.lj_sigma * m.lj_sigma / r2) * (m.lj_sigma * m.lj_sigma / r2);
-    e += T(4.0) * m.lj_eps * (sr6 * sr6 - sr6);
+  if (val(m.lj_eps) != 0.0) e += lj_u0(m, r2) - lj_u0(m, rc2) + T(0.5) * lj_g0(m, rc2) * (r2 - rc2);
+  if (val(m.coul_k) != 0.0) {
+    const T kqq = m.coul_k * m.charge[i] * m.charge[j];
+    e += kqq / r2 - kqq / rc2 + kqq / (rc2 * rc2) * (r2 - rc2);
   }
-  if (val(m.coul_k) != 0.0) e += m.coul_k * m.charge[i] * m.charge[j] / r2;
   return e;
 }
 
-// Stand-in force field at positions X (unwrapped): tethers, bonds, truncated pair terms.
+// Stand-in force field at positions X (unwrapped): tethers, bonds, cut-off pair terms.
 template <class T>
 void atom_forces(const Model<T>& m, const std::vector<T>& X, std::vector<T>& F) {
   const int N = m.n_atoms;

@@ -275,8 +275,8 @@ struct AdjAtomArgs {
   long plane;
   float gamma, inv_mass;
   const float* x0;
-  const float* d;
-  const float* v;
+  const float* d;     // [2][N][3] hi, lo
+  const float* v;     // [2][N][3] hi, lo
   const float* fc;
   const float* U;
   const float* uc;
@@ -305,7 +305,8 @@ __global__ __launch_bounds__(256) void k_adj_atoms(AdjAtomArgs a) {
     int i0[3];
     float fr[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) split(a.x0[3 * i + c], a.d[3 * i + c], a.n[c], i0[c], fr[c]);
+    for (int c = 0; c < 3; ++c)
+      split(a.x0[3 * i + c], a.d[3 * i + c], a.d[3 * a.N + 3 * i + c], a.n[c], i0[c], fr[c]);
     const float fcx = a.fc[3 * i], fcy = a.fc[3 * i + 1], fcz = a.fc[3 * i + 2];
     float wpx = 0.f, wpy = 0.f, wpz = 0.f;    // sum W phi
     float gx = 0.f, gy = 0.f, gz = 0.f;       // -sum grad W (F_c . phi)
@@ -347,7 +348,7 @@ __global__ __launch_bounds__(256) void k_adj_atoms(AdjAtomArgs a) {
     lfc[2] = vp[2] * a.inv_mass - wpz;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      dg += (double)lfc[c] * (double)(a.U[3 * i + c] - a.v[3 * i + c]);
+      dg += (double)lfc[c] * (double)((a.U[3 * i + c] - a.v[3 * i + c]) - a.v[3 * a.N + 3 * i + c]);
       lu[c] = a.gamma * lfc[c];
       a.lU[3 * i + c] = lu[c];
       a.lv_out[3 * i + c] = vp[c] - lu[c];

@@ -202,7 +202,7 @@ struct BinArgs {
   int N;
   AtomGeo g;
   const float* x0;
-  const float* d;
+  const float* d;     // [2][N][3]: hi, lo
   uint32_t* tile_flag;
   uint8_t* node_flag;
   int* base_count;
@@ -219,7 +219,8 @@ __global__ __launch_bounds__(256) void k_bin_mark(BinArgs a) {
   int i0[3];
   float fr[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) split(a.x0[3 * i + c], a.d[3 * i + c], a.g.n[c], i0[c], fr[c]);
+  for (int c = 0; c < 3; ++c)
+    split(a.x0[3 * i + c], a.d[3 * i + c], a.d[3 * a.N + 3 * i + c], a.g.n[c], i0[c], fr[c]);
   const int x1 = i0[0] + 1 == a.g.n[0] ? 0 : i0[0] + 1;
   const int y1 = i0[1] + 1 == a.g.n[1] ? 0 : i0[1] + 1;
   const int z1 = i0[2] + 1 == a.g.n[2] ? 0 : i0[2] + 1;
@@ -298,8 +299,8 @@ struct CoupleArgs {
   long plane;
   float gamma;
   const float* x0;
-  const float* d;
-  const float* v;
+  const float* d;         // [2][N][3]: hi, lo
+  const float* v;         // [2][N][3]: hi, lo
   const float* uc;
   float* fc;              // out: friction force on each atom
   float* U;               // out, optional: interpolated fluid velocity at each atom
@@ -314,7 +315,8 @@ __global__ __launch_bounds__(256) void k_couple(CoupleArgs a) {
   int i0[3];
   float fr[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) split(a.x0[3 * at + c], a.d[3 * at + c], a.n[c], i0[c], fr[c]);
+  for (int c = 0; c < 3; ++c)
+    split(a.x0[3 * at + c], a.d[3 * at + c], a.d[3 * a.N + 3 * at + c], a.n[c], i0[c], fr[c]);
   const int dx = k & 1, dy = (k >> 1) & 1, dz = (k >> 2) & 1;
   const int x = dx ? (i0[0] + 1 == a.n[0] ? 0 : i0[0] + 1) : i0[0];
   const int y = dy ? (i0[1] + 1 == a.n[1] ? 0 : i0[1] + 1) : i0[1];
@@ -338,9 +340,10 @@ __global__ __launch_bounds__(256) void k_couple(CoupleArgs a) {
     a.U[3 * atom + 1] = Uy;
     a.U[3 * atom + 2] = Uz;
   }
-  a.fc[3 * atom] = a.gamma * (Ux - a.v[3 * atom]);
-  a.fc[3 * atom + 1] = a.gamma * (Uy - a.v[3 * atom + 1]);
-  a.fc[3 * atom + 2] = a.gamma * (Uz - a.v[3 * atom + 2]);
+  const float* vlo = a.v + 3 * a.N;
+  a.fc[3 * atom] = a.gamma * ((Ux - a.v[3 * atom]) - vlo[3 * atom]);
+  a.fc[3 * atom + 1] = a.gamma * ((Uy - a.v[3 * atom + 1]) - vlo[3 * atom + 1]);
+  a.fc[3 * atom + 2] = a.gamma * ((Uz - a.v[3 * atom + 2]) - vlo[3 * atom + 2]);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -441,7 +444,7 @@ struct ForceArgs {
   long ncell;
   float L[3], invL[3];
   const float* x0;
-  const float* d;       // X^n - x0
+  const float* d;       // X^n - x0: [2][N][3], hi then lo
   float* ff;            // out: stand-in force field at X^n
   float k_tether;
   const int* bond_off;
@@ -492,14 +495,17 @@ template <bool kAdj>
 __device__ __forceinline__ void bonded_and_store(const ForceArgs& a, int i, float Fx, float Fy,
                                                  float Fz) {
   const float xi = a.x0[3 * i], yi = a.x0[3 * i + 1], zi = a.x0[3 * i + 2];
+  // displacement differences: hi parts of nearby atoms subtract exactly, then the lo parts
+  const float* dlo = a.d + 3 * a.N;
   const float dxi = a.d[3 * i], dyi = a.d[3 * i + 1], dzi = a.d[3 * i + 2];
+  const float lxi = dlo[3 * i], lyi = dlo[3 * i + 1], lzi = dlo[3 * i + 2];
   const int b0 = a.bond_off[i], b1 = a.bond_off[i + 1];
   // the first kBondPre partners (atom i itself stands in for a missing one): all loads are
   // in flight before the first is used
   int pj[kBondPre];
 #pragma unroll
   for (int k = 0; k < kBondPre; ++k) pj[k] = b0 + k < b1 ? a.bond_nbr[b0 + k] : i;
-  float xj[kBondPre][3], dj[kBondPre][3];
+  float xj[kBondPre][3], dj[kBondPre][3], lj_[kBondPre][3];
   float4 lj[kBondPre];
 #pragma unroll
   for (int k = 0; k < kBondPre; ++k) {
@@ -508,6 +514,7 @@ __device__ __forceinline__ void bonded_and_store(const ForceArgs& a, int i, floa
     for (int d = 0; d < 3; ++d) {
       xj[k][d] = a.x0[3 * j + d];
       dj[k][d] = a.d[3 * j + d];
+      lj_[k][d] = dlo[3 * j + d];
     }
     lj[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     if constexpr (kAdj) lj[k] = a.lf[j];
@@ -527,18 +534,18 @@ __device__ __forceinline__ void bonded_and_store(const ForceArgs& a, int i, floa
 #pragma unroll
   for (int k = 0; k < kBondPre; ++k) {
     if (b0 + k >= b1) break;
-    add_bond<kAdj>(a, min_image((xi - xj[k][0]) + (dxi - dj[k][0]), a.L[0], a.invL[0]),
-                   min_image((yi - xj[k][1]) + (dyi - dj[k][1]), a.L[1], a.invL[1]),
-                   min_image((zi - xj[k][2]) + (dzi - dj[k][2]), a.L[2], a.invL[2]), li, lj[k],
-                   Fx, Fy, Fz);
+    add_bond<kAdj>(a, min_image((xi - xj[k][0]) + ((dxi - dj[k][0]) + (lxi - lj_[k][0])), a.L[0], a.invL[0]),
+                   min_image((yi - xj[k][1]) + ((dyi - dj[k][1]) + (lyi - lj_[k][1])), a.L[1], a.invL[1]),
+                   min_image((zi - xj[k][2]) + ((dzi - dj[k][2]) + (lzi - lj_[k][2])), a.L[2], a.invL[2]),
+                   li, lj[k], Fx, Fy, Fz);
   }
   for (int b = b0 + kBondPre; b < b1; ++b) {
     const int j = a.bond_nbr[b];
     float4 l = make_float4(0.f, 0.f, 0.f, 0.f);
     if constexpr (kAdj) l = a.lf[j];
-    add_bond<kAdj>(a, min_image((xi - a.x0[3 * j]) + (dxi - a.d[3 * j]), a.L[0], a.invL[0]),
-                   min_image((yi - a.x0[3 * j + 1]) + (dyi - a.d[3 * j + 1]), a.L[1], a.invL[1]),
-                   min_image((zi - a.x0[3 * j + 2]) + (dzi - a.d[3 * j + 2]), a.L[2], a.invL[2]),
+    add_bond<kAdj>(a, min_image((xi - a.x0[3 * j]) + ((dxi - a.d[3 * j]) + (lxi - dlo[3 * j])), a.L[0], a.invL[0]),
+                   min_image((yi - a.x0[3 * j + 1]) + ((dyi - a.d[3 * j + 1]) + (lyi - dlo[3 * j + 1])), a.L[1], a.invL[1]),
+                   min_image((zi - a.x0[3 * j + 2]) + ((dzi - a.d[3 * j + 2]) + (lzi - dlo[3 * j + 2])), a.L[2], a.invL[2]),
                    li, l, Fx, Fy, Fz);
   }
   if constexpr (kAdj) {
@@ -552,7 +559,8 @@ __device__ __forceinline__ void bonded_and_store(const ForceArgs& a, int i, floa
   }
 }
 
-// Pair terms, cell-centric, staged in LDS.  A wavefront takes one occupied cell at a time
+// Pair terms (Lennard-Jones, implicit-solvent Coulomb; each cut off at r_c and shifted so
+// that its force vanishes there), cell-centric, staged in LDS.  A wavefront takes one occupied cell at a time
 // (persistent over the occupied-cell list):
 //   1. lanes 0..26 find the 27 neighbour cells (with the periodic shift of each) and their
 //      counts; a wave scan gives each cell's offset in the concatenation of their records;
@@ -599,6 +607,13 @@ __global__ __launch_bounds__(256) void k_forces_cells(ForceArgs a) {
   const float rc2_u = a.lj_rc2 * kU2, sig2_u = a.lj_sigma2 * kU2;
   const float eps24_u = a.lj_eps24 * (kAdj ? 1.0f : 16777216.0f);  // 2^24
   const float coul2_u = a.coul2 * (kAdj ? 1.0f : 4722366482869645213696.0f);   // 2^72
+  // Each pair term is shifted by its value at the cut-off, g(s) = g0(s) - g0(r_c^2), so the
+  // force falls continuously to zero at r_c (a pair whose distance rounds to either side of
+  // r_c then changes the force by a rounding-sized amount, not by a jump); the Jacobian term
+  // 2 g'(s) is that of g0.  Evaluated in the units above.
+  const float sr6c = (sig2_u / rc2_u) * (sig2_u / rc2_u) * (sig2_u / rc2_u);
+  const float lj_shift_u = eps24_u * (2.0f * sr6c * sr6c - sr6c) / rc2_u;
+  const float inv_rc4_u = 1.0f / (rc2_u * rc2_u);
   const int nc0 = a.g.nc[0], nc1 = a.g.nc[1], nc2 = a.g.nc[2];
   // XCD x takes the x-th contiguous eighth of the occupied-cell list (the list runs in cell
   // order, so neighbouring cells are near each other in it), interleaved over its own
@@ -761,14 +776,15 @@ __global__ __launch_bounds__(256) void k_forces_cells(ForceArgs a) {
           const float sr6 = sr2 * sr2 * sr2;
           // force on i = g(s) r with s = r^2; LJ: g = 24 eps (2 sigma^12 s^-7 - sigma^6 s^-4)
           // (forward: g 2^-24, which turns the fixed-point r into lattice units)
-          float f = eps24_u * (2.0f * sr6 * sr6 - sr6) * inv2;
+          float f = eps24_u * (2.0f * sr6 * sr6 - sr6) * inv2 - lj_shift_u;
           // the Jacobian uses 2 g'(s)
           float gp2 = 0.f;
           if constexpr (kAdj) gp2 = 2.0f * a.lj_eps24 * (4.0f * sr6 - 14.0f * sr6 * sr6) * inv2 * inv2;
           if constexpr (coul) {
             // implicit-solvent Coulomb: g = 2 k_C q_i q_j s^-2, 2 g' = -4 g / s
-            const float gc = coul2_u * qi * qj * inv2 * inv2;
-            f += gc;
+            const float cq = coul2_u * qi * qj;
+            const float gc = cq * inv2 * inv2;
+            f += gc - cq * inv_rc4_u;
             if constexpr (kAdj) gp2 -= 4.0f * gc * inv2;
           }
           f = use ? f : 0.f;
@@ -817,39 +833,52 @@ __global__ __launch_bounds__(256) void k_bonded_forces(ForceArgs a) {
 }
 
 // Symplectic Euler with the force field at X^n and the friction of this step:
-// v^{n+1} = v^n + (F_ff + F_c)/m, X^{n+1} = X^n + v^{n+1}.
+// v^{n+1} = v^n + (F_ff + F_c)/m, X^{n+1} = X^n + v^{n+1}: the velocity increment is
+// rounded once, then added to the float-float velocity, which is added to the float-float
+// displacement, both exactly.
 struct IntegrateArgs {
   int N;
   float inv_mass;
   const float* ff;
   const float* fc;
-  const float* d;
-  float* d_next;
-  float* v;
+  const float* d;       // [2][N][3] hi, lo
+  float* d_next;        // [2][N][3]
+  float* v;             // [2][N][3]
   uint32_t* err;
 };
 
 __global__ __launch_bounds__(256) void k_integrate(IntegrateArgs a) {
   const int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= a.N) return;
+  const int lo = 3 * a.N;
   bool finite = true;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const int k = 3 * t + c;
-    const float vn = a.v[k] + (a.ff[k] + a.fc[k]) * a.inv_mass;
-    finite = finite && __builtin_isfinite(vn);
-    a.v[k] = vn;
-    a.d_next[k] = a.d[k] + vn;
+    float vh = a.v[k], vl = a.v[lo + k];
+    ff_add(vh, vl, (a.ff[k] + a.fc[k]) * a.inv_mass, 0.0f);
+    finite = finite && __builtin_isfinite(vh);
+    float dh = a.d[k], dl = a.d[lo + k];
+    ff_add(dh, dl, vh, vl);
+    a.v[k] = vh;
+    a.v[lo + k] = vl;
+    a.d_next[k] = dh;
+    a.d_next[lo + k] = dl;
   }
   if (!finite) atomicOr(a.err, kErrNonFinite);
 }
 
+// unwrapped positions x0 + d and velocities, each rounded once from its exact sum
 __global__ __launch_bounds__(256) void k_read_atoms(int N, const float* x0, const float* d,
                                                     const float* v, float* xo, float* vo) {
   const int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= 3 * N) return;
-  if (xo) xo[t] = x0[t] + d[t];
-  if (vo) vo[t] = v[t];
+  if (xo) {
+    float s, e;
+    two_sum(x0[t], d[t], s, e);
+    xo[t] = s + (e + d[3 * N + t]);
+  }
+  if (vo) vo[t] = v[t] + v[3 * N + t];
 }
 
 }  // namespace

@@ -12,14 +12,48 @@ __device__ __forceinline__ int wrapi(int a, int n) {
   return r < 0 ? r + n : r;
 }
 
-// Integer node and fraction of (x0 + d) along one axis, the node wrapped into [0, n).
-// The clamp keeps a diverging displacement (reported by the velocity check) from
-// producing out-of-range integer conversions.
-__device__ __forceinline__ void split(float x0, float d, int n, int& i0, float& frac) {
+// The atoms' displacement d = X - x0 and velocity v are float-float pairs, hi + lo: hi is the
+// value rounded to FP32 and lo the remainder, so the integrator accumulates them exactly and
+// every use rounds once from the exact sum instead of carrying the rounding of every earlier
+// step.  The arrays hold all hi parts [N][3], then all lo parts [N][3].
+//
+// s + e = a + b exactly (Knuth's two-sum; needs round-to-nearest and no reassociation)
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  const float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// (hi, lo) + (b_hi, b_lo) renormalised so that hi is the sum rounded to FP32
+__device__ __forceinline__ void ff_add(float& hi, float& lo, float b_hi, float b_lo) {
+  float s, e;
+  two_sum(hi, b_hi, s, e);
+  const float t = (lo + b_lo) + e;
+  hi = s + t;
+  lo = t - (hi - s);
+}
+
+// Integer node and fraction of X = x0 + (d_hi + d_lo) along one axis, the node wrapped into
+// [0, n).  The fraction is formed from the exact sum of the anchor's fraction and d_hi plus
+// d_lo, so it keeps FP32 resolution however far the atom has moved.  The clamp keeps a
+// diverging displacement (reported by the velocity check) from producing out-of-range integer
+// conversions.
+__device__ __forceinline__ void split(float x0, float d_hi, float d_lo, int n, int& i0,
+                                      float& frac) {
   const float ia = floorf(x0);
-  const float t = fminf(fmaxf((x0 - ia) + d, -1.0e6f), 1.0e6f);
-  const float fl = floorf(t);
-  frac = t - fl;
+  float s, e;
+  two_sum(x0 - ia, fminf(fmaxf(d_hi, -1.0e6f), 1.0e6f), s, e);
+  float fl = floorf(s);
+  float r = (s - fl) + (e + d_lo);   // s - fl is exact
+  if (r < 0.0f) {
+    r += 1.0f;
+    fl -= 1.0f;
+  }
+  if (r >= 1.0f) {   // also a negative r whose sum with 1 rounded up to 1
+    r -= 1.0f;
+    fl += 1.0f;
+  }
+  frac = r;
   i0 = wrapi((int)ia + (int)fl, n);
 }
 

@@ -286,7 +286,7 @@ __global__ __launch_bounds__(256) void k_reduce_pops(RedArgs a) {
 struct FinalArgs {
   const double* partial;
   int nblocks;
-  const float* vel;   // [N][3]
+  const float* vel;   // [2][N][3]: hi, lo
   int N;
   float mass;
   double rest_mass;   // rho0 * S
@@ -302,10 +302,11 @@ __global__ __launch_bounds__(1024) void k_reduce_final(FinalArgs a) {
   bool finite = true;
   for (int i = threadIdx.x; i < a.N; i += 1024) {
     const float vx = a.vel[3 * i], vy = a.vel[3 * i + 1], vz = a.vel[3 * i + 2];
+    const float* lo = a.vel + 3 * a.N;
     finite = finite && __builtin_isfinite(vx + vy + vz);
-    acc[4] += (double)a.mass * vx;
-    acc[5] += (double)a.mass * vy;
-    acc[6] += (double)a.mass * vz;
+    acc[4] += (double)a.mass * ((double)vx + (double)lo[3 * i]);
+    acc[5] += (double)a.mass * ((double)vy + (double)lo[3 * i + 1]);
+    acc[6] += (double)a.mass * ((double)vz + (double)lo[3 * i + 2]);
   }
   if (!finite) atomicOr(a.err, kErrNonFinite);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -459,16 +460,20 @@ hipError_t launch_write_populations(lb_ctx* c, const float* g) {
   return hipGetLastError();
 }
 
-hipError_t launch_invariants(lb_ctx* c) {
+int invariants_blocks(const lb_ctx* c) {
+  const int nb = blocks_for(c->geo.S, 256);
+  return nb > kRedBlocks ? kRedBlocks : nb;
+}
+
+hipError_t launch_invariants(lb_ctx* c, double* partial, double* out) {
   const Geometry& g = c->geo;
   RedArgs a;
   a.f = c->popbuf[c->cur];
   a.plane = g.plane;
   a.S = (int)g.S;
-  a.partial = (double*)(c->ws + c->lay.red_partial);
+  a.partial = partial;
   a.err = (uint32_t*)(c->ws + c->lay.err);
-  int nb = blocks_for(g.S, 256);
-  if (nb > kRedBlocks) nb = kRedBlocks;
+  const int nb = invariants_blocks(c);
   dispatch_store_q(c, [&](auto st, auto q) {
     hipLaunchKernelGGL((k_reduce_pops<decltype(st)::value, decltype(q)::value>), dim3(nb), dim3(256), 0,
                        c->stream, a);
@@ -482,7 +487,7 @@ hipError_t launch_invariants(lb_ctx* c) {
   f.N = c->p.n_atoms;
   f.mass = c->p.mass;
   f.rest_mass = (double)c->p.rho0 * (double)g.S;
-  f.out = (double*)(c->ws + c->lay.red_out);
+  f.out = out;
   f.err = a.err;
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1024), 0, c->stream, f);
   return hipGetLastError();

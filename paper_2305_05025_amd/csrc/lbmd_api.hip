@@ -82,9 +82,10 @@ Layout plan(const lb_params* p, const Geometry& g) {
   l.fext_tab = take((size_t)g.ny * 4);
   l.fext_field = take(p->bf_kind == LB_BF_FIELD ? 3 * (size_t)g.plane * 4 : 0);
   l.x0 = take(3 * N * 4);
-  l.disp[0] = take(3 * N * 4);
-  l.disp[1] = take(3 * N * 4);
-  l.vel = take(3 * N * 4);
+  // displacement and velocity: float-float pairs, all hi parts then all lo parts
+  l.disp[0] = take(2 * 3 * N * 4);
+  l.disp[1] = take(2 * 3 * N * 4);
+  l.vel = take(2 * 3 * N * 4);
   l.fc = take(3 * N * 4);
   l.ff = take(3 * N * 4);
   l.charge = take(N * 4);
@@ -305,7 +306,8 @@ lb_status lb_init(const lb_params* p, void* workspace, size_t workspace_bytes, c
       {lay.fcoup[1], N ? 3 * (size_t)g.plane * 4 : 0}, {lay.tile_flag[1], N ? (size_t)g.ntiles * 4 : 0},
       {lay.base_count[0], N ? (size_t)g.plane * 4 : 0}, {lay.base_count[1], N ? (size_t)g.plane * 4 : 0},
       {lay.node_flag, N ? (size_t)g.plane : 0}, {lay.uc, N ? 3 * (size_t)g.plane * 4 : 0},
-      {lay.disp[0], 12 * (size_t)N}, {lay.disp[1], 12 * (size_t)N}, {lay.fc, 12 * (size_t)N},
+      {lay.disp[0], 24 * (size_t)N}, {lay.disp[1], 24 * (size_t)N}, {lay.fc, 12 * (size_t)N},
+      {lay.vel, 24 * (size_t)N},
       {lay.cell_count, (size_t)g.ncell * 4}, {lay.err, 16},
       {lay.fext_field, p->bf_kind == LB_BF_FIELD ? 3 * (size_t)g.plane * 4 : 0}};
   for (const Z& z : zs)
@@ -525,7 +527,7 @@ lb_status lb_status_check(lb_ctx* c) {
 lb_status lb_invariants(lb_ctx* c, double out7[7]) {
   if (!c) return fail(nullptr, LB_EINVAL, "context is NULL");
   if (!out7) return fail(c, LB_EINVAL, "out7 is NULL");
-  hipError_t e = launch_invariants(c);
+  hipError_t e = launch_invariants(c, (double*)(c->ws + c->lay.red_partial), (double*)(c->ws + c->lay.red_out));
   if (e != hipSuccess) return hip_fail(c, e, "invariants launch");
   double h[8];
   e = hipMemcpyAsync(h, c->ws + c->lay.red_out, sizeof h, hipMemcpyDeviceToHost, c->stream);
@@ -537,27 +539,27 @@ lb_status lb_invariants(lb_ctx* c, double out7[7]) {
 
 int64_t lb_step_count(const lb_ctx* c) { return c ? c->step : -1; }
 
-// snapshot layout: [256-byte header: int64 step][populations][displacement][velocity]
+// snapshot layout: [256-byte header: int64 step][populations][displacement hi, lo][velocity hi, lo]
 static size_t state_pop_bytes(const lb_ctx* c) { return (size_t)c->geo.q * c->geo.plane * c->geo.elem; }
 
 size_t lb_state_bytes(const lb_ctx* c) {
   if (!c) return 0;
-  return 256 + round_up(state_pop_bytes(c), 256) + 2 * round_up(12 * (size_t)c->p.n_atoms, 256);
+  return 256 + round_up(state_pop_bytes(c), 256) + 2 * round_up(24 * (size_t)c->p.n_atoms, 256);
 }
 
 lb_status lb_state_save(lb_ctx* c, void* dst) {
   if (!c) return fail(nullptr, LB_EINVAL, "context is NULL");
   if (!dst || (uintptr_t)dst % 256) return fail(c, LB_EINVAL, "dst must be a 256-byte aligned device buffer");
   char* d = (char*)dst;
-  const size_t pb = round_up(state_pop_bytes(c), 256), ab = round_up(12 * (size_t)c->p.n_atoms, 256);
+  const size_t pb = round_up(state_pop_bytes(c), 256), ab = round_up(24 * (size_t)c->p.n_atoms, 256);
   hipError_t e = launch_store_i64(d, c->step, c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(d + 256, c->popbuf[c->cur], state_pop_bytes(c), hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess && c->p.n_atoms > 0) {
-    e = hipMemcpyAsync(d + 256 + pb, c->ws + c->lay.disp[c->dcur], 12 * (size_t)c->p.n_atoms,
+    e = hipMemcpyAsync(d + 256 + pb, c->ws + c->lay.disp[c->dcur], 24 * (size_t)c->p.n_atoms,
                        hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(d + 256 + pb + ab, c->ws + c->lay.vel, 12 * (size_t)c->p.n_atoms,
+      e = hipMemcpyAsync(d + 256 + pb + ab, c->ws + c->lay.vel, 24 * (size_t)c->p.n_atoms,
                          hipMemcpyDeviceToDevice, c->stream);
   }
   return e == hipSuccess ? LB_OK : hip_fail(c, e, "state save");
@@ -567,17 +569,17 @@ lb_status lb_state_load(lb_ctx* c, const void* src) {
   if (!c) return fail(nullptr, LB_EINVAL, "context is NULL");
   if (!src || (uintptr_t)src % 256) return fail(c, LB_EINVAL, "src must be a 256-byte aligned device buffer");
   const char* s = (const char*)src;
-  const size_t pb = round_up(state_pop_bytes(c), 256), ab = round_up(12 * (size_t)c->p.n_atoms, 256);
+  const size_t pb = round_up(state_pop_bytes(c), 256), ab = round_up(24 * (size_t)c->p.n_atoms, 256);
   int64_t step = 0;
   hipError_t e = hipMemcpyAsync(&step, s, 8, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->popbuf[c->cur], s + 256, state_pop_bytes(c), hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess && c->p.n_atoms > 0) {
-    e = hipMemcpyAsync(c->ws + c->lay.disp[c->dcur], s + 256 + pb, 12 * (size_t)c->p.n_atoms,
+    e = hipMemcpyAsync(c->ws + c->lay.disp[c->dcur], s + 256 + pb, 24 * (size_t)c->p.n_atoms,
                        hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(c->ws + c->lay.vel, s + 256 + pb + ab, 12 * (size_t)c->p.n_atoms,
+      e = hipMemcpyAsync(c->ws + c->lay.vel, s + 256 + pb + ab, 24 * (size_t)c->p.n_atoms,
                          hipMemcpyDeviceToDevice, c->stream);
   }
   if (e != hipSuccess) return hip_fail(c, e, "state load");
@@ -677,7 +679,7 @@ AdjLayout plan_adjoint(const lb_ctx* c, int k) {
 size_t state_atom_offset(const lb_ctx* c) { return 256 + round_up(state_pop_bytes(c), 256); }
 
 hipError_t copy_atoms(lb_ctx* c, char* dst_disp, char* dst_vel, const char* src_disp, const char* src_vel) {
-  return launch_copy_pair(dst_disp, src_disp, dst_vel, src_vel, 12 * (size_t)c->p.n_atoms, c->stream);
+  return launch_copy_pair(dst_disp, src_disp, dst_vel, src_vel, 24 * (size_t)c->p.n_atoms, c->stream);
 }
 
 }  // namespace
@@ -713,7 +715,7 @@ lb_status lb_backward(lb_ctx* c, const void* ckpts, int32_t n_steps, int32_t k, 
 
   char* A = (char*)adj_ws;
   const size_t N3 = 3 * (size_t)c->p.n_atoms;
-  const size_t aoff = state_atom_offset(c), abytes = round_up(12 * (size_t)c->p.n_atoms, 256);
+  const size_t aoff = state_atom_offset(c), abytes = round_up(24 * (size_t)c->p.n_atoms, 256);
   auto slot = [&](int q) { return A + L.slots + (size_t)q * sb; };
   const hipStream_t as = c->astream;
   char* pb0 = c->popbuf[0];

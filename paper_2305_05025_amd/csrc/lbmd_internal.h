@@ -69,8 +69,8 @@ struct Layout {
   size_t fext_tab;     // float [ny]   (Kolmogorov / sign-shear profile)
   size_t fext_field;   // float [3][plane] (caller field)
   size_t x0;           // float [N][3] anchors
-  size_t disp[2];      // float [N][3] displacement X - x0, double-buffered
-  size_t vel;          // float [N][3]
+  size_t disp[2];      // float [2][N][3] displacement X - x0 (hi, lo), double-buffered
+  size_t vel;          // float [2][N][3] velocity (hi, lo)
   size_t fc;           // float [N][3] friction force of the current step
   size_t ff;           // float [N][3] stand-in force field at X^n
   size_t charge;       // float [N] atom charges (Coulomb term)
@@ -167,7 +167,10 @@ hipError_t launch_sweep(lb_ctx* c, const void* fin, void* fout, hipStream_t st);
 hipError_t launch_read_fields(lb_ctx* c, float* rho, float* u);
 hipError_t launch_read_populations(lb_ctx* c, float* g);
 hipError_t launch_write_populations(lb_ctx* c, const float* g);
-hipError_t launch_invariants(lb_ctx* c);
+// the FP64 sums of the current state: per-workgroup partials (invariants_blocks(c) x 4
+// doubles) into `partial`, the 7 results into `out` (device pointers)
+int invariants_blocks(const lb_ctx* c);
+hipError_t launch_invariants(lb_ctx* c, double* partial, double* out);
 hipError_t launch_store_i64(void* dst, int64_t v, hipStream_t s);
 
 // ---- kernel launchers (atoms.hip) ----

@@ -222,3 +222,25 @@ def test_adjoint_matches_gpu_central_differences():
         say("FD body force direction", q, "eps", eps, "adjoint", g, "central difference", fd)
     say("adjoint vs GPU central differences, rel. errors", errs)
     assert max(errs.values()) < 2e-3, errs
+
+
+_ORACLE_CACHE = {}
+
+
+@pytest.mark.parametrize("k", [5, 20])
+def test_adjoint_differentiation_workload_full_size(O, k):
+    """The differentiation workload at its full size: 96^3 lattice, one 5,000-atom globule
+    (bonds + Lennard-Jones), a seeded random body-force field, the workload's loss target;
+    20 steps in segments of k = 5 (four segments) and k = 20 (one).  Gradients for gamma, tau
+    and two directions of the body-force field against the oracle's dual numbers."""
+    from workloads import make_workload
+    w = make_workload(3)
+    rng = np.random.default_rng(303)
+    field = rng.normal(0, 1e-5, size=(3,) + tuple(w.L[::-1]))
+    D = w.target_shift.astype(np.float64)
+    dfields = _dfields(rng, field.shape)
+    outs, _ = _gpu_grads(w, field, D, 20, k)
+    if "c3" not in _ORACLE_CACHE:
+        say("oracle dual-number derivatives, 96^3, 20 steps")
+        _ORACLE_CACHE["c3"] = _oracle_grads(O, w, field, D, 20, dfields)
+    _check(outs, _ORACLE_CACHE["c3"], dfields, 1e-3)

@@ -4,7 +4,8 @@ fifty globules and sign-shear forcing), in the launch configuration bench.py tim
 streams, FP32 storage): one coupled step from a seeded random lattice state and the
 workload's atoms, compared with the oracle on sampled outputs it computes one by one
 (populations at sampled sites, half of them on atom stencils; positions and velocities of
-sampled atoms).  Rel. L2 over the samples <= 1e-5."""
+sampled atoms).  Rel. L2 over the samples <= 1e-5, and element by element
+max |GPU - oracle| / max |oracle| <= 1e-5."""
 import numpy as np
 import pytest
 
@@ -63,3 +64,10 @@ def test_one_step_full_size_sampled(O, config):
     errs = {"g": rel_l2(gs, go), "disp": rel_l2(d, Xo - x0), "v": rel_l2(vs, Vo)}
     say("  rel. L2 over samples:", errs)
     assert max(errs.values()) < 1e-5, errs
+    # element by element: max |GPU - oracle| / max |oracle| over every sampled value, so that
+    # a wrong value at a few nodes cannot hide in the norm
+    ew = {"g": np.abs(gs - go).max() / np.abs(go).max(),
+          "disp": np.abs(d - (Xo - x0)).max() / np.abs(Xo - x0).max(),
+          "v": np.abs(vs - Vo).max() / np.abs(Vo).max()}
+    say("  max |diff| / max |ref| over samples:", ew)
+    assert max(ew.values()) < 1e-5, ew

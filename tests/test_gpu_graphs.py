@@ -1,11 +1,12 @@
-"""For a graph replay of the steady-state steps of the overlapped three-stream schedule
-(eight steps per graph; LBMD_NO_GRAPHS at context creation would turn it off).  Replays must
-give the same bits as the eager launches: calls of different lengths, so that replays start
-in both step parities with eager steps between them, and synchronisations and reads between
-the calls; a globule with LJ and bonds, a ragged ball with a body-force field, D3Q27 with two
-relaxation times and FP16 storage."""
-import os
+"""For a graph replay of the steady-state steps of the overlapped schedule.  Replays must give
+the same bits as the eager launches: calls of different lengths, so that replays start in both
+step parities with eager steps between them, and synchronisations and reads between the calls;
+a globule with LJ and bonds, a ragged ball with a body-force field, D3Q27 with two relaxation
+times and FP16 storage.
 
+The library has no graph path at present (every step is launched eagerly): the test is skipped,
+and un-skipped it fails at once rather than compare eager launches with themselves.  A graph
+path would be switched on by a parameter flag named LB_FLAG_STEP_GRAPHS."""
 import numpy as np
 import pytest
 
@@ -21,14 +22,17 @@ pytestmark = [
 ]
 
 
+def _graph_flag():
+    from paper_2305_05025_amd import _abi as A
+    flag = getattr(A, "LB_FLAG_STEP_GRAPHS", None)
+    if flag is None:
+        pytest.fail("the library has no graph path (no LB_FLAG_STEP_GRAPHS): nothing to compare")
+    return flag
+
+
 def _make(w, graphs, **kw):
     from paper_2305_05025_amd.coupled import CoupledLB
-    if not graphs:
-        os.environ["LBMD_NO_GRAPHS"] = "1"
-    try:
-        return CoupledLB.from_workload(w, **kw)
-    finally:
-        os.environ.pop("LBMD_NO_GRAPHS", None)
+    return CoupledLB.from_workload(w, flags=_graph_flag() if graphs else 0, **kw)
 
 
 def _workload(kind):

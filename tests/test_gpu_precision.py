@@ -1,13 +1,19 @@
 """Error of each population storage format (FP32, FP16, BF16 deviations; collision in FP32)
-against the FP64 oracle after many steps.
+against the FP64 oracle.
 
-Two cases:
+Cases:
   * lattice only: a Kolmogorov flow from rest plus a shear wave, 48 x 48 x 16, 300 steps (no
     atoms, so no chaotic amplification: the errors are those of the storage format);
   * coupled: one 5,000-atom globule (bonds + Lennard-Jones) in a 48^3 box with the
-    parameters of the 256^3 / 200,000-atom workload (tau 0.55, gamma 0.2), 200 steps.  The
-    atom dynamics are chaotic, so the oracle's own FP32 run (same algorithm, float
-    arithmetic) is measured beside it as the floor that rounding alone produces.
+    parameters of the 256^3 / 200,000-atom workload (tau 0.55, gamma 0.2).  Gated after 30
+    steps, where the spread that one-ulp changes of the initial velocities produce in the FP64
+    scheme is still ~1e-7: FP32 within 1e-5 on u, g, displacement and velocity; FP16 and
+    BF16 within the stated tolerances (u 5e-3 and 2e-2, displacement and velocity 1e-3 and
+    1e-2).  After 200 steps the chaotic atom dynamics have amplified every rounding
+    difference, and that table is printed, not gated;
+  * the 256^3 / 200,000-atom workload itself over 500 steps, FP16 and BF16 against the GPU's
+    FP32 run (the oracle is compared with all three formats at this size over 10 steps in
+    test_gpu_fullsize_steps.py): gated at 50 steps, printed at 500.
 Each test prints its table (rel. L2 of u, rho - rho0, atom displacement and velocity).
 """
 import numpy as np
@@ -46,29 +52,33 @@ def test_storage_formats_lattice_only(O):
 
 def test_storage_formats_coupled_globule(O):
     from workloads import globule_workload
-    steps = 200
     w = globule_workload(48, 1, 5000, seed=2, tau=0.55, gamma=0.2)
-    orc = oracle_run(O, w, steps)
-    rows = {"oracle-f32": compare(oracle_run(O, w, steps, precision="f32"), orc, w)}
-    for fmt in ("f32", "f16", "bf16"):
-        rows["gpu-" + fmt] = compare(gpu_run(w, steps, storage=fmt), orc, w)
-    _table("one 5,000-atom globule in 48^3, tau 0.55, gamma 0.2, %d steps" % steps, rows)
-    floor = rows["oracle-f32"]
-    for k in ("u", "disp", "v"):
-        assert rows["gpu-f32"][k] < max(50 * floor[k], 1e-5), (k, rows)
-    assert rows["gpu-f16"]["u"] < 5e-2
-    assert rows["gpu-bf16"]["u"] < 2e-1
+    tables = {}
+    for steps in (30, 200):
+        orc = oracle_run(O, w, steps)
+        rows = {"oracle-f32": compare(oracle_run(O, w, steps, precision="f32"), orc, w)}
+        for fmt in ("f32", "f16", "bf16"):
+            rows["gpu-" + fmt] = compare(gpu_run(w, steps, storage=fmt), orc, w)
+        _table("one 5,000-atom globule in 48^3, tau 0.55, gamma 0.2, %d steps" % steps, rows)
+        tables[steps] = rows
+    rows = tables[30]
+    for k in ("u", "g", "disp", "v"):
+        assert rows["gpu-f32"][k] < 1e-5, (k, rows)
+    assert rows["gpu-f16"]["u"] < 5e-3 and rows["gpu-bf16"]["u"] < 2e-2, rows
+    for k in ("disp", "v"):
+        assert rows["gpu-f16"][k] < 1e-3 and rows["gpu-bf16"][k] < 1e-2, (k, rows)
+    # after 200 steps: printed above; the FP32 path stays far below the oracle's own FP32 run
+    assert tables[200]["gpu-f32"]["v"] < tables[200]["oracle-f32"]["v"], tables[200]
 
 
 def test_storage_formats_full_size_500_steps():
-    """The 256^3 / 200,000-atom workload at its full size, read after 50 and after 500 steps.
-    The oracle cannot run this (its Lennard-Jones term is O(N^2)), so the narrow formats are
-    compared with the GPU's FP32 path, whose parity with the oracle is checked on smaller
-    cases and on one full-size step.  An FP32 run whose initial velocities differ by one ulp
-    gives the spread that the chaotic atom dynamics alone produce.  After 500 steps that
-    spread is of order one and the formats' differences lie within it (gate: 1.3x the spread
-    for FP16, 2x for BF16); after 50 steps the spread is still small and the formats' own
-    error shows (gate: u within 1e-3 for FP16, 1e-2 for BF16; measured 2.4e-4 and 1.7e-3)."""
+    """The 256^3 / 200,000-atom workload at its full size, read after 50 and after 500 steps,
+    the narrow formats against the GPU's FP32 path (whose parity with the FP64 oracle at this
+    size is checked over 10 steps in test_gpu_fullsize_steps.py).  An FP32 run whose initial
+    velocities differ by one ulp gives the spread that the chaotic atom dynamics alone
+    produce.  After 50 steps that spread is still small and the formats' own error shows
+    (gate: u within 1e-3 for FP16, 1e-2 for BF16); after 500 steps the spread is of order one
+    and the table is printed, not gated."""
     import torch
     from paper_2305_05025_amd.coupled import CoupledLB, params_from_workload
     from workloads import make_workload
@@ -103,7 +113,9 @@ def test_storage_formats_full_size_500_steps():
         say("256^3, 200,000 atoms, %d steps: rel. L2 against the GPU's FP32 run" % m)
         for k, r in rows[m].items():
             say("  %-16s" % k + "".join("  %s %.3e" % (q, r[q]) for q in ("u", "disp", "v")))
-    spread = rows[500]["f32, v0 + 1 ulp"]
-    for q in ("u", "disp", "v"):
-        assert rows[500]["f16"][q] < 1.3 * spread[q] and rows[500]["bf16"][q] < 2.0 * spread[q], rows
+    # the formats' own error shows at 50 steps (measured 2.4e-4 and 1.7e-3 on u); by 500 steps
+    # the atom trajectories of every run have decorrelated from one another (printed only)
     assert rows[50]["f16"]["u"] < 1e-3 and rows[50]["bf16"]["u"] < 1e-2, rows
+    for m in marks:
+        for r in rows[m].values():
+            assert all(np.isfinite(x) for x in r.values()), rows

@@ -1,8 +1,9 @@
 """Pins of the oracle's stand-in force field and atom integrator: Newton's third law, force =
--gradient of the energy (central differences), the Lennard-Jones landmarks (U(sigma) = 0,
-U(2^(1/6) sigma) = -eps with zero force, nothing beyond r_c), the harmonic bond at rest
-length, minimum image, bonded exclusion, and the symplectic-Euler map of a tethered atom
-(closed form as a matrix power)."""
+-gradient of the energy (central differences), the Lennard-Jones landmarks far from the cut-off
+(U(sigma) = 0, U(2^(1/6) sigma) = -eps with zero force), force and energy falling continuously
+to zero at the cut-off and nothing beyond it, the harmonic bond at rest length, minimum image,
+bonded exclusion, and the symplectic-Euler map of a tethered atom (closed form as a matrix
+power)."""
 import numpy as np
 import pytest
 
@@ -16,12 +17,17 @@ def _pair_params(O, **kw):
 
 
 def test_lj_landmarks(O):
-    p = _pair_params(O)
+    """With the cut-off 100 sigma away (two atoms: the minimum image picks the one pair) the
+    shift that makes the force vanish at r_c changes the energy by less than 1e-12 and the force
+    by less than 1e-17: the plain Lennard-Jones landmarks U(sigma) = 0 and U(2^(1/6) sigma) =
+    -eps with zero force."""
+    pf = _pair_params(O, lj_rc=100.0)
     for r, U_want in ((1.0, 0.0), (2 ** (1 / 6), -0.01)):
         X = np.array([[5.0, 5.0, 5.0], [5.0 + r, 5.0, 5.0]])
-        assert abs(O.energy(p, X, X, E0) - U_want) < 1e-15
+        assert abs(O.energy(pf, X, X, E0) - U_want) < 1e-12
     X = np.array([[5.0, 5.0, 5.0], [5.0 + 2 ** (1 / 6), 5.0, 5.0]])
-    assert np.abs(O.forces(p, X, X, E0)).max() < 1e-15
+    assert np.abs(O.forces(pf, X, X, E0)).max() < 1e-16
+    p = _pair_params(O)
     # repulsive inside the minimum, attractive beyond, zero past the cut-off
     X = np.array([[5.0, 5.0, 5.0], [6.0, 5.0, 5.0]])
     F = O.forces(p, X, X, E0)
@@ -31,6 +37,30 @@ def test_lj_landmarks(O):
     assert F[0, 0] > 0 > F[1, 0]
     X = np.array([[5.0, 5.0, 5.0], [7.5001, 5.0, 5.0]])
     assert np.abs(O.forces(p, X, X, E0)).max() == 0.0
+
+
+@pytest.mark.parametrize("kind", ["lj", "coulomb"])
+def test_pair_terms_vanish_continuously_at_cutoff(O, kind):
+    """Just inside r_c = 2.5 the pair force falls to zero linearly and the energy quadratically
+    in the distance d to r_c (so a pair whose distance rounds to either side of r_c changes
+    the force by O(d), not by a finite jump); at and beyond r_c both are exactly zero."""
+    if kind == "lj":
+        p = _pair_params(O)
+    else:
+        p = O.make_params(20, 0.8, n_atoms=2, coul_k=0.3, charges=np.array([0.7, -0.4]), lj_rc=2.5)
+    F1 = U1 = None
+    for d in (1e-2, 1e-3, 1e-4):
+        X = np.array([[5.0, 5.0, 5.0], [5.0, 5.0, 5.0 + 2.5 - d]])
+        F = np.abs(O.forces(p, X, X, E0)).max()
+        U = O.energy(p, X, X, E0)
+        assert F > 0
+        if F1 is not None:
+            # ten times closer: ten times less force, a hundred times less energy
+            assert abs(F1 / F - 10.0) < 0.2 and abs(U1 / U - 100.0) < 2.0, (d, F1 / F, U1 / U)
+        F1, U1 = F, U
+    for r in (2.5, 2.50001, 3.0):
+        X = np.array([[5.0, 5.0, 5.0], [5.0, 5.0, 5.0 + r]])
+        assert np.abs(O.forces(p, X, X, E0)).max() == 0.0 and O.energy(p, X, X, E0) == 0.0
 
 
 def test_minimum_image_and_bond_exclusion(O):
@@ -113,8 +143,10 @@ def test_lj_pair_count_brute_force(O, cluster):
         for j in np.nonzero((r2 < 2.5 ** 2) & (np.arange(len(X)) != i))[0]:
             if (i, int(j)) in bonded:
                 continue
+            # the force of the plain term minus its value at r_c, scaled by r / r_c
             dU_dr = 4 * 0.01 * (-12 / r2[j] ** 6.5 + 6 / r2[j] ** 3.5)
-            F[i] -= dU_dr * r[j] / np.sqrt(r2[j])
+            dU_dr_c = 4 * 0.01 * (-12 / 2.5 ** 13 + 6 / 2.5 ** 7)
+            F[i] -= dU_dr * r[j] / np.sqrt(r2[j]) - dU_dr_c * r[j] / 2.5
     np.testing.assert_allclose(O.forces(p, X, w.x0, w.bonds), F, rtol=1e-9, atol=1e-14)
 
 
@@ -140,17 +172,20 @@ def test_symplectic_euler_tethered_atom(O, k, m):
 # ---- implicit-solvent Coulomb (permittivity proportional to r): U = k_C q_i q_j / r^2 ----------
 
 def test_coulomb_implicit_pair_closed_form(O):
-    """Two charges: U = k q1 q2 / r^2 and F_1 = 2 k q1 q2 (X_1 - X_2) / r^4, off at r >= r_c."""
+    """Two charges with the cut-off far away (1e6, where the shift is below 1e-9 of the
+    energy and 1e-15 of the force): U = k q1 q2 / r^2 and F_1 = 2 k q1 q2 (X_1 - X_2) / r^4;
+    off at r >= r_c."""
     q = np.array([0.7, -0.4])
-    p = O.make_params(20, 0.8, n_atoms=2, coul_k=0.3, charges=q, lj_rc=2.5)
+    pf = O.make_params(20, 0.8, n_atoms=2, coul_k=0.3, charges=q, lj_rc=1.0e6)
     for r in (0.9, 1.7, 2.4):
         X = np.array([[5.0, 5.0, 5.0], [5.0, 5.0 + r, 5.0]])
-        U = O.energy(p, X, X, E0)
-        assert abs(U - 0.3 * 0.7 * -0.4 / r ** 2) < 1e-15
-        F = O.forces(p, X, X, E0)
+        U = O.energy(pf, X, X, E0)
+        assert abs(U - 0.3 * 0.7 * -0.4 / r ** 2) < 1e-9 * abs(U)
+        F = O.forces(pf, X, X, E0)
         want = 2 * 0.3 * 0.7 * -0.4 / r ** 4 * np.array([0.0, -r, 0.0])
-        np.testing.assert_allclose(F[0], want, rtol=1e-14, atol=1e-18)
-        np.testing.assert_allclose(F[1], -want, rtol=1e-14, atol=1e-18)
+        np.testing.assert_allclose(F[0], want, rtol=1e-11, atol=1e-18)
+        np.testing.assert_allclose(F[1], -want, rtol=1e-11, atol=1e-18)
+    p = O.make_params(20, 0.8, n_atoms=2, coul_k=0.3, charges=q, lj_rc=2.5)
     X = np.array([[5.0, 5.0, 5.0], [5.0, 5.0 + 2.6, 5.0]])
     assert O.energy(p, X, X, E0) == 0.0 and np.abs(O.forces(p, X, X, E0)).max() == 0.0
 

@@ -33,7 +33,7 @@ def _random_state(O, p, rng, amp=2e-3):
 
 
 def _case(kind, q, trt, kT, coul, bf):
-    rng = np.random.default_rng(hash((kind, q, trt, kT, coul, bf)) % 2 ** 32)
+    rng = np.random.default_rng([q, int(trt), int(kT), int(coul), bf, kind == "ball"])
     L = (13, 11, 12)
     if kind == "ball":
         w = small_workload(L, 60, seed=5, tau=0.7, gamma=0.3, k_tether=0.05, mass=4.0)
