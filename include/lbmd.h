@@ -197,6 +197,18 @@ lb_status lb_set_populations(lb_ctx* c, const float* g);
  * Synchronises the stream; returns LB_ENONFINITE / LB_EOVERFLOW if latched. */
 lb_status lb_invariants(lb_ctx* c, double out7[7]);
 
+/* For callers that cannot allocate device memory or wait on the stream (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the sums of lb_invariants,
+ * written to out7 [7] (device, FP64) asynchronously on the context's stream, with the
+ * reduction's per-workgroup partial sums in a fixed array of the library's own device memory
+ * instead of the workspace.  The array holds 1024 partial sums of 4 doubles (32 KiB) on every
+ * GPU the library runs on, until the process ends; each reduction workgroup loops over sites,
+ * so every lattice lb_init accepts fits (a context needing more partial sums would be rejected
+ * with LB_EINVAL).  Allocates nothing and does not synchronise.  All calls on one GPU share
+ * its array, and every call rewrites the part it reads: calls that overlap in time on one GPU
+ * (different streams) race.  Latched device-side conditions are left to lb_status_check. */
+lb_status lb_invariants_noalloc(lb_ctx* c, double* out7);
+
 /* Synchronise the stream and report any latched device-side condition. */
 lb_status lb_status_check(lb_ctx* c);
 

@@ -73,6 +73,7 @@ _SIGS = [
     ("lb_set_populations", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("lb_set_charges", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("lb_invariants", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    ("lb_invariants_noalloc", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("lb_status_check", ctypes.c_int, [ctypes.c_void_p]),
     ("lb_step_count", ctypes.c_int64, [ctypes.c_void_p]),
     ("lb_state_bytes", ctypes.c_size_t, [ctypes.c_void_p]),
@@ -175,6 +176,11 @@ def lb_invariants(ctx):
     out = (ctypes.c_double * 7)()
     _check(lib().lb_invariants(ctx, out), ctx)
     return list(out)
+
+
+def lb_invariants_noalloc(ctx, out7: int):
+    """Queue the 7 sums into the device buffer at out7 (FP64); asynchronous."""
+    _check(lib().lb_invariants_noalloc(ctx, out7 or None), ctx)
 
 
 def lb_status_check(ctx):

@@ -17,6 +17,7 @@
 // One thread per site, 256 sites per workgroup.  A workgroup is also the unit ("tile") of
 // the sparse atom force: tiles that atoms touched in this step carry a flag, and only their
 // sites read (and clear) the fixed-point coupling-force field.
+#include <mutex>
 #include <type_traits>
 
 #include "lattice_common.h"
@@ -458,6 +459,37 @@ hipError_t launch_write_populations(lb_ctx* c, const float* g) {
     hipLaunchKernelGGL((k_write<decltype(st)::value, decltype(q)::value>), grid, block, 0, c->stream, a);
   });
   return hipGetLastError();
+}
+
+// ---- scratch of lb_invariants_noalloc ---------------------------------------------------------
+// The per-workgroup partial sums of the FP64 reduction in a fixed array of the library's own
+// device memory, one copy on every GPU the library runs on, held until the process ends (its
+// size does not depend on the lattice: each reduction workgroup loops over sites).  In host
+// code the name `scratch` is a host-side stand-in, not a device address: every host use goes
+// through the address that setup_invariants_scratch() looks up once per device.
+static __device__ __align__(256) double scratch[kNoallocScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t setup_invariants_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = static_cast<double*>(p);
+  return hipSuccess;
+}
+
+double* invariants_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
 }
 
 int invariants_blocks(const lb_ctx* c) {

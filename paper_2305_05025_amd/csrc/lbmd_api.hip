@@ -280,9 +280,14 @@ lb_status lb_init(const lb_params* p, void* workspace, size_t workspace_bytes, c
     }
   }
 
+  int device = 0;
+  if ((e = hipGetDevice(&device)) != hipSuccess) return hip_fail(nullptr, e, "querying the device");
+  if ((e = setup_invariants_scratch(device)) != hipSuccess)
+    return hip_fail(nullptr, e, "looking up the reduction scratch on this device");
   lb_ctx* c = new (std::nothrow) lb_ctx();
   if (!c) return fail(nullptr, LB_ENOMEM, "host allocation failed");
   c->p = *p;
+  c->device = device;
   c->geo = g;
   c->lay = lay;
   c->stream = st;
@@ -535,6 +540,21 @@ lb_status lb_invariants(lb_ctx* c, double out7[7]) {
   if (e != hipSuccess) return hip_fail(c, e, "invariants read");
   for (int k = 0; k < 7; ++k) out7[k] = h[k];
   return lb_status_check(c);
+}
+
+lb_status lb_invariants_noalloc(lb_ctx* c, double* out7) {
+  if (!c) return fail(nullptr, LB_EINVAL, "context is NULL");
+  if (!out7) return fail(c, LB_EINVAL, "out7 is NULL");
+  double* part = invariants_scratch(c->device);
+  if (!part) return fail(c, LB_ESTATE, "the reduction scratch of this context's device is not set up");
+  if (invariants_blocks(c) * 4 > kNoallocScratchDoubles) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "the reduction needs %d partial sums, the fixed scratch holds %d",
+                  invariants_blocks(c), kNoallocScratchDoubles / 4);
+    return fail(c, LB_EINVAL, buf);
+  }
+  hipError_t e = launch_invariants(c, part, out7);
+  return e == hipSuccess ? LB_OK : hip_fail(c, e, "invariants launch");
 }
 
 int64_t lb_step_count(const lb_ctx* c) { return c ? c->step : -1; }

@@ -101,6 +101,8 @@ inline FastDiv make_fastdiv(uint32_t d) {
 }
 
 constexpr int kRedBlocks = 1024;
+// the fixed scratch of lb_invariants_noalloc: kRedBlocks partial sums of 4 doubles (32 KiB)
+constexpr int kNoallocScratchDoubles = kRedBlocks * 4;
 constexpr int kTimedEvents = 8;
 
 struct Geometry {
@@ -139,6 +141,7 @@ struct lb_ctx {
   lbmd::Geometry geo;
   lbmd::Layout lay;
   hipStream_t stream;
+  int device;       // the HIP device current at lb_init
   char* ws;
   char* popbuf[2];  // population buffers A / B (inside ws; the adjoint points them at its slots)
   float* couple_u = nullptr;  // when set, k_couple also stores U (the adjoint needs it)
@@ -171,6 +174,10 @@ hipError_t launch_write_populations(lb_ctx* c, const float* g);
 // doubles) into `partial`, the 7 results into `out` (device pointers)
 int invariants_blocks(const lb_ctx* c);
 hipError_t launch_invariants(lb_ctx* c, double* partial, double* out);
+// lb_invariants_noalloc's scratch: looked up once per device (with that device current),
+// then its device address on `device` (NULL before set-up)
+hipError_t setup_invariants_scratch(int device);
+double* invariants_scratch(int device);
 hipError_t launch_store_i64(void* dst, int64_t v, hipStream_t s);
 
 // ---- kernel launchers (atoms.hip) ----
