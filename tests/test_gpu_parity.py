@@ -119,18 +119,24 @@ def test_config0_without_lj_100_steps(O):
     assert max(r.values()) < 1e-5, r
 
 
-def test_config0_100_steps_within_chaotic_spread(O):
+def test_config0_100_steps(O):
+    """The ball workload (tethers, Lennard-Jones between all atoms) over 100 steps.  Its LJ
+    dynamics amplify rounding: the spread of the FP64 scheme itself under a one-ulp (2^-24
+    relative, random sign) change of the initial velocities is 2.1e-6 on v after 100 steps.
+    Gates: u, rho, g and the displacement within 1e-5; the velocity within 6 times that
+    spread (measured 9.9e-6, 4.7 times it; for seeds 10 and 11 of the same construction
+    9.4e-6 and 1.2e-5, so a flat 1e-5 on v does not hold for every seed)."""
     w = _c0()
     orc = oracle_run(O, w, 100)
-    # spread of the FP64 scheme itself under an FP32-sized perturbation of v0
     rng = np.random.default_rng(17)
     wp = _c0()
     wp.v0 = (w.v0.astype(np.float64) * (1 + 2.0 ** -24 * rng.choice([-1, 1], size=w.v0.shape)))
     spread = compare(oracle_run(O, wp, 100), orc, w)
     r = compare(gpu_run(w, 100), orc, w)
-    say("c0 100 gpu", r, "fp64 spread", spread)
-    for k in r:
-        assert r[k] < max(50 * spread[k], 1e-5), (k, r[k], spread[k])
+    say("c0 100 gpu", r, "fp64 one-ulp spread", spread)
+    for k in ("u", "rho", "g", "disp", "x"):
+        assert r[k] < 1e-5, (k, r[k])
+    assert r["v"] < 6.0 * spread["v"], (r["v"], spread["v"])
 
 
 # ------------------------------------------------------------------ coupled: globules
