@@ -87,6 +87,19 @@ typedef enum {
                                       bits.  For lattices of about 32^3 sites and below the
                                       step is bound by the host's launch and event calls,
                                       and this schedule (fewer calls) is the faster one */
+#define LB_FLAG_FUSED_COUPLING 0x4u /* couple in the sweep itself: every 16 x 4 x 4 brick of sites
+                                      that an atom stencil touches is updated by one workgroup
+                                      that first computes the coupling velocity on the brick and
+                                      its halo, the friction of the atoms there and their spread
+                                      force (staged in LDS), on a stream of its own beside the
+                                      sweep of the other sites.  Same bits as the default, which
+                                      runs the coupling as separate kernels before one sweep.  On
+                                      MI355X the default is faster from 96^3 sites up (256^3 with
+                                      200,000 atoms: 0.568 against 0.567 ms in FP32, 0.364 against
+                                      0.408 in FP16; 384^3 with 10^6 atoms 2.13 against 2.44);
+                                      this one for small lattices bound by the host's launch
+                                      rate (32^3 with 500 atoms: 0.080 against 0.088 ms).  Needs
+                                      lb_workspace_bytes() for these flags */
 
 typedef struct {
   int32_t L[3];              /* nx, ny, nz >= 2; periodic */

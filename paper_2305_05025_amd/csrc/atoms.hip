@@ -255,6 +255,83 @@ __global__ __launch_bounds__(256) void k_bin_mark(BinArgs a) {
 }
 
 // ------------------------------------------------------------------------------------------
+// Binning of the fused coupled sweep.  One thread per atom: the atom joins the list of every
+// brick that one of its 8 stencil nodes lies in (up to 8; a brick's list thus holds every atom
+// whose interpolation or spread touches the brick), and a record of it joins its
+// neighbour-list cell as in k_bin_mark.  List order comes from atomics; the hot-brick sweep
+// treats every listed atom on its own and sums the spread in integers, so results do not
+// depend on it.
+struct BrickBinArgs {
+  int N;
+  AtomGeo g;
+  int nb0, nb1;         // bricks along x and y
+  const float* x0;
+  const float* d;       // [2][N][3]: hi, lo
+  int* brick_count;
+  int* brick_list;      // [nbricks][kBrickCap]
+  int* cell_count;
+  int4* cell_rec;       // [ncell][kCellCap]
+  uint32_t* err;
+};
+
+__global__ __launch_bounds__(256) void k_brick_bin(BrickBinArgs a) {
+  const int i = xcd_block() * 256 + threadIdx.x;
+  if (i >= a.N) return;   // (lanes that leave are inactive in the ballots below)
+  int i0[3];
+  float fr[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    split(a.x0[3 * i + c], a.d[3 * i + c], a.d[3 * a.N + 3 * i + c], a.g.n[c], i0[c], fr[c]);
+  const int x1 = i0[0] + 1 == a.g.n[0] ? 0 : i0[0] + 1;
+  const int y1 = i0[1] + 1 == a.g.n[1] ? 0 : i0[1] + 1;
+  const int z1 = i0[2] + 1 == a.g.n[2] ? 0 : i0[2] + 1;
+  const int bx[2] = {i0[0] >> kBrickShiftX, x1 >> kBrickShiftX};
+  const int by[2] = {i0[1] >> kBrickShiftY, y1 >> kBrickShiftY};
+  const int bz[2] = {i0[2] >> kBrickShiftZ, z1 >> kBrickShiftZ};
+  // Neighbouring atoms (consecutive along a chain) mostly share bricks, so the lanes of a
+  // wavefront that append to the same brick reserve their slots with one atomic between them.
+  const unsigned long long below = (1ull << (threadIdx.x & 63)) - 1ull;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int dx = k & 1, dy = (k >> 1) & 1, dz = (k >> 2) & 1;
+    // each distinct brick of this atom once
+    const bool dup = (dx && bx[1] == bx[0]) || (dy && by[1] == by[0]) || (dz && bz[1] == bz[0]);
+    long b = dup ? -1 : bx[dx] + (long)a.nb0 * (by[dy] + (long)a.nb1 * bz[dz]);
+    while (__ballot(b >= 0) != 0ull) {
+      const unsigned long long act = __ballot(b >= 0);
+      const int leader = __ffsll((long long)act) - 1;
+      const long bl = __shfl(b, leader, 64);
+      const unsigned long long same = __ballot(b == bl);
+      int base = 0;
+      if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(a.brick_count + bl, __popcll(same));
+      base = __shfl(base, leader, 64);
+      if (b == bl) {
+        const int slot = base + __popcll(same & below);
+        if (slot < kBrickCap)
+          a.brick_list[bl * kBrickCap + slot] = i;
+        else
+          atomicOr(a.err, kErrOverflow);
+        b = -1;
+      }
+    }
+  }
+  if (a.g.nc[0] > 0) {
+    int q[3], P[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      q[c] = cell_of(i0[c], fr[c], a.g.inv_cw[c], a.g.nc[c]);
+      P[c] = cell_fixed(i0[c] - cell_origin(q[c], a.g.n[c], a.g.nc[c]), fr[c]);
+    }
+    const long cell = q[0] + (long)a.g.nc[0] * (q[1] + (long)a.g.nc[1] * q[2]);
+    const int slot = atomicAdd(a.cell_count + cell, 1);
+    if (slot < kCellCap)
+      a.cell_rec[cell * kCellCap + slot] = make_int4(P[0], P[1], P[2], i);
+    else
+      atomicOr(a.err, kErrOverflow);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 struct NodeArgs {
   const void* f;
   long plane;
@@ -915,6 +992,47 @@ hipError_t launch_compact(lb_ctx* c) {
   b.node_list = (int*)(c->ws + c->lay.node_list[c->step & 1]);
   b.occ_count = a.occ_count;
   hipLaunchKernelGGL(k_node_compact, dim3(1024), dim3(256), 0, c->astream, b);
+  return hipGetLastError();
+}
+
+// clear the counts, bin, then list the occupied cells and the hot bricks (whose count is kept
+// where the old path keeps its flagged-tile count, occ_count[1])
+hipError_t launch_brick_binning(lb_ctx* c) {
+  const int par = (int)(c->step & 1);
+  PrepArgs p;
+  p.cell_count = (int*)(c->ws + c->lay.cell_count);
+  p.ncell = c->geo.ncell;
+  p.tile_flag = (uint32_t*)(c->ws + c->lay.brick_count[par]);
+  p.ntiles = (int)c->geo.nbricks;
+  p.occ_count = (int*)(c->ws + c->lay.occ_count[par]);
+  const long n = p.ncell > p.ntiles ? p.ncell : p.ntiles;
+  hipLaunchKernelGGL(k_prep, dim3(blocks(n, 256)), dim3(256), 0, c->astream, p);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  BrickBinArgs b;
+  b.N = c->p.n_atoms;
+  b.g = atom_geo(c);
+  b.nb0 = c->geo.nb[0];
+  b.nb1 = c->geo.nb[1];
+  b.x0 = (const float*)(c->ws + c->lay.x0);
+  b.d = (const float*)(c->ws + c->lay.disp[c->dcur]);
+  b.brick_count = (int*)(c->ws + c->lay.brick_count[par]);
+  b.brick_list = (int*)(c->ws + c->lay.brick_list[par]);
+  b.cell_count = p.cell_count;
+  b.cell_rec = (int4*)(c->ws + c->lay.cell_rec);
+  b.err = (uint32_t*)(c->ws + c->lay.err);
+  hipLaunchKernelGGL(k_brick_bin, dim3(blocks8(b.N, 256)), dim3(256), 0, c->astream, b);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  CompactArgs a;
+  a.cell_count = p.cell_count;
+  a.ncell = c->geo.ncell;
+  a.occ_cells = (int*)(c->ws + c->lay.occ_cells);
+  a.tile_flag = (const uint32_t*)b.brick_count;
+  a.ntiles = (int)c->geo.nbricks;
+  a.occ_tiles = (int*)(c->ws + c->lay.hot_bricks[par]);
+  a.occ_count = p.occ_count;
+  const long nb = (a.ncell + 255) / 256 + (a.ntiles + 255) / 256;
+  hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(256), 0, c->astream, a);
   return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@
 #include <mutex>
 #include <type_traits>
 
-#include "lattice_common.h"
+#include "atoms_common.h"
 
 namespace lbmd {
 namespace {
@@ -46,28 +46,22 @@ struct SweepArgs {
   int narrow;                  // planes take 32-bit byte offsets
 };
 
-// Q velocities (19 or 27)
+// The update of site s = (x, y, z): pull its pre-collision values, add the coupling force
+// (Fcx, Fcy, Fcz) to the external force density when `coupled`, collide (BGK or two relaxation
+// times, Guo forcing), add the thermal noise, store.  Q velocities (19 or 27).
 template <int ST, bool NOISE, bool TRT, int Q>
-__device__ __forceinline__ void sweep_site(const SweepArgs& a, int s, bool hot) {
+__device__ __forceinline__ void update_site(const SweepArgs& a, int s, int x, int y, int z,
+                                            bool coupled, float Fcx, float Fcy, float Fcz) {
   using T = typename Store<ST>::T;
-  int x, y, z;
-  site_xyz(s, a.nx, a.ny, a.dnx, a.dny, x, y, z);
   float g[Q];
   gather<ST, Q>(reinterpret_cast<const T*>(a.fin), a.plane, x, y, z, a.nx, a.ny, a.nz,
                 a.narrow != 0, g);
   float Fx, Fy, Fz;
   external_force(a.bf_kind, a.fext_tab, a.fext_field, a.plane, s, y, Fx, Fy, Fz);
-  if (hot) {
-    // atoms touched this 64-site tile: add their spread force and leave the per-step
-    // atom-side buffers clear for the next step
-    float* fc = a.fcoup;
-    Fx += fc[s];
-    Fy += fc[a.plane + s];
-    Fz += fc[2 * a.plane + s];
-    fc[s] = 0.f;
-    fc[a.plane + s] = 0.f;
-    fc[2 * a.plane + s] = 0.f;
-    a.base_count[s] = 0;
+  if (coupled) {
+    Fx += Fcx;
+    Fy += Fcy;
+    Fz += Fcz;
   }
   float rho = 0.f;
   if constexpr (NOISE) {
@@ -98,6 +92,27 @@ __device__ __forceinline__ void sweep_site(const SweepArgs& a, int s, bool hot) 
   }
 }
 
+// Q velocities (19 or 27)
+template <int ST, bool NOISE, bool TRT, int Q>
+__device__ __forceinline__ void sweep_site(const SweepArgs& a, int s, bool hot) {
+  int x, y, z;
+  site_xyz(s, a.nx, a.ny, a.dnx, a.dny, x, y, z);
+  float Fcx = 0.f, Fcy = 0.f, Fcz = 0.f;
+  if (hot) {
+    // atoms touched this 64-site tile: add their spread force and leave the per-step
+    // atom-side buffers clear for the next step
+    float* fc = a.fcoup;
+    Fcx = fc[s];
+    Fcy = fc[a.plane + s];
+    Fcz = fc[2 * a.plane + s];
+    fc[s] = 0.f;
+    fc[a.plane + s] = 0.f;
+    fc[2 * a.plane + s] = 0.f;
+    a.base_count[s] = 0;
+  }
+  update_site<ST, NOISE, TRT, Q>(a, s, x, y, z, hot, Fcx, Fcy, Fcz);
+}
+
 // One thread per site, in site order.  The instances without noise are held to 64 VGPRs (8
 // wavefronts per SIMD) except the D3Q27 TRT one, which would spill there.
 template <int ST, bool NOISE, bool TRT, int Q>
@@ -107,6 +122,191 @@ __attribute__((amdgpu_waves_per_eu(NOISE || (TRT && Q == 27) ? 1 : 8))) void k_s
   if (s >= a.S) return;
   const bool hot = a.tile_flag != nullptr && a.tile_flag[s >> kTileShift] != 0u;
   sweep_site<ST, NOISE, TRT, Q>(a, s, hot);
+}
+
+// ---- the coupled sweep, fused -------------------------------------------------------------------
+// The lattice is cut into bricks of 16 x 4 x 4 sites.  A hot brick (one that some atom's stencil
+// touches) is handled by one workgroup, which does the whole coupling of Section 2.2 for it
+// before updating its sites:
+//   1. the atoms listed for the brick mark their 8 stencil nodes, which lie in the brick and a
+//      one-node halo around it (18 x 6 x 6 nodes);
+//   2. the coupling velocity u_c = (j + F_ext/2)/rho of the pre-collision state at every marked
+//      node, pulled from the stored populations, into LDS;
+//   3. per listed atom: U = trilinear interpolation of u_c at X^n, F_c = gamma (U - v); the
+//      workgroup of the brick holding the atom's stencil base stores F_c for the integration;
+//      -W F_c is added to the brick's own stencil nodes in an LDS force tile, in 2^-40 fixed
+//      point (integer sums do not depend on the order of their terms);
+//   4. every site of the brick: collision with F = F_ext + spread force, streaming, store.
+// An atom near a brick face is listed in each brick its stencil reaches, and its F_c is then
+// computed by each of them with the same instructions on the same values.  The arithmetic of
+// u_c, U (summed over the corners in the order (0+1)+(2+3), (4+5)+(6+7), then the two halves),
+// F_c and the spread is that of k_node_u, k_couple and k_spread, so the results are the same
+// bits as the unfused kernels'.  The remaining sites are swept by k_sweep_cold.
+struct HotArgs {
+  int nb0, nb1;            // bricks along x and y
+  const int* hot;          // the hot bricks, compacted
+  const int* nhot;         // their number
+  const int* brick_count;
+  const int* brick_list;   // [nbricks][kBrickCap]
+  int N;
+  const float* x0;
+  const float* d;          // [2][N][3]: hi, lo
+  const float* v;          // [2][N][3]: hi, lo
+  float gamma;
+  float* fc;               // out: friction force on each atom
+};
+
+constexpr int kHotAtomsPerThread = (kBrickCap + kSweepBlock - 1) / kSweepBlock;
+
+__device__ __forceinline__ int wrap_once(int r, int n) {
+  r = r < 0 ? r + n : r;
+  return r >= n ? r - n : r;
+}
+
+template <int ST, bool NOISE, bool TRT, int Q>
+__global__ __launch_bounds__(kSweepBlock) void k_hot_sweep(SweepArgs a, HotArgs h) {
+  using T = typename Store<ST>::T;
+  __shared__ float ucx[kHaloNodes], ucy[kHaloNodes], ucz[kHaloNodes];
+  __shared__ unsigned char need[kHaloNodes];
+  __shared__ long long fsx[kSweepBlock], fsy[kSweepBlock], fsz[kSweepBlock];
+  const int t = threadIdx.x;
+  const int nhot = *h.nhot;
+  // XCD x takes the x-th contiguous eighth of the list: neighbouring hot bricks share halo
+  // nodes, which then meet in that XCD's L2 (the grid is a multiple of 8 workgroups)
+  const int chunk = (nhot + 7) >> 3;
+  const int k0 = (int)(blockIdx.x & 7u) * chunk, k1 = min(k0 + chunk, nhot);
+  for (int k = k0 + (int)(blockIdx.x >> 3); k < k1; k += (int)(gridDim.x >> 3)) {
+    const int b = h.hot[k];
+    const int bx = b % h.nb0, byz = b / h.nb0;
+    const int by = byz % h.nb1, bz = byz / h.nb1;
+    const int ox = bx * kBrickX, oy = by * kBrickY, oz = bz * kBrickZ;   // brick origin
+    for (int q = t; q < kHaloNodes; q += kSweepBlock) need[q] = 0;
+    fsx[t] = 0;
+    fsy[t] = 0;
+    fsz[t] = 0;
+    __syncthreads();
+    // 1. listed atoms: stencil base relative to the halo's lower corner (ox - 1, oy - 1, oz - 1),
+    //    wrapped once into the lattice.  The list holds the atoms whose stencil reaches the
+    //    brick, so their relative base is at most 16, 4, 4 along x, y, z, and every node index
+    //    below stays within the halo (and within the lattice after one wrap).
+    const int na = min(h.brick_count[b], kBrickCap);
+    int at[kHotAtomsPerThread], rel[kHotAtomsPerThread];
+    float frs[kHotAtomsPerThread][3];
+#pragma unroll
+    for (int j = 0; j < kHotAtomsPerThread; ++j) {
+      const int slot = t + j * kSweepBlock;
+      at[j] = slot < na ? h.brick_list[(long)b * kBrickCap + slot] : -1;
+    }
+#pragma unroll
+    for (int j = 0; j < kHotAtomsPerThread; ++j) {
+      rel[j] = 0;
+      frs[j][0] = frs[j][1] = frs[j][2] = 0.f;
+      if (at[j] < 0) continue;
+      const int i = at[j];
+      int i0[3];
+      split(h.x0[3 * i], h.d[3 * i], h.d[3 * h.N + 3 * i], a.nx, i0[0], frs[j][0]);
+      split(h.x0[3 * i + 1], h.d[3 * i + 1], h.d[3 * h.N + 3 * i + 1], a.ny, i0[1], frs[j][1]);
+      split(h.x0[3 * i + 2], h.d[3 * i + 2], h.d[3 * h.N + 3 * i + 2], a.nz, i0[2], frs[j][2]);
+      const int rx = wrap_once(i0[0] - ox + 1, a.nx);
+      const int ry = wrap_once(i0[1] - oy + 1, a.ny);
+      const int rz = wrap_once(i0[2] - oz + 1, a.nz);
+      rel[j] = rx + kHaloX * (ry + kHaloY * rz);
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        need[rel[j] + (c & 1) + kHaloX * (((c >> 1) & 1) + kHaloY * ((c >> 2) & 1))] = 1;
+    }
+    __syncthreads();
+    // 2. u_c at the marked halo nodes
+    for (int q = t; q < kHaloNodes; q += kSweepBlock) {
+      if (!need[q]) continue;
+      const int hx = q % kHaloX, hyz = q / kHaloX;
+      const int x = wrap_once(ox - 1 + hx, a.nx);
+      const int y = wrap_once(oy - 1 + hyz % kHaloY, a.ny);
+      const int z = wrap_once(oz - 1 + hyz / kHaloY, a.nz);
+      const int s = x + a.nx * (y + a.ny * z);
+      float g[Q];
+      gather<ST, Q>(reinterpret_cast<const T*>(a.fin), a.plane, x, y, z, a.nx, a.ny, a.nz,
+                    a.narrow != 0, g);
+      float drho, jx, jy, jz, Fx, Fy, Fz;
+      moments<Q>(g, drho, jx, jy, jz);
+      external_force(a.bf_kind, a.fext_tab, a.fext_field, a.plane, s, y, Fx, Fy, Fz);
+      const float inv = 1.0f / (a.rho0 + drho);
+      ucx[q] = (jx + 0.5f * Fx) * inv;
+      ucy[q] = (jy + 0.5f * Fy) * inv;
+      ucz[q] = (jz + 0.5f * Fz) * inv;
+    }
+    __syncthreads();
+    // 3. friction of each listed atom; its spread onto this brick's nodes
+#pragma unroll
+    for (int j = 0; j < kHotAtomsPerThread; ++j) {
+      if (at[j] < 0) continue;
+      const int i = at[j];
+      float wk[8], ux[8], uy[8], uz[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
+        wk[c] = (dx ? frs[j][0] : 1.0f - frs[j][0]) * (dy ? frs[j][1] : 1.0f - frs[j][1]) *
+                (dz ? frs[j][2] : 1.0f - frs[j][2]);
+        const int q = rel[j] + dx + kHaloX * (dy + kHaloY * dz);
+        ux[c] = wk[c] * ucx[q];
+        uy[c] = wk[c] * ucy[q];
+        uz[c] = wk[c] * ucz[q];
+      }
+      const float Ux = ((ux[0] + ux[1]) + (ux[2] + ux[3])) + ((ux[4] + ux[5]) + (ux[6] + ux[7]));
+      const float Uy = ((uy[0] + uy[1]) + (uy[2] + uy[3])) + ((uy[4] + uy[5]) + (uy[6] + uy[7]));
+      const float Uz = ((uz[0] + uz[1]) + (uz[2] + uz[3])) + ((uz[4] + uz[5]) + (uz[6] + uz[7]));
+      const float* vlo = h.v + 3 * h.N;
+      const float fx = h.gamma * ((Ux - h.v[3 * i]) - vlo[3 * i]);
+      const float fy = h.gamma * ((Uy - h.v[3 * i + 1]) - vlo[3 * i + 1]);
+      const float fz = h.gamma * ((Uz - h.v[3 * i + 2]) - vlo[3 * i + 2]);
+      const int rx = rel[j] % kHaloX, ryz = rel[j] / kHaloX;
+      const int ry = ryz % kHaloY, rz = ryz / kHaloY;
+      // stencil base node and its brick: that brick's workgroup stores F_c
+      const int b0x = wrap_once(ox - 1 + rx, a.nx), b0y = wrap_once(oy - 1 + ry, a.ny),
+                b0z = wrap_once(oz - 1 + rz, a.nz);
+      if ((b0x >> kBrickShiftX) == bx && (b0y >> kBrickShiftY) == by && (b0z >> kBrickShiftZ) == bz) {
+        h.fc[3 * i] = fx;
+        h.fc[3 * i + 1] = fy;
+        h.fc[3 * i + 2] = fz;
+      }
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
+        const int lx = wrap_once(b0x + dx, a.nx) - ox;
+        const int ly = wrap_once(b0y + dy, a.ny) - oy;
+        const int lz = wrap_once(b0z + dz, a.nz) - oz;
+        if (lx < 0 || lx >= kBrickX || ly < 0 || ly >= kBrickY || lz < 0 || lz >= kBrickZ) continue;
+        const int l = lx + kBrickX * (ly + kBrickY * lz);
+        atomicAdd(reinterpret_cast<unsigned long long*>(&fsx[l]), (unsigned long long)to_fixed(-wk[c] * fx, kFixScale));
+        atomicAdd(reinterpret_cast<unsigned long long*>(&fsy[l]), (unsigned long long)to_fixed(-wk[c] * fy, kFixScale));
+        atomicAdd(reinterpret_cast<unsigned long long*>(&fsz[l]), (unsigned long long)to_fixed(-wk[c] * fz, kFixScale));
+      }
+    }
+    __syncthreads();
+    // 4. the brick's sites
+    const int x = ox + (t & (kBrickX - 1));
+    const int y = oy + ((t >> kBrickShiftX) & (kBrickY - 1));
+    const int z = oz + (t >> (kBrickShiftX + kBrickShiftY));
+    if (x < a.nx && y < a.ny && z < a.nz)
+      update_site<ST, NOISE, TRT, Q>(a, x + a.nx * (y + a.ny * z), x, y, z, true,
+                                     (float)fsx[t] * kFixInv, (float)fsy[t] * kFixInv,
+                                     (float)fsz[t] * kFixInv);
+    __syncthreads();   // LDS is reused by the next brick
+  }
+}
+
+// Every site outside the hot bricks: the plain stream-and-collide update.
+template <int ST, bool NOISE, bool TRT, int Q>
+__global__ __launch_bounds__(kSweepBlock)
+__attribute__((amdgpu_waves_per_eu(NOISE || (TRT && Q == 27) ? 1 : 8))) void k_sweep_cold(
+    SweepArgs a, const int* brick_count, int nb0, int nb1) {
+  const int s = blockIdx.x * kSweepBlock + threadIdx.x;
+  if (s >= a.S) return;
+  int x, y, z;
+  site_xyz(s, a.nx, a.ny, a.dnx, a.dny, x, y, z);
+  if (brick_count[(x >> kBrickShiftX) + nb0 * ((y >> kBrickShiftY) + nb1 * (z >> kBrickShiftZ))] != 0)
+    return;
+  update_site<ST, NOISE, TRT, Q>(a, s, x, y, z, false, 0.f, 0.f, 0.f);
 }
 
 template <int ST>
@@ -414,6 +614,101 @@ hipError_t launch_sweep(lb_ctx* c, const void* fin, void* fout, hipStream_t st) 
     case LB_STORE_F16: launch_sweep_st<LB_STORE_F16>(g.q, noise, trt, grid, block, st, a); break;
     default: launch_sweep_st<LB_STORE_BF16>(g.q, noise, trt, grid, block, st, a); break;
   }
+  return hipGetLastError();
+}
+
+namespace {
+
+// Launch K<storage, noise, two relaxation times, Q> for the context's parameters.
+template <class F>
+void dispatch_sweep(const lb_ctx* c, F&& launch) {
+  using std::integral_constant;
+  const bool noise = c->p.kT > 0.0f, trt = c->p.trt_magic > 0.0f;
+  dispatch_store_q(c, [&](auto st, auto q) {
+    if (noise && trt) launch(st, integral_constant<bool, true>{}, integral_constant<bool, true>{}, q);
+    else if (noise) launch(st, integral_constant<bool, true>{}, integral_constant<bool, false>{}, q);
+    else if (trt) launch(st, integral_constant<bool, false>{}, integral_constant<bool, true>{}, q);
+    else launch(st, integral_constant<bool, false>{}, integral_constant<bool, false>{}, q);
+  });
+}
+
+SweepArgs sweep_args(lb_ctx* c, const void* fin, void* fout) {
+  const Geometry& g = c->geo;
+  SweepArgs a;
+  a.fin = fin;
+  a.fout = fout;
+  a.plane = g.plane;
+  a.nx = g.nx;
+  a.ny = g.ny;
+  a.nz = g.nz;
+  a.S = (int)g.S;
+  a.rho0 = c->p.rho0;
+  a.omega = c->omega;
+  a.pref = 1.0f - 0.5f * c->omega;
+  a.bf_kind = c->p.bf_kind;
+  a.fext_tab = (const float*)(c->ws + c->lay.fext_tab);
+  a.fext_field = (const float*)(c->ws + c->lay.fext_field);
+  a.tile_flag = nullptr;
+  a.fcoup = nullptr;
+  a.base_count = nullptr;
+  a.err = (uint32_t*)(c->ws + c->lay.err);
+  a.kT = c->p.kT;
+  a.seed0 = c->p.seed[0];
+  a.seed1 = c->p.seed[1];
+  a.step = c->step;
+  a.omega_m = c->omega_m;
+  a.dnx = g.div_nx;
+  a.dny = g.div_ny;
+  a.narrow = g.narrow ? 1 : 0;
+  return a;
+}
+
+}  // namespace
+
+// Workgroups of the hot-brick sweep: persistent over the list of hot bricks (at most one per
+// brick and eight per atom), a multiple of 8, at most 2048 (eight per CU).
+static unsigned hot_grid(const lb_ctx* c) {
+  long n = std::min(c->geo.nbricks, 8L * c->p.n_atoms);
+  if (n > 2048) n = 2048;
+  return (unsigned)((std::max(n, 8L) + 7) & ~7L);
+}
+
+hipError_t launch_hot_sweep(lb_ctx* c, const void* fin, void* fout, hipStream_t st) {
+  const SweepArgs a = sweep_args(c, fin, fout);
+  const int par = (int)(c->step & 1);
+  HotArgs h;
+  h.nb0 = c->geo.nb[0];
+  h.nb1 = c->geo.nb[1];
+  h.hot = (const int*)(c->ws + c->lay.hot_bricks[par]);
+  h.nhot = (const int*)(c->ws + c->lay.occ_count[par]) + 1;
+  h.brick_count = (const int*)(c->ws + c->lay.brick_count[par]);
+  h.brick_list = (const int*)(c->ws + c->lay.brick_list[par]);
+  h.N = c->p.n_atoms;
+  h.x0 = (const float*)(c->ws + c->lay.x0);
+  h.d = (const float*)(c->ws + c->lay.disp[c->dcur]);
+  h.v = (const float*)(c->ws + c->lay.vel);
+  h.gamma = c->p.gamma;
+  h.fc = (float*)(c->ws + c->lay.fc);
+  const dim3 grid(hot_grid(c)), block(kSweepBlock);
+  dispatch_sweep(c, [&](auto st_, auto nz, auto tr, auto q) {
+    hipLaunchKernelGGL((k_hot_sweep<decltype(st_)::value, decltype(nz)::value, decltype(tr)::value,
+                                    decltype(q)::value>),
+                       grid, block, 0, st, a, h);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_cold_sweep(lb_ctx* c, const void* fin, void* fout, hipStream_t st) {
+  const SweepArgs a = sweep_args(c, fin, fout);
+  const int par = (int)(c->step & 1);
+  const int* bc = (const int*)(c->ws + c->lay.brick_count[par]);
+  const int nb0 = c->geo.nb[0], nb1 = c->geo.nb[1];
+  const dim3 grid(c->geo.nblocks), block(kSweepBlock);
+  dispatch_sweep(c, [&](auto st_, auto nz, auto tr, auto q) {
+    hipLaunchKernelGGL((k_sweep_cold<decltype(st_)::value, decltype(nz)::value, decltype(tr)::value,
+                                     decltype(q)::value>),
+                       grid, block, 0, st, a, bc, nb0, nb1);
+  });
   return hipGetLastError();
 }
 

@@ -26,6 +26,10 @@ bool geometry(const lb_params* p, Geometry* g) {
   g->plane = (long)round_up((size_t)g->S, 64) + kPlanePad;
   g->nblocks = (int)((g->S + kSweepBlock - 1) / kSweepBlock);
   g->ntiles = (int)((g->S + 63) / 64);
+  g->nb[0] = (g->nx + kBrickX - 1) / kBrickX;
+  g->nb[1] = (g->ny + kBrickY - 1) / kBrickY;
+  g->nb[2] = (g->nz + kBrickZ - 1) / kBrickZ;
+  g->nbricks = (long)g->nb[0] * g->nb[1] * g->nb[2];
   g->elem = elem_bytes(p->storage);
   g->div_nx = make_fastdiv((uint32_t)g->nx);
   g->div_ny = make_fastdiv((uint32_t)g->ny);
@@ -34,6 +38,7 @@ bool geometry(const lb_params* p, Geometry* g) {
   const double sweep_bytes = (double)g->S * 2.0 * g->q * (double)g->elem;
   g->late_forces = std::getenv("LBMD_LATE_FORCES") != nullptr ||
                    (g->S >= (1L << 23) && sweep_bytes >= 7168.0 * (double)p->n_atoms);
+  g->fused = (p->flags & LB_FLAG_FUSED_COUPLING) != 0 && p->n_atoms > 0;
   g->ncell = 0;
   for (int k = 0; k < 3; ++k) {
     g->nc[k] = 0;
@@ -78,6 +83,9 @@ Layout plan(const lb_params* p, const Geometry& g) {
     l.occ_tiles[k] = take(N ? (size_t)g.ntiles * 4 : 0);
     l.node_list[k] = take(std::min(8 * N, (size_t)g.S) * 4);
     l.occ_count[k] = take(N ? 16 : 0);
+    l.brick_count[k] = take(g.fused ? (size_t)g.nbricks * 4 : 0);
+    l.brick_list[k] = take(g.fused ? (size_t)g.nbricks * kBrickCap * 4 : 0);
+    l.hot_bricks[k] = take(g.fused ? (size_t)g.nbricks * 4 : 0);
   }
   l.fext_tab = take((size_t)g.ny * 4);
   l.fext_field = take(p->bf_kind == LB_BF_FIELD ? 3 * (size_t)g.plane * 4 : 0);
@@ -114,7 +122,7 @@ static std::string validate(const lb_params* p) {
   const double S = (double)p->L[0] * p->L[1] * p->L[2];
   if (S > 2147483647.0) return "lattice has more than 2^31 - 1 sites";
   if (!finite(p->tau) || !(p->tau > 0.5f)) return "tau must be finite and > 0.5 (nu = (tau - 1/2)/3 > 0)";
-  if (p->flags & ~(LB_FLAG_CHECK_FINITE | LB_FLAG_SINGLE_STREAM))
+  if (p->flags & ~(LB_FLAG_CHECK_FINITE | LB_FLAG_SINGLE_STREAM | LB_FLAG_FUSED_COUPLING))
     return "flags holds an unknown bit";
   if (!finite(p->kT) || p->kT < 0.0f) return "kT must be finite and >= 0";
   if (!finite(p->trt_magic) || p->trt_magic < 0.0f) return "trt_magic must be finite and >= 0";
@@ -362,8 +370,110 @@ lb_status lb_init(const lb_params* p, void* workspace, size_t workspace_bytes, c
       lb_destroy(c);
       return hip_fail(nullptr, e, "creating the atom stream");
     }
+    if (g.fused)
+      for (int k = 0; k < 2 && e == hipSuccess; ++k)
+        if ((k == 0 && (e = hipStreamCreateWithFlags(&c->hstream, hipStreamNonBlocking)) != hipSuccess) ||
+            (e = hipEventCreateWithFlags(&c->ev_hot[k], dev_ev)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&c->ev_cold[k], dev_ev)) != hipSuccess) {
+          lb_destroy(c);
+          return hip_fail(nullptr, e, "creating the hot-brick stream");
+        }
   }
   *out = c;
+  return LB_OK;
+}
+
+// The fused step.  Three streams: the caller's ("cold"), "hot" and "atoms".  Step n:
+//   hot:    wait ev_bin(n) and ev_cold(n - 1); hot-brick sweep (coupling of step n, update of the
+//           hot bricks' sites) -> ev_hot(n)
+//   cold:   wait ev_bin(n) and ev_hot(n - 1); sweep of every other site -> ev_cold(n)
+//   atoms:  (binning, cell sort and force field at X^n done) wait ev_hot(n); integration with
+//           the friction of step n; then, for step n + 1: binning -> ev_bin(n + 1), cell sort,
+//           force field at X^{n+1}
+// The two sweeps of a step read the populations of step n and write disjoint sites of step
+// n + 1, so they run side by side; the hot sweep of step n + 1 reads the halo of its bricks,
+// written by both sweeps of step n, and the cold sweep of step n + 1 overwrites the buffer the
+// hot sweep of step n reads.  The integration and the next step's binning, cell sort and force
+// field overlap the cold sweep.  Per-step buffers written by the binning are double-buffered by
+// step parity, so the sweeps of step n (which read step n's brick lists and counts) and the
+// binning of step n + 1 never share one.  With LB_FLAG_SINGLE_STREAM every launch goes to the
+// caller's stream: binning, cell sort, force field, hot bricks, the rest, integration.
+static lb_status couple_step_fused(lb_ctx* c, int32_t n_steps) {
+  const bool multi = c->astream != c->stream;
+  hipStream_t hs = multi ? c->hstream : c->stream;
+  hipError_t e;
+  auto rec = [&](hipEvent_t* ev, int k, hipStream_t st) {
+    if (ev) (void)hipEventRecord(ev[k], st);
+  };
+  auto slot = [&]() -> hipEvent_t* {
+    return c->timed < c->timed_cap ? &c->ev[kTimedEvents * (size_t)c->timed] : nullptr;
+  };
+  // binning of the current step, its cell sort and the force field at its positions, on the
+  // atom stream
+  auto atom_prologue = [&](hipEvent_t* ev) -> lb_status {
+    rec(ev, 4, c->astream);
+    if ((e = launch_brick_binning(c)) != hipSuccess) return hip_fail(c, e, "binning launch");
+    rec(ev, 5, c->astream);
+    if (multi && (e = hipEventRecord(c->ev_bin, c->astream)) != hipSuccess) return hip_fail(c, e, "binning event");
+    if (c->geo.ncell > 0 && (e = launch_cell_sort(c)) != hipSuccess) return hip_fail(c, e, "cell sort launch");
+    rec(ev, 6, c->astream);
+    if ((e = launch_forces(c)) != hipSuccess) return hip_fail(c, e, "force launch");
+    rec(ev, 7, c->astream);
+    return LB_OK;
+  };
+  if (multi) {
+    if ((e = hipEventRecord(c->ev_fork, c->stream)) != hipSuccess ||
+        (e = hipStreamWaitEvent(c->astream, c->ev_fork, 0)) != hipSuccess ||
+        (e = hipStreamWaitEvent(hs, c->ev_fork, 0)) != hipSuccess)
+      return hip_fail(c, e, "stream fork");
+  }
+  lb_status st;
+  hipEvent_t* ev = slot();
+  if (ev) c->timed++;
+  if ((st = atom_prologue(ev)) != LB_OK) return st;
+  for (int n = 0; n < n_steps; ++n) {
+    void* fin = c->popbuf[c->cur];
+    void* fout = c->popbuf[c->cur ^ 1];
+    const int par = (int)(c->step & 1);
+    if (multi && ((e = hipStreamWaitEvent(hs, c->ev_bin, 0)) != hipSuccess ||
+                  (n > 0 && (e = hipStreamWaitEvent(hs, c->ev_cold[par ^ 1], 0)) != hipSuccess)))
+      return hip_fail(c, e, "hot sweep wait");
+    rec(ev, 0, hs);
+    if ((e = launch_hot_sweep(c, fin, fout, hs)) != hipSuccess) return hip_fail(c, e, "hot sweep launch");
+    rec(ev, 1, hs);
+    if (multi && (e = hipEventRecord(c->ev_hot[par], hs)) != hipSuccess) return hip_fail(c, e, "hot sweep event");
+    // the cold sweep skips the bricks this step's binning marked hot
+    if (multi && ((e = hipStreamWaitEvent(c->stream, c->ev_bin, 0)) != hipSuccess ||
+                  (n > 0 && (e = hipStreamWaitEvent(c->stream, c->ev_hot[par ^ 1], 0)) != hipSuccess)))
+      return hip_fail(c, e, "cold sweep wait");
+    rec(ev, 2, c->stream);
+    if ((e = launch_cold_sweep(c, fin, fout, c->stream)) != hipSuccess) return hip_fail(c, e, "sweep launch");
+    rec(ev, 3, c->stream);
+    if (multi && (e = hipEventRecord(c->ev_cold[par], c->stream)) != hipSuccess) return hip_fail(c, e, "cold sweep event");
+    if (multi && (e = hipStreamWaitEvent(c->astream, c->ev_hot[par], 0)) != hipSuccess)
+      return hip_fail(c, e, "coupling wait");
+    if ((e = launch_integrate(c)) != hipSuccess) return hip_fail(c, e, "integration launch");
+    c->cur ^= 1;
+    c->dcur ^= 1;
+    c->step++;
+    if (n + 1 < n_steps) {
+      ev = slot();
+      if (ev) c->timed++;
+      if ((st = atom_prologue(ev)) != LB_OK) return st;
+    }
+    if (c->p.flags & LB_FLAG_CHECK_FINITE) {
+      if (multi && ((e = hipEventRecord(c->ev_join, c->astream)) != hipSuccess ||
+                    (e = hipStreamWaitEvent(c->stream, c->ev_join, 0)) != hipSuccess))
+        return hip_fail(c, e, "stream join");
+      if ((st = lb_status_check(c)) != LB_OK) return st;
+    }
+  }
+  if (multi) {
+    // the atom stream has waited for the last hot sweep; the cold stream joins it
+    if ((e = hipEventRecord(c->ev_join, c->astream)) != hipSuccess ||
+        (e = hipStreamWaitEvent(c->stream, c->ev_join, 0)) != hipSuccess)
+      return hip_fail(c, e, "stream join");
+  }
   return LB_OK;
 }
 
@@ -372,6 +482,7 @@ lb_status lb_couple_step(lb_ctx* c, int32_t n_steps) {
   if (n_steps < 0) return fail(c, LB_EINVAL, "n_steps must be >= 0");
   if (n_steps == 0) return LB_OK;
   const bool atoms = c->p.n_atoms > 0;
+  if (atoms && c->geo.fused) return couple_step_fused(c, n_steps);
   hipError_t e;
   // Two streams (the caller's "main" stream and "atoms").  Step n:
   //   main:   wait ev_bin(n); node u_c, couple (-> ev_couple); spread -> ev_spread; sweep
@@ -862,12 +973,13 @@ restore:
 lb_status lb_destroy(lb_ctx* c) {
   if (!c) return fail(nullptr, LB_EINVAL, "context is NULL");
   free_events(c);
-  for (hipStream_t s : {c->astream})
+  for (hipStream_t s : {c->astream, c->hstream})
     if (s && s != c->stream) {
       (void)hipStreamSynchronize(s);
       (void)hipStreamDestroy(s);
     }
-  for (hipEvent_t e : {c->ev_fork, c->ev_bin, c->ev_couple, c->ev_spread, c->ev_join})
+  for (hipEvent_t e : {c->ev_fork, c->ev_bin, c->ev_couple, c->ev_spread, c->ev_join, c->ev_hot[0],
+                       c->ev_hot[1], c->ev_cold[0], c->ev_cold[1]})
     if (e) (void)hipEventDestroy(e);
   delete c;
   return LB_OK;

@@ -42,6 +42,19 @@ constexpr int kTileShift = 6;           // force tile = 64 sites (one wavefront 
 // site count rounded to 64: with a power-of-two lattice the 19 population planes would
 // otherwise share every low address bit, and the sweep's 38 streams measured about 1% slower.
 constexpr long kPlanePad = 256;
+// Bricks of 16 x 4 x 4 sites (one sweep workgroup each): the unit of the coupled part of the
+// sweep.  A brick that some atom's 2 x 2 x 2 stencil touches is "hot": one workgroup computes
+// the coupling velocity on the brick and a one-node halo, the friction of the atoms listed
+// there and their spread force, and updates the brick's sites; the other sites are swept
+// plainly.
+constexpr int kBrickX = 16, kBrickY = 4, kBrickZ = 4;
+constexpr int kBrickShiftX = 4, kBrickShiftY = 2, kBrickShiftZ = 2;
+constexpr int kHaloX = kBrickX + 2, kHaloY = kBrickY + 2, kHaloZ = kBrickZ + 2;
+constexpr int kHaloNodes = kHaloX * kHaloY * kHaloZ;   // 648
+// atoms listed per brick: those whose stencil base lies in the 17 x 5 x 5 nodes around it
+// (at most 425 for atoms at least one lattice spacing apart along some axis); more latches
+// LB_EOVERFLOW
+constexpr int kBrickCap = 640;
 constexpr int kCellCap = 48;            // atoms per neighbour-list cell
 constexpr int kBaseCap = 8;             // atoms whose stencil base is one node
 constexpr float kFixScale = 1099511627776.0f;      // 2^40: fixed-point scale of spread forces
@@ -65,7 +78,11 @@ struct Layout {
   size_t occ_cells;    // int32 [min(ncell, N)]: neighbour-list cells holding atoms this step
   size_t occ_tiles[2]; // int32 [ntiles]: flagged force tiles, by step parity
   size_t node_list[2]; // int32 [min(8 N, S)]: flagged nodes (atom stencil nodes), by step parity
-  size_t occ_count[2]; // int32 [4] by step parity: lengths of the cell, tile and node lists
+  size_t occ_count[2]; // int32 [4] by step parity: lengths of the cell, tile (or hot-brick)
+                       // and node lists
+  size_t brick_count[2]; // int32 [nbricks] by step parity: atoms listed per brick
+  size_t brick_list[2];  // int32 [nbricks][kBrickCap]
+  size_t hot_bricks[2];  // int32 [nbricks]: the hot bricks, compacted
   size_t fext_tab;     // float [ny]   (Kolmogorov / sign-shear profile)
   size_t fext_field;   // float [3][plane] (caller field)
   size_t x0;           // float [N][3] anchors
@@ -112,6 +129,8 @@ struct Geometry {
   long plane;        // population plane stride (elements), S rounded up to 64 plus kPlanePad
   int nblocks;       // ceil(S / kSweepBlock)
   int ntiles;        // ceil(S / 64): force tiles
+  int nb[3];         // bricks per axis
+  long nbricks;
   int nc[3];         // neighbour-list cells per axis (0 when LJ is off)
   long ncell;
   float inv_cw[3];   // 1 / cell width
@@ -129,6 +148,10 @@ struct Geometry {
   // environment variable LBMD_LATE_FORCES (any value) at context creation takes the late start
   // on any lattice, so both orders can be compared on small ones.
   bool late_forces;
+  // LB_FLAG_FUSED_COUPLING with atoms: the coupled step runs as the hot-brick sweep beside the
+  // cold sweep; otherwise the coupling velocity, friction and spread run as separate kernels
+  // before one sweep over every site.  Both give the same bits.
+  bool fused;
 };
 
 bool geometry(const lb_params* p, Geometry* g);
@@ -154,6 +177,10 @@ struct lb_ctx {
   // second stream for the atom work that overlaps the sweep, and its fork/join events
   hipStream_t astream = nullptr;  // atom stream (the caller's stream when single-stream)
   hipEvent_t ev_fork = nullptr, ev_bin = nullptr, ev_couple = nullptr, ev_spread = nullptr, ev_join = nullptr;
+  // fused step: the hot-brick sweep runs on a stream of its own beside the cold sweep; events
+  // by step parity (a wait refers to the previous step's record while this step's is queued)
+  hipStream_t hstream = nullptr;
+  hipEvent_t ev_hot[2] = {nullptr, nullptr}, ev_cold[2] = {nullptr, nullptr};
   // optional per-phase event timing (lb_timing_begin / lb_timing_end)
   std::vector<hipEvent_t> ev;  // kTimedEvents per timed step
   int timed_cap = 0;
@@ -167,6 +194,10 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_copy_pair(void* d0, const void* s0, void* d1, const void* s1, size_t bytes,
                             hipStream_t s);
 hipError_t launch_sweep(lb_ctx* c, const void* fin, void* fout, hipStream_t st);
+// the two parts of the coupled sweep: the hot bricks (coupling + update of their sites), then
+// every other site
+hipError_t launch_hot_sweep(lb_ctx* c, const void* fin, void* fout, hipStream_t st);
+hipError_t launch_cold_sweep(lb_ctx* c, const void* fin, void* fout, hipStream_t st);
 hipError_t launch_read_fields(lb_ctx* c, float* rho, float* u);
 hipError_t launch_read_populations(lb_ctx* c, float* g);
 hipError_t launch_write_populations(lb_ctx* c, const float* g);
@@ -185,6 +216,9 @@ hipError_t launch_prep(lb_ctx* c);
 hipError_t launch_bin_mark(lb_ctx* c);
 hipError_t launch_compact(lb_ctx* c);   // occupied cells, flagged tiles, then flagged nodes
 hipError_t launch_cell_sort(lb_ctx* c);
+// binning of the fused path: atoms to the bricks their stencils touch and to the neighbour-list
+// cells; lists of the hot bricks and of the occupied cells
+hipError_t launch_brick_binning(lb_ctx* c);
 hipError_t launch_node_u(lb_ctx* c);
 hipError_t launch_couple(lb_ctx* c);
 hipError_t launch_spread(lb_ctx* c);
