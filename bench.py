@@ -6,9 +6,11 @@ Default workload: the 256^3 periodic D3Q19 lattice (tau = 0.55) with 200,000 ato
 (atom coupling + spreading, neighbour-list binning, the fused stream/collide sweep, atom
 forces and integration), all on the GPU with the inputs resident in HBM.
 
-Prints one JSON line: MLUPS (the value), the step's algorithmic HBM GB/s, the roofline of
-the dominant kernel (the sweep, timed live with HIP events on its own stream), and the CPU
-oracle timed on a bounded sample of the same workload.
+After W untimed warm-up steps, five runs of exactly K steps are timed (HIP events on the
+step's stream, device synchronisation on both sides of each run); the reported step time is
+their median.  Prints one JSON line: MLUPS (the value), the step's algorithmic HBM GB/s, the
+roofline of the dominant kernel (the sweep, timed live with HIP events on its own stream),
+and the CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -60,56 +62,103 @@ def measured_traffic(workload: str, storage: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(k: int):
-    """The CPU oracle (FP64, single thread) on a bounded sample of the workload: six
-    coupled steps of one eighth of the lattice (half the extent per axis) holding one
-    20,000-atom globule of the same construction and parameters, so the sample has the
-    workload's site and atom mix.  Reported as site updates per second."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_timing(w, steps: int):
+    """Seconds the CPU oracle (FP64, its OpenMP loops) takes for `steps` coupled steps of
+    workload `w` from the rest state, buffer allocation and first touch included."""
     import numpy as np
+    from oracle import oracle as O
+    p = O.params_from_workload(w)
+    g = np.zeros(O.pop_shape(p))
+    t0 = time.perf_counter()
+    O.run(p, g, w.x0, w.v0, w.x0, w.bonds, w.body_force, steps)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(k: int):
+    """The CPU oracle on a bounded sample of the workload: 30 coupled steps of one eighth of
+    the lattice (half the extent per axis) holding one 20,000-atom globule of the same
+    construction and parameters, so the sample has the workload's mix of sites and atoms
+    (about 10 s on 8 to 16 cores).  Reported as site updates per second.  Beside it, the
+    oracle on two whole workloads: the 32^3 tethered ball over its 100 steps and the first
+    20 of the 96^3 differentiation workload's 200 steps."""
     from oracle import oracle as O
     from workloads import make_workload
     from workloads.gen import globule_workload
     w = make_workload(k)
+    if w.n_atoms == 0:
+        raise ValueError("cpu_baseline needs a workload with atoms")
     Ls = tuple(max(8, l // 2) for l in w.L)
     n_per = min(w.n_atoms, 20000)
-    ws = globule_workload(Ls, 1 if n_per else 0, n_per, seed=k, tau=w.tau, gamma=w.gamma,
+    ws = globule_workload(Ls, 1, n_per, seed=k, tau=w.tau, gamma=w.gamma,
                           name="cpu_sample", k_tether=w.k_tether, k_bond=w.k_bond,
                           r0_bond=w.r0_bond, lj_eps=w.lj_eps, lj_sigma=w.lj_sigma,
                           lj_rc=w.lj_rc, lj_exclude_bonded=w.lj_exclude_bonded,
                           bf_kind=0 if w.bf_kind == 3 else w.bf_kind, bf_amp=w.bf_amp,
-                          mass=w.mass) if n_per else None
-    if ws is None:
-        raise ValueError("cpu_baseline needs a workload with atoms")
-    p = O.params_from_workload(ws)
-    g = np.zeros(O.pop_shape(p))
-    O.run(p, g, ws.x0, ws.v0, ws.x0, ws.bonds, None, 1)     # touch the buffers once
-    steps = 6
-    t0 = time.perf_counter()
-    O.run(p, g, ws.x0, ws.v0, ws.x0, ws.bonds, None, steps)
-    dt = time.perf_counter() - t0
-    S = ws.n_sites
-    return {"value": S * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+                          mass=w.mass)
+    steps = 30
+    dt = oracle_timing(ws, steps)
+    others = []
+    for kk, n in ((0, 100), (3, 20)):
+        wk = make_workload(kk)
+        t = oracle_timing(wk, n)
+        others.append({"workload": wk.name, "steps": n, "seconds": round(t, 2),
+                       "mlups": round(wk.n_sites * n / t / 1e6, 2)})
+    threads = O.num_threads()
+    return {"value": round(ws.n_sites * steps / dt / 1e6, 2), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle", "cpu": cpu_model(),
             "sample": "%d coupled steps of a %dx%dx%d lattice with one %d-atom globule, the "
-                      "parameters of %s (FP64, single thread, %.1f s)"
-                      % (steps, Ls[0], Ls[1], Ls[2], n_per, w.name, dt)}
+                      "parameters of %s (FP64, %d threads, %.1f s, allocation included)"
+                      % (steps, Ls[0], Ls[1], Ls[2], n_per, w.name, threads, dt),
+            "whole_workloads": others}
 
 
-def time_steps(sim, steps: int, warmup: int):
-    """(ms per step, wall s) of `steps` coupled steps after `warmup` untimed ones, bracketed by
-    device synchronisation; no per-phase events are queued."""
+def cpu_baseline_full():
+    """The oracle over the full step counts of the 32^3 ball (100), the 128^3 globule (1000)
+    and the 96^3 differentiation workload (200), and 20 steps of the 256^3 workload: one JSON
+    line per workload.  Takes tens of minutes; not part of the default run."""
+    from oracle import oracle as O
+    from workloads import make_workload
+    for k, n in ((0, 100), (3, 200), (1, 1000), (2, 20)):
+        w = make_workload(k)
+        t = oracle_timing(w, n)
+        print(json.dumps({"cpu_baseline_workload": w.name, "steps": n, "seconds": round(t, 2),
+                          "mlups": round(w.n_sites * n / t / 1e6, 3), "kind": "oracle",
+                          "cores": O.num_threads(), "cpu": cpu_model()}), flush=True)
+
+
+def time_steps(sim, steps: int, warmup: int, reps: int = 5):
+    """(median ms per step, wall s of the timed runs, the runs' ms per step): `warmup`
+    untimed steps, then `reps` runs of exactly `steps` coupled steps, each bracketed by
+    device synchronisation and timed by HIP events on the step's stream; no per-phase
+    events are queued."""
     import torch
     sim.step(warmup)
     sim.check()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    ev0.record(sim.stream)
-    sim.step(steps)
-    ev1.record(sim.stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    sim.check()
-    return ev0.elapsed_time(ev1) / steps, wall
+    runs = []
+    wall = 0.0
+    for _ in range(reps):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        ev0.record(sim.stream)
+        sim.step(steps)
+        ev1.record(sim.stream)
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t_start
+        sim.check()
+        runs.append(ev0.elapsed_time(ev1) / steps)
+    runs_sorted = sorted(runs)
+    return runs_sorted[len(runs) // 2], wall, runs
 
 
 def adjoint_ratio(dev):
@@ -123,7 +172,7 @@ def adjoint_ratio(dev):
     w = make_workload(3)
     n_steps, k = 200, 20
     sim = CoupledLB.from_workload(w, device=dev)
-    fwd_ms, _ = time_steps(sim, n_steps, 0)
+    fwd_ms = time_steps(sim, n_steps, 20, reps=3)[0]
     sim.close()
     res = []
     for rep in range(2):      # the first pass includes one-off allocation
@@ -166,7 +215,7 @@ def run(args):
     flags = A.LB_FLAG_SINGLE_STREAM if args.single_stream else 0
     sim = CoupledLB.from_workload(w, storage=args.storage, device=dev, flags=flags)
     # the step: K steps with no per-phase events in the queue
-    step_ms, wall = time_steps(sim, args.steps, args.warmup)
+    step_ms, wall, runs = time_steps(sim, args.steps, args.warmup)
     # the kernels: K more steps with HIP events around each phase, on the streams the
     # phases run on
     A.lb_timing_begin(sim.ctx, args.steps)
@@ -174,9 +223,10 @@ def run(args):
     sweep_ms, atom_ms, nsteps = A.lb_timing_end(sim.ctx)
     sim.check()
     sim.close()
-    log("timed %d steps: %.4f ms/step (events), wall %.3f s; per step in a second timed run: "
-        "sweep kernel %.4f ms, atom kernel chains %.4f ms" %
-        (args.steps, step_ms, wall, sweep_ms / nsteps, atom_ms / nsteps))
+    log("timed 5 x %d steps: median %.4f ms/step (events; runs %s), wall %.3f s; per step in a "
+        "further timed run: sweep kernel %.4f ms, atom kernel chains %.4f ms" %
+        (args.steps, step_ms, " ".join("%.4f" % r for r in runs), wall, sweep_ms / nsteps,
+         atom_ms / nsteps))
     # the other storage formats, same workload and schedule
     storage_ms = {args.storage: round(step_ms, 5)}
     if args.formats:
@@ -241,6 +291,7 @@ def run(args):
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(step_ms, 5),
+        "ms_per_step_runs": [round(r, 5) for r in runs],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -296,6 +347,8 @@ def main():
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--cpu-baseline-full", action="store_true",
+                    help="only time the CPU oracle over whole workloads (tens of minutes)")
     ap.add_argument("--no-formats", dest="formats", action="store_false",
                     help="skip the FP16/BF16 (or FP32) storage, thermal-noise and D3Q27 timings")
     ap.add_argument("--no-adjoint", dest="adjoint", action="store_false",
@@ -309,6 +362,8 @@ def main():
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy(args)
+    elif args.cpu_baseline_full:
+        cpu_baseline_full()
     else:
         run(args)
 

@@ -57,6 +57,8 @@
 #include <algorithm>
 #include <array>
 
+#include <omp.h>
+
 namespace {
 
 // ---------------------------------------------------------------------------------------
@@ -957,6 +959,9 @@ int run_impl(const or_params* p, double* g, double* X, double* V, const double* 
 }  // namespace
 
 extern "C" {
+
+// threads the parallel loops of the oracle use (OpenMP's default team size)
+int32_t or_num_threads() { return (int32_t)omp_get_max_threads(); }
 
 void or_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
   philox4x32_10(ctr, key, out);

@@ -17,7 +17,10 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lbmd_oracle.cpp")
-LIB = os.path.join(HERE, "liblbmd_oracle.so")
+# LBMD_ORACLE_LIB names another build of the same source (the sanitizer test's); it is used
+# as it is, never rebuilt here
+LIB_OVERRIDE = os.environ.get("LBMD_ORACLE_LIB")
+LIB = LIB_OVERRIDE or os.path.join(HERE, "liblbmd_oracle.so")
 
 # The oracle is compiled without target-specific flags so that the same binary runs on any
 # x86-64 host, and without floating-point contraction so that it evaluates exactly the
@@ -29,11 +32,25 @@ CXXFLAGS = ["-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off", "-fno-
 
 
 def build(force: bool = True) -> str:
+    if LIB_OVERRIDE:
+        return LIB
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
         subprocess.check_call(["g++", *CXXFLAGS, SRC, "-o", tmp])
         os.replace(tmp, LIB)
     return LIB
+
+
+# AddressSanitizer and UndefinedBehaviorSanitizer, every finding fatal
+SANITIZE_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                  "-fno-omit-frame-pointer", "-g"]
+
+
+def build_sanitized(path: str) -> str:
+    """The oracle built with the sanitizers at `path` (load it with the ASan runtime
+    preloaded)."""
+    subprocess.check_call(["g++", *CXXFLAGS, *SANITIZE_FLAGS, SRC, "-o", path])
+    return path
 
 
 class OrParams(ctypes.Structure):
@@ -72,7 +89,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        if not LIB_OVERRIDE and (not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC)):
             build(force=True)
         L = ctypes.CDLL(LIB)
         dp = ctypes.POINTER(ctypes.c_double)
@@ -119,6 +136,8 @@ def lib():
                                       up, ctypes.c_int64, ctypes.c_int64, dp, ctypes.c_double]
         L.or_site_normals_n.argtypes = [up, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, dp]
         L.or_mode_basis27.argtypes = [dp, dp, ip]
+        L.or_num_threads.argtypes = []
+        L.or_num_threads.restype = ctypes.c_int32
         _lib = L
     return _lib
 
@@ -245,6 +264,11 @@ def forces(p: OrParams, X, X0, bonds):
     F = np.zeros_like(X)
     lib().or_forces(ctypes.byref(p), _d(X), _d(f64(X0)), _i(i32(bonds).reshape(-1, 2)), _d(F))
     return F
+
+
+def num_threads() -> int:
+    """Threads of the oracle's parallel loops."""
+    return int(lib().or_num_threads())
 
 
 def forces_by_atom(p: OrParams, X, X0, bonds):
