@@ -509,16 +509,16 @@ static AdjLatticeArgs lattice_args(lb_ctx* c, const AdjointBuffers& b) {
   a.bf_kind = c->p.bf_kind;
   a.fext_tab = (const float*)(c->ws + c->lay.fext_tab);
   a.fext_field = (const float*)(c->ws + c->lay.fext_field);
-  a.tile_flag = (const uint32_t*)(c->ws + c->lay.tile_flag[par]);
-  a.fcoup = (const float*)(c->ws + c->lay.fcoup[par]);
-  a.fcoup_clear = (float*)(c->ws + c->lay.fcoup[par]);
-  a.base_count = (int*)(c->ws + c->lay.base_count[par]);
+  a.tile_flag = (const uint32_t*)(c->bin + c->lay.tile_flag[par]);
+  a.fcoup = (const float*)(c->bin + c->lay.fcoup[par]);
+  a.fcoup_clear = (float*)(c->bin + c->lay.fcoup[par]);
+  a.base_count = (int*)(c->bin + c->lay.base_count[par]);
   a.luc = b.luc;
   a.phi = b.phi;
   a.db = b.db;
   a.dom_part = b.dom_part;
-  a.hot_list = (const int*)(c->ws + c->lay.occ_tiles[par]);
-  a.hot_count = (const int*)(c->ws + c->lay.occ_count[par]) + 1;
+  a.hot_list = (const int*)(c->bin + c->lay.occ_tiles[par]);
+  a.hot_count = (const int*)(c->bin + c->lay.occ_count[par]) + 1;
   a.kT = c->p.kT;
   a.seed0 = c->p.seed[0];
   a.seed1 = c->p.seed[1];
@@ -542,9 +542,9 @@ static AdjAtomArgs atom_args(lb_ctx* c, const AdjointBuffers& b) {
   a.x0 = (const float*)(c->ws + c->lay.x0);
   a.d = (const float*)(c->ws + c->lay.disp[c->dcur]);
   a.v = (const float*)(c->ws + c->lay.vel);
-  a.fc = (const float*)(c->ws + c->lay.fc);
+  a.fc = (const float*)(c->bin + c->lay.fc);
   a.U = b.U;
-  a.uc = (const float*)(c->ws + c->lay.uc);
+  a.uc = (const float*)(c->bin + c->lay.uc);
   a.phi = b.phi;
   a.lx_in = b.lx_in;
   a.lv_in = b.lv_in;
@@ -598,11 +598,11 @@ hipError_t launch_adjoint_step(lb_ctx* c, const AdjointBuffers& b) {
   sa.n[1] = g.ny;
   sa.n[2] = g.nz;
   sa.plane = g.plane;
-  sa.occ_tiles = (const int*)(c->ws + c->lay.occ_tiles[par]);
-  sa.occ_count = (const int*)(c->ws + c->lay.occ_count[par]) + 1;
-  sa.base_count = (const int*)(c->ws + c->lay.base_count[par]);
-  sa.base_list = (const int*)(c->ws + c->lay.base_list[par]);
-  sa.atom_frac = (const float4*)(c->ws + c->lay.atom_frac);
+  sa.occ_tiles = (const int*)(c->bin + c->lay.occ_tiles[par]);
+  sa.occ_count = (const int*)(c->bin + c->lay.occ_count[par]) + 1;
+  sa.base_count = (const int*)(c->bin + c->lay.base_count[par]);
+  sa.base_list = (const int*)(c->bin + c->lay.base_list[par]);
+  sa.atom_frac = (const float4*)(c->bin + c->lay.atom_frac);
   sa.lU = b.lU;
   sa.luc = b.luc;
   hipLaunchKernelGGL(k_adj_spread, tgrid, blk, 0, st, sa);

@@ -962,11 +962,11 @@ __global__ __launch_bounds__(256) void k_read_atoms(int N, const float* x0, cons
 
 hipError_t launch_prep(lb_ctx* c) {
   PrepArgs a;
-  a.cell_count = (int*)(c->ws + c->lay.cell_count);
+  a.cell_count = (int*)(c->bin + c->lay.cell_count);
   a.ncell = c->geo.ncell;
-  a.tile_flag = (uint32_t*)(c->ws + c->lay.tile_flag[c->step & 1]);
+  a.tile_flag = (uint32_t*)(c->bin + c->lay.tile_flag[c->step & 1]);
   a.ntiles = c->geo.ntiles;
-  a.occ_count = (int*)(c->ws + c->lay.occ_count[c->step & 1]);
+  a.occ_count = (int*)(c->bin + c->lay.occ_count[c->step & 1]);
   const long n = a.ncell > a.ntiles ? a.ncell : a.ntiles;
   hipLaunchKernelGGL(k_prep, dim3(blocks(n, 256)), dim3(256), 0, c->astream, a);
   return hipGetLastError();
@@ -974,13 +974,13 @@ hipError_t launch_prep(lb_ctx* c) {
 
 hipError_t launch_compact(lb_ctx* c) {
   CompactArgs a;
-  a.cell_count = (const int*)(c->ws + c->lay.cell_count);
+  a.cell_count = (const int*)(c->bin + c->lay.cell_count);
   a.ncell = c->geo.ncell;
-  a.occ_cells = (int*)(c->ws + c->lay.occ_cells);
-  a.tile_flag = (const uint32_t*)(c->ws + c->lay.tile_flag[c->step & 1]);
+  a.occ_cells = (int*)(c->bin + c->lay.occ_cells);
+  a.tile_flag = (const uint32_t*)(c->bin + c->lay.tile_flag[c->step & 1]);
   a.ntiles = c->geo.ntiles;
-  a.occ_tiles = (int*)(c->ws + c->lay.occ_tiles[c->step & 1]);
-  a.occ_count = (int*)(c->ws + c->lay.occ_count[c->step & 1]);
+  a.occ_tiles = (int*)(c->bin + c->lay.occ_tiles[c->step & 1]);
+  a.occ_count = (int*)(c->bin + c->lay.occ_count[c->step & 1]);
   const long nb = (a.ncell + 255) / 256 + (a.ntiles + 255) / 256;
   hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(256), 0, c->astream, a);
   hipError_t e = hipGetLastError();
@@ -989,7 +989,7 @@ hipError_t launch_compact(lb_ctx* c) {
   b.S = (int)c->geo.S;
   b.occ_tiles = a.occ_tiles;
   b.node_flag = (const uint8_t*)(c->ws + c->lay.node_flag);
-  b.node_list = (int*)(c->ws + c->lay.node_list[c->step & 1]);
+  b.node_list = (int*)(c->bin + c->lay.node_list[c->step & 1]);
   b.occ_count = a.occ_count;
   hipLaunchKernelGGL(k_node_compact, dim3(1024), dim3(256), 0, c->astream, b);
   return hipGetLastError();
@@ -1000,11 +1000,11 @@ hipError_t launch_compact(lb_ctx* c) {
 hipError_t launch_brick_binning(lb_ctx* c) {
   const int par = (int)(c->step & 1);
   PrepArgs p;
-  p.cell_count = (int*)(c->ws + c->lay.cell_count);
+  p.cell_count = (int*)(c->bin + c->lay.cell_count);
   p.ncell = c->geo.ncell;
   p.tile_flag = (uint32_t*)(c->ws + c->lay.brick_count[par]);
   p.ntiles = (int)c->geo.nbricks;
-  p.occ_count = (int*)(c->ws + c->lay.occ_count[par]);
+  p.occ_count = (int*)(c->bin + c->lay.occ_count[par]);
   const long n = p.ncell > p.ntiles ? p.ncell : p.ntiles;
   hipLaunchKernelGGL(k_prep, dim3(blocks(n, 256)), dim3(256), 0, c->astream, p);
   hipError_t e = hipGetLastError();
@@ -1019,14 +1019,14 @@ hipError_t launch_brick_binning(lb_ctx* c) {
   b.brick_count = (int*)(c->ws + c->lay.brick_count[par]);
   b.brick_list = (int*)(c->ws + c->lay.brick_list[par]);
   b.cell_count = p.cell_count;
-  b.cell_rec = (int4*)(c->ws + c->lay.cell_rec);
+  b.cell_rec = (int4*)(c->bin + c->lay.cell_rec);
   b.err = (uint32_t*)(c->ws + c->lay.err);
   hipLaunchKernelGGL(k_brick_bin, dim3(blocks8(b.N, 256)), dim3(256), 0, c->astream, b);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   CompactArgs a;
   a.cell_count = p.cell_count;
   a.ncell = c->geo.ncell;
-  a.occ_cells = (int*)(c->ws + c->lay.occ_cells);
+  a.occ_cells = (int*)(c->bin + c->lay.occ_cells);
   a.tile_flag = (const uint32_t*)b.brick_count;
   a.ntiles = (int)c->geo.nbricks;
   a.occ_tiles = (int*)(c->ws + c->lay.hot_bricks[par]);
@@ -1038,10 +1038,10 @@ hipError_t launch_brick_binning(lb_ctx* c) {
 
 hipError_t launch_cell_sort(lb_ctx* c) {
   SortArgs a;
-  a.occ_cells = (const int*)(c->ws + c->lay.occ_cells);
-  a.occ_count = (const int*)(c->ws + c->lay.occ_count[c->step & 1]);
-  a.cell_count = (const int*)(c->ws + c->lay.cell_count);
-  a.cell_rec = (int4*)(c->ws + c->lay.cell_rec);
+  a.occ_cells = (const int*)(c->bin + c->lay.occ_cells);
+  a.occ_count = (const int*)(c->bin + c->lay.occ_count[c->step & 1]);
+  a.cell_count = (const int*)(c->bin + c->lay.cell_count);
+  a.cell_rec = (int4*)(c->bin + c->lay.cell_rec);
   hipLaunchKernelGGL(k_cell_sort, dim3(persistent_grid(std::min(c->geo.ncell, (long)c->p.n_atoms))),
                      dim3(256), 0, c->astream, a);
   return hipGetLastError();
@@ -1054,13 +1054,13 @@ hipError_t launch_bin_mark(lb_ctx* c) {
   a.x0 = (const float*)(c->ws + c->lay.x0);
   a.d = (const float*)(c->ws + c->lay.disp[c->dcur]);
   const int par = (int)(c->step & 1);
-  a.tile_flag = (uint32_t*)(c->ws + c->lay.tile_flag[par]);
+  a.tile_flag = (uint32_t*)(c->bin + c->lay.tile_flag[par]);
   a.node_flag = (uint8_t*)(c->ws + c->lay.node_flag);
-  a.base_count = (int*)(c->ws + c->lay.base_count[par]);
-  a.base_list = (int*)(c->ws + c->lay.base_list[par]);
-  a.atom_frac = (float4*)(c->ws + c->lay.atom_frac);
-  a.cell_count = (int*)(c->ws + c->lay.cell_count);
-  a.cell_rec = (int4*)(c->ws + c->lay.cell_rec);
+  a.base_count = (int*)(c->bin + c->lay.base_count[par]);
+  a.base_list = (int*)(c->bin + c->lay.base_list[par]);
+  a.atom_frac = (float4*)(c->bin + c->lay.atom_frac);
+  a.cell_count = (int*)(c->bin + c->lay.cell_count);
+  a.cell_rec = (int4*)(c->bin + c->lay.cell_rec);
   a.err = (uint32_t*)(c->ws + c->lay.err);
   hipLaunchKernelGGL(k_bin_mark, dim3(blocks8(a.N, 256)), dim3(256), 0, c->astream, a);
   return hipGetLastError();
@@ -1079,9 +1079,9 @@ hipError_t launch_node_u(lb_ctx* c) {
   a.bf_kind = c->p.bf_kind;
   a.fext_tab = (const float*)(c->ws + c->lay.fext_tab);
   a.fext_field = (const float*)(c->ws + c->lay.fext_field);
-  a.node_list = (const int*)(c->ws + c->lay.node_list[c->step & 1]);
-  a.node_count = (const int*)(c->ws + c->lay.occ_count[c->step & 1]) + 2;
-  a.uc = (float*)(c->ws + c->lay.uc);
+  a.node_list = (const int*)(c->bin + c->lay.node_list[c->step & 1]);
+  a.node_count = (const int*)(c->bin + c->lay.occ_count[c->step & 1]) + 2;
+  a.uc = (float*)(c->bin + c->lay.uc);
   a.dnx = g.div_nx;
   a.dny = g.div_ny;
   a.narrow = g.narrow ? 1 : 0;
@@ -1115,8 +1115,8 @@ hipError_t launch_couple(lb_ctx* c) {
   a.x0 = (const float*)(c->ws + c->lay.x0);
   a.d = (const float*)(c->ws + c->lay.disp[c->dcur]);
   a.v = (const float*)(c->ws + c->lay.vel);
-  a.uc = (const float*)(c->ws + c->lay.uc);
-  a.fc = (float*)(c->ws + c->lay.fc);
+  a.uc = (const float*)(c->bin + c->lay.uc);
+  a.fc = (float*)(c->bin + c->lay.fc);
   a.U = c->couple_u;
   hipLaunchKernelGGL(k_couple, dim3(blocks8(8L * a.N, 256)), dim3(256), 0, c->stream, a);
   return hipGetLastError();
@@ -1130,14 +1130,14 @@ hipError_t launch_spread(lb_ctx* c) {
   a.n[2] = c->geo.nz;
   a.plane = c->geo.plane;
   const int par = (int)(c->step & 1);
-  a.node_list = (const int*)(c->ws + c->lay.node_list[par]);
-  a.node_count = (const int*)(c->ws + c->lay.occ_count[par]) + 2;
+  a.node_list = (const int*)(c->bin + c->lay.node_list[par]);
+  a.node_count = (const int*)(c->bin + c->lay.occ_count[par]) + 2;
   a.node_flag = (uint8_t*)(c->ws + c->lay.node_flag);
-  a.base_count = (const int*)(c->ws + c->lay.base_count[par]);
-  a.base_list = (const int*)(c->ws + c->lay.base_list[par]);
-  a.atom_frac = (const float4*)(c->ws + c->lay.atom_frac);
-  a.fc = (const float*)(c->ws + c->lay.fc);
-  a.fcoup = (float*)(c->ws + c->lay.fcoup[par]);
+  a.base_count = (const int*)(c->bin + c->lay.base_count[par]);
+  a.base_list = (const int*)(c->bin + c->lay.base_list[par]);
+  a.atom_frac = (const float4*)(c->bin + c->lay.atom_frac);
+  a.fc = (const float*)(c->bin + c->lay.fc);
+  a.fcoup = (float*)(c->bin + c->lay.fcoup[par]);
   hipLaunchKernelGGL(k_spread, dim3(node_grid(c)), dim3(256), 0, c->stream, a);
   return hipGetLastError();
 }
@@ -1165,10 +1165,10 @@ static ForceArgs force_args(lb_ctx* c) {
   a.charge = (const float*)(c->ws + c->lay.charge);
   a.lj_rc2 = c->p.lj_rc * c->p.lj_rc;
   a.lj_exclude_bonded = c->p.lj_exclude_bonded;
-  a.cell_count = (const int*)(c->ws + c->lay.cell_count);
-  a.cell_rec = (const int4*)(c->ws + c->lay.cell_rec);
-  a.occ_cells = (const int*)(c->ws + c->lay.occ_cells);
-  a.occ_count = (const int*)(c->ws + c->lay.occ_count[c->step & 1]);
+  a.cell_count = (const int*)(c->bin + c->lay.cell_count);
+  a.cell_rec = (const int4*)(c->bin + c->lay.cell_rec);
+  a.occ_cells = (const int*)(c->bin + c->lay.occ_cells);
+  a.occ_count = (const int*)(c->bin + c->lay.occ_count[c->step & 1]);
   a.err = (uint32_t*)(c->ws + c->lay.err);
   a.lf = nullptr;
   a.lx_in = nullptr;
@@ -1220,7 +1220,7 @@ hipError_t launch_integrate(lb_ctx* c) {
   a.N = c->p.n_atoms;
   a.inv_mass = 1.0f / c->p.mass;
   a.ff = (const float*)(c->ws + c->lay.ff);
-  a.fc = (const float*)(c->ws + c->lay.fc);
+  a.fc = (const float*)(c->bin + c->lay.fc);
   a.d = (const float*)(c->ws + c->lay.disp[c->dcur]);
   a.d_next = (float*)(c->ws + c->lay.disp[c->dcur ^ 1]);
   a.v = (float*)(c->ws + c->lay.vel);

@@ -36,7 +36,7 @@ struct SweepArgs {
   const float* fext_field;
   const uint32_t* tile_flag;   // NULL when there are no atoms
   float* fcoup;                // [3][plane] spread coupling force (hot tiles only)
-  int* base_count;             // [plane] cleared here for hot tiles
+  int* base_count;             // [plane] cleared here for hot tiles, with fcoup (NULL: both kept)
   uint32_t* err;
   float kT;                    // thermal noise (NOISE instances only)
   uint32_t seed0, seed1;
@@ -105,10 +105,12 @@ __device__ __forceinline__ void sweep_site(const SweepArgs& a, int s, bool hot) 
     Fcx = fc[s];
     Fcy = fc[a.plane + s];
     Fcz = fc[2 * a.plane + s];
-    fc[s] = 0.f;
-    fc[a.plane + s] = 0.f;
-    fc[2 * a.plane + s] = 0.f;
-    a.base_count[s] = 0;
+    if (a.base_count) {
+      fc[s] = 0.f;
+      fc[a.plane + s] = 0.f;
+      fc[2 * a.plane + s] = 0.f;
+      a.base_count[s] = 0;
+    }
   }
   update_site<ST, NOISE, TRT, Q>(a, s, x, y, z, hot, Fcx, Fcy, Fcz);
 }
@@ -595,9 +597,9 @@ hipError_t launch_sweep(lb_ctx* c, const void* fin, void* fout, hipStream_t st) 
   a.fext_tab = (const float*)(c->ws + c->lay.fext_tab);
   a.fext_field = (const float*)(c->ws + c->lay.fext_field);
   const int par = (int)(c->step & 1);
-  a.tile_flag = c->p.n_atoms > 0 ? (const uint32_t*)(c->ws + c->lay.tile_flag[par]) : nullptr;
-  a.fcoup = (float*)(c->ws + c->lay.fcoup[par]);
-  a.base_count = (int*)(c->ws + c->lay.base_count[par]);
+  a.tile_flag = c->p.n_atoms > 0 ? (const uint32_t*)(c->bin + c->lay.tile_flag[par]) : nullptr;
+  a.fcoup = (float*)(c->bin + c->lay.fcoup[par]);
+  a.base_count = c->keep_coupling ? nullptr : (int*)(c->bin + c->lay.base_count[par]);
   a.err = (uint32_t*)(c->ws + c->lay.err);
   a.kT = c->p.kT;
   a.seed0 = c->p.seed[0];
@@ -680,7 +682,7 @@ hipError_t launch_hot_sweep(lb_ctx* c, const void* fin, void* fout, hipStream_t 
   h.nb0 = c->geo.nb[0];
   h.nb1 = c->geo.nb[1];
   h.hot = (const int*)(c->ws + c->lay.hot_bricks[par]);
-  h.nhot = (const int*)(c->ws + c->lay.occ_count[par]) + 1;
+  h.nhot = (const int*)(c->bin + c->lay.occ_count[par]) + 1;
   h.brick_count = (const int*)(c->ws + c->lay.brick_count[par]);
   h.brick_list = (const int*)(c->ws + c->lay.brick_list[par]);
   h.N = c->p.n_atoms;
@@ -688,7 +690,7 @@ hipError_t launch_hot_sweep(lb_ctx* c, const void* fin, void* fout, hipStream_t 
   h.d = (const float*)(c->ws + c->lay.disp[c->dcur]);
   h.v = (const float*)(c->ws + c->lay.vel);
   h.gamma = c->p.gamma;
-  h.fc = (float*)(c->ws + c->lay.fc);
+  h.fc = (float*)(c->bin + c->lay.fc);
   const dim3 grid(hot_grid(c)), block(kSweepBlock);
   dispatch_sweep(c, [&](auto st_, auto nz, auto tr, auto q) {
     hipLaunchKernelGGL((k_hot_sweep<decltype(st_)::value, decltype(nz)::value, decltype(tr)::value,

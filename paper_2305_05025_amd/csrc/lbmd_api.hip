@@ -57,6 +57,36 @@ bool geometry(const lb_params* p, Geometry* g) {
   return true;
 }
 
+size_t plan_bin(const lb_params* p, const Geometry& g, bool one_parity, Layout* l) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += round_up(bytes, 256);
+    return o;
+  };
+  // [step parity] buffers: two, or one shared by both parities
+  auto take2 = [&](size_t (&o)[2], size_t bytes) {
+    o[0] = take(bytes);
+    o[1] = one_parity ? o[0] : take(bytes);
+  };
+  const size_t N = (size_t)p->n_atoms;
+  take2(l->fcoup, N ? 3 * (size_t)g.plane * 4 : 0);
+  take2(l->tile_flag, N ? (size_t)g.ntiles * 4 : 0);
+  take2(l->base_count, N ? (size_t)g.plane * 4 : 0);
+  take2(l->base_list, N ? (size_t)g.plane * kBaseCap * 4 : 0);
+  l->uc = take(N ? 3 * (size_t)g.plane * 4 : 0);
+  l->atom_frac = take(N * 16);
+  l->occ_cells = take(std::min((size_t)g.ncell, N) * 4);
+  take2(l->occ_tiles, N ? (size_t)g.ntiles * 4 : 0);
+  take2(l->node_list, std::min(8 * N, (size_t)g.S) * 4);
+  take2(l->occ_count, N ? 16 : 0);
+  l->fc = take(3 * N * 4);
+  l->cell_count = take((size_t)g.ncell * 4);
+  l->cell_rec = take((size_t)g.ncell * kCellCap * 16);
+  l->U = take(3 * N * 4);
+  return off;
+}
+
 Layout plan(const lb_params* p, const Geometry& g) {
   Layout l;
   size_t off = 0;
@@ -69,20 +99,10 @@ Layout plan(const lb_params* p, const Geometry& g) {
   const size_t popb = (size_t)g.q * g.plane * g.elem;
   l.pop[0] = take(popb);
   l.pop[1] = take(popb);
-  for (int k = 0; k < 2; ++k) {
-    l.fcoup[k] = take(N ? 3 * (size_t)g.plane * 4 : 0);
-    l.tile_flag[k] = take(N ? (size_t)g.ntiles * 4 : 0);
-    l.base_count[k] = take(N ? (size_t)g.plane * 4 : 0);
-    l.base_list[k] = take(N ? (size_t)g.plane * kBaseCap * 4 : 0);
-  }
+  l.bin_bytes = plan_bin(p, g, false, &l);
+  l.bin_base = take(l.bin_bytes);
   l.node_flag = take(N ? (size_t)g.plane : 0);
-  l.uc = take(N ? 3 * (size_t)g.plane * 4 : 0);
-  l.atom_frac = take(N * 16);
-  l.occ_cells = take(std::min((size_t)g.ncell, N) * 4);
   for (int k = 0; k < 2; ++k) {
-    l.occ_tiles[k] = take(N ? (size_t)g.ntiles * 4 : 0);
-    l.node_list[k] = take(std::min(8 * N, (size_t)g.S) * 4);
-    l.occ_count[k] = take(N ? 16 : 0);
     l.brick_count[k] = take(g.fused ? (size_t)g.nbricks * 4 : 0);
     l.brick_list[k] = take(g.fused ? (size_t)g.nbricks * kBrickCap * 4 : 0);
     l.hot_bricks[k] = take(g.fused ? (size_t)g.nbricks * 4 : 0);
@@ -94,13 +114,10 @@ Layout plan(const lb_params* p, const Geometry& g) {
   l.disp[0] = take(2 * 3 * N * 4);
   l.disp[1] = take(2 * 3 * N * 4);
   l.vel = take(2 * 3 * N * 4);
-  l.fc = take(3 * N * 4);
   l.ff = take(3 * N * 4);
   l.charge = take(N * 4);
   l.bond_off = take((N + 1) * 4);
   l.bond_nbr = take(2 * (size_t)p->n_bonds * 4);
-  l.cell_count = take((size_t)g.ncell * 4);
-  l.cell_rec = take((size_t)g.ncell * kCellCap * 16);
   l.red_partial = take((size_t)kRedBlocks * 4 * 8);
   l.red_out = take(8 * 8);
   l.err = take(4 * 4);
@@ -300,6 +317,7 @@ lb_status lb_init(const lb_params* p, void* workspace, size_t workspace_bytes, c
   c->lay = lay;
   c->stream = st;
   c->ws = (char*)workspace;
+  c->bin = c->ws + lay.bin_base;
   c->popbuf[0] = c->ws + lay.pop[0];
   c->popbuf[1] = c->ws + lay.pop[1];
   c->cur = 0;
@@ -311,17 +329,13 @@ lb_status lb_init(const lb_params* p, void* workspace, size_t workspace_bytes, c
                    : c->omega;
 
   char* ws = c->ws;
-  // zero everything the step relies on being zero
+  // zero everything the step relies on being zero (the binning region as a whole)
   const size_t popb = (size_t)g.q * g.plane * g.elem;
   struct Z { size_t off, bytes; } zs[] = {
-      {lay.pop[0], popb}, {lay.pop[1], popb},
-      {lay.fcoup[0], N ? 3 * (size_t)g.plane * 4 : 0}, {lay.tile_flag[0], N ? (size_t)g.ntiles * 4 : 0},
-      {lay.fcoup[1], N ? 3 * (size_t)g.plane * 4 : 0}, {lay.tile_flag[1], N ? (size_t)g.ntiles * 4 : 0},
-      {lay.base_count[0], N ? (size_t)g.plane * 4 : 0}, {lay.base_count[1], N ? (size_t)g.plane * 4 : 0},
-      {lay.node_flag, N ? (size_t)g.plane : 0}, {lay.uc, N ? 3 * (size_t)g.plane * 4 : 0},
-      {lay.disp[0], 24 * (size_t)N}, {lay.disp[1], 24 * (size_t)N}, {lay.fc, 12 * (size_t)N},
-      {lay.vel, 24 * (size_t)N},
-      {lay.cell_count, (size_t)g.ncell * 4}, {lay.err, 16},
+      {lay.pop[0], popb}, {lay.pop[1], popb}, {lay.bin_base, lay.bin_bytes},
+      {lay.node_flag, N ? (size_t)g.plane : 0},
+      {lay.disp[0], 24 * (size_t)N}, {lay.disp[1], 24 * (size_t)N},
+      {lay.vel, 24 * (size_t)N}, {lay.err, 16},
       {lay.fext_field, p->bf_kind == LB_BF_FIELD ? 3 * (size_t)g.plane * 4 : 0}};
   for (const Z& z : zs)
     if (z.bytes && (e = launch_zero(ws + z.off, round_up(z.bytes, 4), st)) != hipSuccess) {
@@ -773,12 +787,18 @@ lb_status lb_timing_end(lb_ctx* c, double out_ms[3]) {
 // ---- adjoint -------------------------------------------------------------------------------
 namespace {
 
+// final state, k state slots, k binning regions (one per step of a segment: the recomputed
+// forward step q bins into region q and its backward step reads it there), adjoint fields
 struct AdjLayout {
-  size_t final_state, slots, lam[2], phi, luc, U, lU, lf, lx[2], lv[2], dg_part, dom_part, acc, total;
+  size_t final_state, slots, sets, set_bytes, lam[2], phi, luc, lU, lf, lx[2], lv[2], dg_part,
+      dom_part, acc, total;
+  Layout set;  // the context's layout with the binning offsets of one step's region
 };
 
 AdjLayout plan_adjoint(const lb_ctx* c, int k) {
   AdjLayout l;
+  l.set = c->lay;
+  l.set_bytes = round_up(plan_bin(&c->p, c->geo, true, &l.set), 256);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -788,11 +808,11 @@ AdjLayout plan_adjoint(const lb_ctx* c, int k) {
   const size_t sb = lb_state_bytes(c), N = (size_t)c->p.n_atoms, plane = (size_t)c->geo.plane;
   l.final_state = take(sb);
   l.slots = take(sb * (size_t)k);
+  l.sets = take(l.set_bytes * (size_t)k);
   l.lam[0] = take((size_t)c->geo.q * plane * 4);
   l.lam[1] = take((size_t)c->geo.q * plane * 4);
   l.phi = take(3 * plane * 4);
   l.luc = take(3 * plane * 4);
-  l.U = take(12 * N);
   l.lU = take(12 * N);
   l.lf = take(16 * N);
   for (int q = 0; q < 2; ++q) {
@@ -848,13 +868,38 @@ lb_status lb_backward(lb_ctx* c, const void* ckpts, int32_t n_steps, int32_t k, 
   const size_t N3 = 3 * (size_t)c->p.n_atoms;
   const size_t aoff = state_atom_offset(c), abytes = round_up(24 * (size_t)c->p.n_atoms, 256);
   auto slot = [&](int q) { return A + L.slots + (size_t)q * sb; };
+  auto set = [&](int q) { return A + L.sets + (size_t)q * L.set_bytes; };
   const hipStream_t as = c->astream;
   char* pb0 = c->popbuf[0];
   char* pb1 = c->popbuf[1];
+  const Layout lay0 = c->lay;
+  char* bin0 = c->bin;
+  const bool fused0 = c->geo.fused;
+  // step q of a segment bins into its own region (lay = L.set, bin = set(q))
+  auto use_set = [&](int q) {
+    c->lay = L.set;
+    c->bin = set(q);
+  };
+  auto use_own = [&]() {
+    c->lay = lay0;
+    c->bin = bin0;
+  };
   lb_status st = LB_OK;
-  // every kernel of the backward pass runs in order on the caller's stream
+  // every kernel of the backward pass runs in order on the caller's stream, and the forward
+  // steps are recomputed by the unfused kernels (the same bits), which leave the binning,
+  // coupling velocity, friction and spread force of each step in its region
   c->astream = c->stream;
+  c->geo.fused = false;
   if ((st = lb_state_save(c, A + L.final_state)) != LB_OK) goto restore;
+  // the regions' spread force and base-node counts start at zero; each backward step clears
+  // those of its step again (on the flagged tiles, where its forward step wrote them)
+  for (int q = 0; q < k; ++q) {
+    if ((e = launch_zero(set(q) + L.set.fcoup[0], 12 * (size_t)c->geo.plane, c->stream)) != hipSuccess ||
+        (e = launch_zero(set(q) + L.set.base_count[0], 4 * (size_t)c->geo.plane, c->stream)) != hipSuccess) {
+      st = hip_fail(c, e, "adjoint set-up");
+      goto restore;
+    }
+  }
   if ((e = launch_zero(A + L.lam[0], (size_t)c->geo.q * c->geo.plane * 4, c->stream)) != hipSuccess ||
       (e = launch_zero(A + L.acc, 24, c->stream)) != hipSuccess ||
       (dL_db && (e = launch_zero(dL_db, 12 * (size_t)c->geo.S, c->stream)) != hipSuccess) ||
@@ -884,7 +929,14 @@ lb_status lb_backward(lb_ctx* c, const void* ckpts, int32_t n_steps, int32_t k, 
         c->popbuf[c->cur] = slot(q) + 256;
         c->popbuf[c->cur ^ 1] = slot(q + 1) + 256;
         c->step = first + t0 + q;
-        if ((st = lb_couple_step(c, 1)) != LB_OK) goto restore;
+        use_set(q);
+        c->couple_u = (float*)(set(q) + L.set.U);
+        c->keep_coupling = true;
+        st = lb_couple_step(c, 1);
+        c->keep_coupling = false;
+        c->couple_u = nullptr;
+        use_own();
+        if (st != LB_OK) goto restore;
         if ((e = copy_atoms(c, slot(q + 1) + aoff, slot(q + 1) + aoff + abytes, c->ws + c->lay.disp[c->dcur],
                             c->ws + c->lay.vel)) != hipSuccess) {
           st = hip_fail(c, e, "recompute copy");
@@ -900,16 +952,24 @@ lb_status lb_backward(lb_ctx* c, const void* ckpts, int32_t n_steps, int32_t k, 
         }
         c->popbuf[c->cur] = slot(q) + 256;
         c->step = first + t0 + q;
-        c->couple_u = (float*)(A + L.U);
-        if ((e = launch_prep(c)) != hipSuccess || (e = launch_bin_mark(c)) != hipSuccess ||
-            (e = launch_compact(c)) != hipSuccess ||
-            (c->geo.ncell > 0 && (e = launch_cell_sort(c)) != hipSuccess) ||
-            (e = launch_node_u(c)) != hipSuccess || (e = launch_couple(c)) != hipSuccess ||
-            (e = launch_spread(c)) != hipSuccess) {
-          st = hip_fail(c, e, "adjoint recompute launch");
-          goto restore;
+        use_set(q);
+        // the last step of the segment was not recomputed (its output is the next segment's
+        // checkpoint): bin and couple it here
+        if (q == len - 1) {
+          c->couple_u = (float*)(set(q) + L.set.U);
+          e = launch_prep(c);
+          if (e == hipSuccess) e = launch_bin_mark(c);
+          if (e == hipSuccess) e = launch_compact(c);
+          if (e == hipSuccess && c->geo.ncell > 0) e = launch_cell_sort(c);
+          if (e == hipSuccess) e = launch_node_u(c);
+          if (e == hipSuccess) e = launch_couple(c);
+          if (e == hipSuccess) e = launch_spread(c);
+          c->couple_u = nullptr;
+          if (e != hipSuccess) {
+            st = hip_fail(c, e, "adjoint recompute launch");
+            goto restore;
+          }
         }
-        c->couple_u = nullptr;
         AdjointBuffers b;
         b.lam_in = (const float*)(A + L.lam[li]);
         b.lam_out = (float*)(A + L.lam[li ^ 1]);
@@ -919,14 +979,16 @@ lb_status lb_backward(lb_ctx* c, const void* ckpts, int32_t n_steps, int32_t k, 
         b.dom_part = (double*)(A + L.dom_part);
         b.dg_part = (double*)(A + L.dg_part);
         b.acc = (double*)(A + L.acc);
-        b.U = (const float*)(A + L.U);
+        b.U = (const float*)(set(q) + L.set.U);
         b.lU = (float*)(A + L.lU);
         b.lf = (float4*)(A + L.lf);
         b.lx_in = (const float*)(A + L.lx[li]);
         b.lv_in = (const float*)(A + L.lv[li]);
         b.lx_out = (float*)(A + L.lx[li ^ 1]);
         b.lv_out = (float*)(A + L.lv[li ^ 1]);
-        if ((e = launch_adjoint_step(c, b)) != hipSuccess) {
+        e = launch_adjoint_step(c, b);
+        use_own();
+        if (e != hipSuccess) {
           st = hip_fail(c, e, "adjoint step launch");
           goto restore;
         }
@@ -959,6 +1021,9 @@ lb_status lb_backward(lb_ctx* c, const void* ckpts, int32_t n_steps, int32_t k, 
   }
 restore:
   c->couple_u = nullptr;
+  c->keep_coupling = false;
+  use_own();
+  c->geo.fused = fused0;
   c->popbuf[0] = pb0;
   c->popbuf[1] = pb1;
   {

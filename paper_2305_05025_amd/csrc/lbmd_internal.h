@@ -64,9 +64,15 @@ constexpr float kFixInv = 1.0f / 1099511627776.0f;
 constexpr uint32_t kErrOverflow = 1u;
 constexpr uint32_t kErrNonFinite = 2u;
 
-// Byte offsets of every buffer inside the caller's workspace.
+// Byte offsets of every buffer.  The buffers a step's binning and coupling produce (from
+// fcoup to cell_rec, and U) are offsets into the binning region at lb_ctx::bin, normally the
+// part of the workspace at bin_base; the adjoint gives each step of a segment a region of its
+// own, so that its backward step reuses the binning of its recomputed forward step.  All
+// others are offsets into the workspace.
 struct Layout {
   size_t pop[2];       // population buffers A / B, q planes of `plane` elements
+  size_t bin_base;     // the binning region inside the workspace, and its size
+  size_t bin_bytes;
   // [step parity]: a step's sweep still reads these while the next step bins its atoms
   size_t fcoup[2];     // float [3][plane]: spread coupling force at marked nodes
   size_t tile_flag[2]; // uint32 per 64-site force tile
@@ -95,6 +101,7 @@ struct Layout {
   size_t bond_nbr;     // int32 [2 n_bonds]
   size_t cell_count;   // int32 [ncell]
   size_t cell_rec;     // int4 [ncell][kCellCap]: fixed-point position in the cell, atom index
+  size_t U;            // float [N][3]: fluid velocity interpolated at each atom (adjoint only)
   size_t red_partial;  // double [kRedBlocks][4]
   size_t red_out;      // double [8]
   size_t err;          // uint32 [4]
@@ -156,6 +163,9 @@ struct Geometry {
 
 bool geometry(const lb_params* p, Geometry* g);
 Layout plan(const lb_params* p, const Geometry& g);
+// Offsets of the binning region's buffers (relative to its start) into *l; returns its size.
+// one_parity: a region used by one step only, whose [2] buffers share one allocation.
+size_t plan_bin(const lb_params* p, const Geometry& g, bool one_parity, Layout* l);
 
 }  // namespace lbmd
 
@@ -166,8 +176,12 @@ struct lb_ctx {
   hipStream_t stream;
   int device;       // the HIP device current at lb_init
   char* ws;
+  char* bin;        // the binning region (inside ws; the adjoint points it at a step's own)
   char* popbuf[2];  // population buffers A / B (inside ws; the adjoint points them at its slots)
   float* couple_u = nullptr;  // when set, k_couple also stores U (the adjoint needs it)
+  // the sweep leaves the spread force and the base-node counts in place (the adjoint's
+  // recomputed steps, whose backward steps read them)
+  bool keep_coupling = false;
   int cur;        // which population buffer holds the current state
   int dcur;       // which displacement buffer holds X^n - x0
   int64_t step;
