@@ -85,12 +85,13 @@ def oracle_timing(w, steps: int):
 
 
 def cpu_baseline(k: int):
-    """The CPU oracle on a bounded sample of the workload: 30 coupled steps of one eighth of
-    the lattice (half the extent per axis) holding one 20,000-atom globule of the same
-    construction and parameters, so the sample has the workload's mix of sites and atoms
-    (about 10 s on 8 to 16 cores).  Reported as site updates per second.  Beside it, the
-    oracle on two whole workloads: the 32^3 tethered ball over its 100 steps and the first
-    20 of the 96^3 differentiation workload's 200 steps."""
+    """The CPU oracle on a bounded sample of the workload: coupled steps of one eighth of the
+    lattice (half the extent per axis) holding one 20,000-atom globule of the same
+    construction and parameters, so the sample has the workload's mix of sites and atoms.  A
+    10-step probe sizes the timed run to about 10 s of the host's work (10 to 400 steps).
+    Reported as site updates per second.  Beside it, the oracle on two whole workloads: the
+    32^3 tethered ball over its 100 steps and the first 20 of the 96^3 differentiation
+    workload's 200 steps."""
     from oracle import oracle as O
     from workloads import make_workload
     from workloads.gen import globule_workload
@@ -105,7 +106,8 @@ def cpu_baseline(k: int):
                           lj_rc=w.lj_rc, lj_exclude_bonded=w.lj_exclude_bonded,
                           bf_kind=0 if w.bf_kind == 3 else w.bf_kind, bf_amp=w.bf_amp,
                           mass=w.mass)
-    steps = 30
+    probe = oracle_timing(ws, 10) / 10
+    steps = int(min(400, max(10, round(10.0 / probe))))
     dt = oracle_timing(ws, steps)
     others = []
     for kk, n in ((0, 100), (3, 20)):

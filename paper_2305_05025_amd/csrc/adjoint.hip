@@ -468,18 +468,45 @@ __global__ __launch_bounds__(256) void k_adj_spread(AdjSpreadArgs a) {
 }
 
 // acc[0] += sum of the n0 partials p0; acc[1], acc[2] += sums of the two rows of n1 partials
-// p1 (fixed order, one workgroup)
-__global__ __launch_bounds__(256) void k_adj_reduce(const double* p0, int n0, const double* p1, int n1,
-                                                    double* acc) {
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  for (int k = threadIdx.x; k < n0; k += 256) s0 += p0[k];
-  for (int k = threadIdx.x; k < n1; k += 256) {
-    s1 += p1[k];
-    s2 += p1[n1 + k];
+// p1 (fixed order, one workgroup of kAdjRed threads).  Each thread keeps kAdjRedUnroll loads
+// of each array in flight per round, so a large lattice's 65,536 sweep partials take a few
+// memory round trips rather than one per element.
+constexpr int kAdjRed = 1024, kAdjRedUnroll = 8;
+
+__device__ __forceinline__ double block_sum_red(double v) {
+  __shared__ double part[kAdjRed / 64];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int w = 0; w < kAdjRed / 64; ++w) r += part[w];
+  __syncthreads();
+  return r;
+}
+
+// sum over k = threadIdx.x, + kAdjRed, ... < n of p[k], in that order
+__device__ __forceinline__ double thread_sum(const double* p, int n) {
+  double s = 0.0;
+  for (int base = 0; base < n; base += kAdjRed * kAdjRedUnroll) {
+    double v[kAdjRedUnroll];
+#pragma unroll
+    for (int u = 0; u < kAdjRedUnroll; ++u) {
+      const int k = base + u * kAdjRed + (int)threadIdx.x;
+      v[u] = k < n ? p[k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kAdjRedUnroll; ++u) s += v[u];
   }
-  s0 = block_sum(s0);
-  s1 = block_sum(s1);
-  s2 = block_sum(s2);
+  return s;
+}
+
+__global__ __launch_bounds__(kAdjRed) void k_adj_reduce(const double* p0, int n0, const double* p1,
+                                                        int n1, double* acc) {
+  const double s0 = block_sum_red(thread_sum(p0, n0));
+  const double s1 = block_sum_red(thread_sum(p1, n1));
+  const double s2 = block_sum_red(thread_sum(p1 + n1, n1));
   if (threadIdx.x == 0) {
     acc[0] += s0;
     acc[1] += s1;
@@ -625,7 +652,7 @@ hipError_t launch_adjoint_step(lb_ctx* c, const AdjointBuffers& b) {
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // 6. FP64 accumulators
-  hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(256), 0, st, (const double*)b.dg_part, (int)nab,
+  hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(kAdjRed), 0, st, (const double*)b.dg_part, (int)nab,
                      (const double*)b.dom_part, g.nblocks, b.acc);
   return hipGetLastError();
 }
