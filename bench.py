@@ -163,16 +163,15 @@ def time_steps(sim, steps: int, warmup: int, reps: int = 5):
     return runs_sorted[len(runs) // 2], wall, runs
 
 
-def adjoint_ratio(dev):
+def adjoint_ratio(dev, config: int = 3, n_steps: int = 200, k: int = 20):
     """Forward and backward (adjoint with checkpoint-and-recompute) times on the
-    differentiation workload: 96^3 lattice, one 5,000-atom globule, body-force field, 200
-    steps, checkpoints every 20 steps."""
+    differentiation workload (by default: 96^3 lattice, one 5,000-atom globule, body-force
+    field, 200 steps, checkpoints every 20 steps)."""
     import numpy as np
     import torch
     from paper_2305_05025_amd.coupled import CoupledLB
     from workloads import make_workload
-    w = make_workload(3)
-    n_steps, k = 200, 20
+    w = make_workload(config)
     sim = CoupledLB.from_workload(w, device=dev)
     fwd_ms = time_steps(sim, n_steps, 20, reps=3)[0]
     sim.close()
@@ -185,7 +184,9 @@ def adjoint_ratio(dev):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         d = sim.displacement().double()
-        D = torch.tensor(w.target_shift, dtype=torch.float64, device=dev)
+        # the loss of the differentiation workload (a workload without a target shift: D = 0)
+        D = torch.tensor(w.target_shift if w.target_shift is not None else [0.0, 0.0, 0.0],
+                         dtype=torch.float64, device=dev)
         dLdX = (2.0 * (d - D) / w.n_atoms).float()
         torch.cuda.synchronize()
         t2 = time.perf_counter()
@@ -351,6 +352,12 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--cpu-baseline-full", action="store_true",
                     help="only time the CPU oracle over whole workloads (tens of minutes)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only time the forward and backward passes (--adjoint-config, "
+                         "--adjoint-steps, --adjoint-k) and print them as JSON")
+    ap.add_argument("--adjoint-config", type=int, default=3)
+    ap.add_argument("--adjoint-steps", type=int, default=200)
+    ap.add_argument("--adjoint-k", type=int, default=20)
     ap.add_argument("--no-formats", dest="formats", action="store_false",
                     help="skip the FP16/BF16 (or FP32) storage, thermal-noise and D3Q27 timings")
     ap.add_argument("--no-adjoint", dest="adjoint", action="store_false",
@@ -366,6 +373,10 @@ def main():
         calibrate_copy(args)
     elif args.cpu_baseline_full:
         cpu_baseline_full()
+    elif args.adjoint_only:
+        import torch
+        print(json.dumps(adjoint_ratio(torch.device("cuda:0"), args.adjoint_config,
+                                       args.adjoint_steps, args.adjoint_k)), flush=True)
     else:
         run(args)
 
