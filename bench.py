@@ -215,7 +215,8 @@ def run(args):
     t0 = time.time()
     w = make_workload(args.config)
     log("workload %s: lattice %s, %d atoms, built in %.1f s" % (w.name, w.L, w.n_atoms, time.time() - t0))
-    flags = A.LB_FLAG_SINGLE_STREAM if args.single_stream else 0
+    flags = (A.LB_FLAG_SINGLE_STREAM if args.single_stream else 0) | \
+        (A.LB_FLAG_STEP_GRAPHS if args.graphs else 0)
     sim = CoupledLB.from_workload(w, storage=args.storage, device=dev, flags=flags)
     # the step: K steps with no per-phase events in the queue
     step_ms, wall, runs = time_steps(sim, args.steps, args.warmup)
@@ -302,7 +303,7 @@ def run(args):
         "data": "synthetic",
         "config": {"workload": w.name, "lattice": list(w.L), "atoms": w.n_atoms,
                    "storage": args.storage, "tau": w.tau, "steps_per_call": args.steps,
-                   "streams": 1 if args.single_stream else 2},
+                   "streams": 1 if args.single_stream else 2, "graphs": bool(args.graphs)},
         "hbm_gbs_step": round(step_gbs, 1),
         "hbm_frac_step": round(step_gbs / HBM_PEAK_GBS, 4),
         # summed durations of the atom-side kernel chains (binning, coupling, cell sort +
@@ -364,6 +365,8 @@ def main():
                     help="skip the adjoint/forward timing on the differentiation workload")
     ap.add_argument("--single-stream", action="store_true",
                     help="queue every kernel on one stream (no overlap of atom and lattice work)")
+    ap.add_argument("--graphs", action="store_true",
+                    help="replay the steps from captured HIP graphs (LB_FLAG_STEP_GRAPHS)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the multi-GPU (domain-decomposed) path is not "

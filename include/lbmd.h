@@ -100,6 +100,25 @@ typedef enum {
                                       this one for small lattices bound by the host's launch
                                       rate (32^3 with 500 atoms: 0.080 against 0.088 ms).  Needs
                                       lb_workspace_bytes() for these flags */
+#define LB_FLAG_STEP_GRAPHS 0x8u    /* replay the step from a HIP graph: the first call that starts
+                                      at an even (odd) step captures the launches and events of
+                                      two steps, and every call of two or more steps replays it,
+                                      so the host makes one call per two steps instead of about
+                                      sixteen per step.  Same bits as the launches it replaces.
+                                      Applies to the unfused step without thermal noise (kT = 0),
+                                      without LB_FLAG_CHECK_FINITE and outside lb_timing_begin /
+                                      lb_timing_end; other calls, a call's odd last step and the
+                                      backward pass's steps are launched as usual.  The graphs
+                                      hold the context's buffer addresses and are released by
+                                      lb_destroy.  Measured on MI355X it is not faster than the
+                                      best eager schedule at any size (ms per step, graphs
+                                      against eager: 32^3 with 500 atoms 0.054 against 0.075
+                                      with two streams and 0.051 with one; 96^3 0.082 against
+                                      0.076; 128^3 0.121 against 0.110; 256^3 0.606 against
+                                      0.562): small lattices are bound by the dependent kernels'
+                                      dispatch latency on the GPU, which a graph keeps, and the
+                                      replay overlaps the atom and lattice work less.  It is for
+                                      callers that launch the step from graphs of their own */
 
 typedef struct {
   int32_t L[3];              /* nx, ny, nz >= 2; periodic */

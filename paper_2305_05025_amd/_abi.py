@@ -18,6 +18,7 @@ LB_BF_NONE, LB_BF_KOLMOGOROV, LB_BF_SIGN_SHEAR, LB_BF_FIELD = 0, 1, 2, 3
 LB_FLAG_CHECK_FINITE = 0x1
 LB_FLAG_SINGLE_STREAM = 0x2
 LB_FLAG_FUSED_COUPLING = 0x4
+LB_FLAG_STEP_GRAPHS = 0x8
 
 STATUS_NAMES = {0: "LB_OK", 1: "LB_EINVAL", 2: "LB_ENOMEM", 3: "LB_EDEVICE", 4: "LB_ESTATE",
                 5: "LB_ENONFINITE", 6: "LB_EOVERFLOW"}

@@ -139,7 +139,7 @@ static std::string validate(const lb_params* p) {
   const double S = (double)p->L[0] * p->L[1] * p->L[2];
   if (S > 2147483647.0) return "lattice has more than 2^31 - 1 sites";
   if (!finite(p->tau) || !(p->tau > 0.5f)) return "tau must be finite and > 0.5 (nu = (tau - 1/2)/3 > 0)";
-  if (p->flags & ~(LB_FLAG_CHECK_FINITE | LB_FLAG_SINGLE_STREAM | LB_FLAG_FUSED_COUPLING))
+  if (p->flags & ~(LB_FLAG_CHECK_FINITE | LB_FLAG_SINGLE_STREAM | LB_FLAG_FUSED_COUPLING | LB_FLAG_STEP_GRAPHS))
     return "flags holds an unknown bit";
   if (!finite(p->kT) || p->kT < 0.0f) return "kT must be finite and >= 0";
   if (!finite(p->trt_magic) || p->trt_magic < 0.0f) return "trt_magic must be finite and >= 0";
@@ -393,6 +393,11 @@ lb_status lb_init(const lb_params* p, void* workspace, size_t workspace_bytes, c
           return hip_fail(nullptr, e, "creating the hot-brick stream");
         }
   }
+  if ((p->flags & LB_FLAG_STEP_GRAPHS) &&
+      (e = hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking)) != hipSuccess) {
+    lb_destroy(c);
+    return hip_fail(nullptr, e, "creating the capture stream");
+  }
   *out = c;
   return LB_OK;
 }
@@ -491,12 +496,75 @@ static lb_status couple_step_fused(lb_ctx* c, int32_t n_steps) {
   return LB_OK;
 }
 
+static lb_status couple_steps_eager(lb_ctx* c, int32_t n_steps);
+
+// LB_FLAG_STEP_GRAPHS: the step's launches and events, captured once per step parity as a
+// graph of two steps and replayed.  A captured call is self-contained: it forks the atom
+// stream from an event recorded inside the capture, bins its first step inside it and joins
+// the atom stream back at its end, so no operation in it waits on an event recorded outside
+// the capture.  Two steps return the population and displacement buffers to where they
+// started, so one graph serves every call that starts at that parity; kernel arguments hold
+// no other per-step value without thermal noise (whose counter is the step).
+static bool graph_eligible(const lb_ctx* c, int32_t n_steps) {
+  return (c->p.flags & LB_FLAG_STEP_GRAPHS) && c->gstream && n_steps >= 2 && !(c->p.flags & LB_FLAG_CHECK_FINITE) &&
+         !c->geo.fused && c->p.kT == 0.0f && c->timed_cap == 0 && !c->keep_coupling && !c->couple_u &&
+         c->bin == c->ws + c->lay.bin_base && c->popbuf[0] == c->ws + c->lay.pop[0] &&
+         c->popbuf[1] == c->ws + c->lay.pop[1];
+}
+
+static lb_status couple_steps_graph(lb_ctx* c, int32_t n_steps) {
+  hipError_t e;
+  const int par = (int)(c->step & 1);
+  if (!c->gexec[par]) {
+    // captured on the library's own stream (the caller's may be the legacy null stream, which
+    // cannot be captured); the graph is launched on the caller's
+    const int cur = c->cur, dcur = c->dcur;
+    const int64_t step = c->step;
+    const hipStream_t caller = c->stream, as = c->astream;
+    if ((e = hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      return hip_fail(c, e, "beginning the step capture");
+    c->stream = c->gstream;
+    if (as == caller) c->astream = c->gstream;   // single-stream schedule
+    const lb_status st = couple_steps_eager(c, 2);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(c->gstream, &g);
+    c->stream = caller;
+    c->astream = as;
+    // nothing ran: the two captured steps are launched below
+    c->cur = cur;
+    c->dcur = dcur;
+    c->step = step;
+    if (st != LB_OK || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return st != LB_OK ? st : hip_fail(c, e, "ending the step capture");
+    }
+    e = hipGraphInstantiate(&c->gexec[par], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      c->gexec[par] = nullptr;
+      return hip_fail(c, e, "instantiating the step graph");
+    }
+  }
+  int32_t done = 0;
+  for (; done + 2 <= n_steps; done += 2) {
+    if ((e = hipGraphLaunch(c->gexec[par], c->stream)) != hipSuccess) return hip_fail(c, e, "step graph launch");
+    c->step += 2;
+  }
+  return done < n_steps ? couple_steps_eager(c, n_steps - done) : LB_OK;
+}
+
 lb_status lb_couple_step(lb_ctx* c, int32_t n_steps) {
   if (!c) return fail(nullptr, LB_EINVAL, "context is NULL");
   if (n_steps < 0) return fail(c, LB_EINVAL, "n_steps must be >= 0");
   if (n_steps == 0) return LB_OK;
+  if (c->p.n_atoms > 0 && c->geo.fused) return couple_step_fused(c, n_steps);
+  if (graph_eligible(c, n_steps)) return couple_steps_graph(c, n_steps);
+  return couple_steps_eager(c, n_steps);
+}
+
+// the unfused step, every launch and event enqueued by the host
+static lb_status couple_steps_eager(lb_ctx* c, int32_t n_steps) {
   const bool atoms = c->p.n_atoms > 0;
-  if (atoms && c->geo.fused) return couple_step_fused(c, n_steps);
   hipError_t e;
   // Two streams (the caller's "main" stream and "atoms").  Step n:
   //   main:   wait ev_bin(n); node u_c, couple (-> ev_couple); spread -> ev_spread; sweep
@@ -1038,7 +1106,12 @@ restore:
 lb_status lb_destroy(lb_ctx* c) {
   if (!c) return fail(nullptr, LB_EINVAL, "context is NULL");
   free_events(c);
-  for (hipStream_t s : {c->astream, c->hstream})
+  if (c->gexec[0] || c->gexec[1]) {
+    (void)hipStreamSynchronize(c->stream);
+    for (hipGraphExec_t g : c->gexec)
+      if (g) (void)hipGraphExecDestroy(g);
+  }
+  for (hipStream_t s : {c->astream, c->hstream, c->gstream})
     if (s && s != c->stream) {
       (void)hipStreamSynchronize(s);
       (void)hipStreamDestroy(s);

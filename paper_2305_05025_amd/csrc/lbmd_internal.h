@@ -195,6 +195,10 @@ struct lb_ctx {
   // by step parity (a wait refers to the previous step's record while this step's is queued)
   hipStream_t hstream = nullptr;
   hipEvent_t ev_hot[2] = {nullptr, nullptr}, ev_cold[2] = {nullptr, nullptr};
+  // LB_FLAG_STEP_GRAPHS: the two-step graph of each starting parity (built on first use) and
+  // the stream it is captured on
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  hipStream_t gstream = nullptr;
   // optional per-phase event timing (lb_timing_begin / lb_timing_end)
   std::vector<hipEvent_t> ev;  // kTimedEvents per timed step
   int timed_cap = 0;
