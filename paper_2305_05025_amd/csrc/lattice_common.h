@@ -19,6 +19,8 @@ struct Store<LB_STORE_F32> {
   template <class P>
   static __device__ __forceinline__ float ld(const P* p) { return *p; }
   template <class P>
+  static __device__ __forceinline__ float ld_nt(const P* p) { return __builtin_nontemporal_load(p); }
+  template <class P>
   static __device__ __forceinline__ void st(P* p, float v) { __builtin_nontemporal_store(v, p); }
 };
 
@@ -27,6 +29,8 @@ struct Store<LB_STORE_F16> {
   using T = _Float16;
   template <class P>
   static __device__ __forceinline__ float ld(const P* p) { return (float)*p; }
+  template <class P>
+  static __device__ __forceinline__ float ld_nt(const P* p) { return (float)__builtin_nontemporal_load(p); }
   // conversion to binary16 rounds to nearest even; subnormals are kept
   template <class P>
   static __device__ __forceinline__ void st(P* p, float v) {
@@ -40,6 +44,10 @@ struct Store<LB_STORE_BF16> {
   template <class P>
   static __device__ __forceinline__ float ld(const P* p) {
     return __uint_as_float((uint32_t)(*p) << 16);
+  }
+  template <class P>
+  static __device__ __forceinline__ float ld_nt(const P* p) {
+    return __uint_as_float((uint32_t)__builtin_nontemporal_load(p) << 16);
   }
   // conversion by the hardware (v_cvt_pk_bf16_f32): round to nearest even, NaN stays NaN
   template <class P>
@@ -78,8 +86,11 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* plane_at(T* f, i
 
 // ---- pull gather: pre-collision values at (x, y, z) -----------------------------------------
 // Q = 19 or 27 velocities (the default 19 is the D3Q19 set of Eq. 1).  `narrow`: the
-// lattice's planes fit 32-bit byte offsets (uniform across the launch).
-template <int ST, int Q = 19>
+// lattice's planes fit 32-bit byte offsets (uniform across the launch).  NT: the loads are
+// non-temporal (the sweep reads every stored value exactly once, so keeping its lines in L2
+// only displaces the data of the kernels that run beside it; gathers at scattered nodes,
+// whose neighbouring rows share lines, keep the default).
+template <int ST, int Q = 19, bool NT = false>
 __device__ __forceinline__ void gather(const typename Store<ST>::T* __restrict__ f, long plane,
                                        int x, int y, int z, int nx, int ny, int nz, bool narrow,
                                        float g[Q]) {
@@ -94,8 +105,10 @@ __device__ __forceinline__ void gather(const typename Store<ST>::T* __restrict__
     const uint32_t Y3[3] = {E * nx * ym, E * nx * y, E * nx * yp};
     const uint32_t Z3[3] = {E * nxy * zm, E * nxy * z, E * nxy * zp};
 #pragma unroll
-    for (int i = 0; i < Q; ++i)
-      g[i] = Store<ST>::ld(plane_at(f, i, plane, X3[1 - CX[i]] + Y3[1 - CY[i]] + Z3[1 - CZ[i]]));
+    for (int i = 0; i < Q; ++i) {
+      const auto* p = plane_at(f, i, plane, X3[1 - CX[i]] + Y3[1 - CY[i]] + Z3[1 - CZ[i]]);
+      g[i] = NT ? Store<ST>::ld_nt(p) : Store<ST>::ld(p);
+    }
   } else {
     const int X3[3] = {xm, x, xp};
     const int Y3[3] = {ym * nx, y * nx, yp * nx};
@@ -103,7 +116,8 @@ __device__ __forceinline__ void gather(const typename Store<ST>::T* __restrict__
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const int src = X3[1 - CX[i]] + Y3[1 - CY[i]] + Z3[1 - CZ[i]];
-      g[i] = Store<ST>::ld(f + (size_t)i * plane + src);
+      const auto* p = f + (size_t)i * plane + src;
+      g[i] = NT ? Store<ST>::ld_nt(p) : Store<ST>::ld(p);
     }
   }
 }

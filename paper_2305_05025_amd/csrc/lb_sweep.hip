@@ -44,6 +44,12 @@ struct SweepArgs {
   float omega_m;               // rate of the odd part (TRT instances only)
   FastDiv dnx, dny;
   int narrow;                  // planes take 32-bit byte offsets
+  // Non-temporal population loads: every stored value is read exactly once per sweep, and
+  // when a workgroup's sites are whole rows (nx divides kSweepBlock) its x-shifted reads share
+  // no cache line with another workgroup's, so keeping the lines would only displace the data
+  // of the kernels that run beside the sweep.  Rows that straddle workgroups (which run on
+  // different XCDs) share a line at each boundary, and a line not kept is then fetched twice.
+  int nt_loads;
 };
 
 // The update of site s = (x, y, z): pull its pre-collision values, add the coupling force
@@ -54,8 +60,12 @@ __device__ __forceinline__ void update_site(const SweepArgs& a, int s, int x, in
                                             bool coupled, float Fcx, float Fcy, float Fcz) {
   using T = typename Store<ST>::T;
   float g[Q];
-  gather<ST, Q>(reinterpret_cast<const T*>(a.fin), a.plane, x, y, z, a.nx, a.ny, a.nz,
-                a.narrow != 0, g);
+  if (a.nt_loads)
+    gather<ST, Q, true>(reinterpret_cast<const T*>(a.fin), a.plane, x, y, z, a.nx, a.ny, a.nz,
+                        a.narrow != 0, g);
+  else
+    gather<ST, Q, false>(reinterpret_cast<const T*>(a.fin), a.plane, x, y, z, a.nx, a.ny, a.nz,
+                         a.narrow != 0, g);
   float Fx, Fy, Fz;
   external_force(a.bf_kind, a.fext_tab, a.fext_field, a.plane, s, y, Fx, Fy, Fz);
   if (coupled) {
@@ -609,6 +619,7 @@ hipError_t launch_sweep(lb_ctx* c, const void* fin, void* fout, hipStream_t st) 
   a.dnx = g.div_nx;
   a.dny = g.div_ny;
   a.narrow = g.narrow ? 1 : 0;
+  a.nt_loads = kSweepBlock % g.nx == 0 ? 1 : 0;
   const dim3 block(kSweepBlock), grid(g.nblocks);
   const bool noise = c->p.kT > 0.0f, trt = c->p.trt_magic > 0.0f;
   switch (c->p.storage) {
@@ -662,6 +673,7 @@ SweepArgs sweep_args(lb_ctx* c, const void* fin, void* fout) {
   a.dnx = g.div_nx;
   a.dny = g.div_ny;
   a.narrow = g.narrow ? 1 : 0;
+  a.nt_loads = 0;   // hot bricks share lines at every brick face
   return a;
 }
 
