@@ -88,7 +88,8 @@ def cpu_baseline(k: int):
     """The CPU oracle on a bounded sample of the workload: coupled steps of one eighth of the
     lattice (half the extent per axis) holding one 20,000-atom globule of the same
     construction and parameters, so the sample has the workload's mix of sites and atoms.  A
-    10-step probe sizes the timed run to about 10 s of the host's work (10 to 400 steps).
+    10-step probe (allocation included, so it overestimates a step) sizes the timed run to
+    about 15-20 s of the host's work (10 to 400 steps).
     Reported as site updates per second.  Beside it, the oracle on two whole workloads: the
     32^3 tethered ball over its 100 steps and the first 20 of the 96^3 differentiation
     workload's 200 steps."""
@@ -107,7 +108,7 @@ def cpu_baseline(k: int):
                           bf_kind=0 if w.bf_kind == 3 else w.bf_kind, bf_amp=w.bf_amp,
                           mass=w.mass)
     probe = oracle_timing(ws, 10) / 10
-    steps = int(min(400, max(10, round(10.0 / probe))))
+    steps = int(min(400, max(10, round(20.0 / probe))))
     dt = oracle_timing(ws, steps)
     others = []
     for kk, n in ((0, 100), (3, 20)):

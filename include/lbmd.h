@@ -112,10 +112,10 @@ typedef enum {
                                       hold the context's buffer addresses and are released by
                                       lb_destroy.  Measured on MI355X it is not faster than the
                                       best eager schedule at any size (ms per step, graphs
-                                      against eager: 32^3 with 500 atoms 0.054 against 0.075
-                                      with two streams and 0.051 with one; 96^3 0.082 against
-                                      0.076; 128^3 0.121 against 0.110; 256^3 0.606 against
-                                      0.562): small lattices are bound by the dependent kernels'
+                                      against eager two-stream: 32^3 with 500 atoms 0.054
+                                      against 0.065, and 0.051 eager on one stream; 96^3 0.082
+                                      against 0.075; 128^3 0.119 against 0.108; 256^3 0.591
+                                      against 0.548): small lattices are bound by the dependent kernels'
                                       dispatch latency on the GPU, which a graph keeps, and the
                                       replay overlaps the atom and lattice work less.  It is for
                                       callers that launch the step from graphs of their own */
