@@ -53,16 +53,30 @@ def oracle_run(O, w, steps, g0=None, precision="f64"):
                 inv=O.invariants(p, g1, V1))
 
 
+def max_rel(a, b):
+    """Element by element: max |a - b| over max |b| (a wrong value at a few sites or atoms
+    shows here even where it would vanish in a norm over the whole field)."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    mb = np.abs(b).max() if b.size else 0.0
+    return float(np.abs(a - b).max() / (mb if mb > 0 else 1.0)) if b.size else 0.0
+
+
 def compare(gp, orc, w):
-    """rel. L2 errors.  The density deviation is compared through the populations g (its
+    """rel. L2 errors, and element-by-element errors (keys ending in _max: max |GPU - oracle|
+    over max |oracle|).  The density deviation is compared through the populations g (its
     exact carrier); rho itself comes back as FP32 absolute density, whose rounding near rho0
     (2^-24 relative) is compared as such.  Atom displacement is the library's integrated
     X - x0; the unwrapped FP32 positions are compared at their own resolution."""
     r = dict(u=rel_l2(gp["u"], orc["u"]),
              rho=rel_l2(gp["rho"], orc["rho"]),
-             g=rel_l2(gp["g"], orc["g"]))
+             g=rel_l2(gp["g"], orc["g"]),
+             u_max=max_rel(gp["u"], orc["u"]),
+             g_max=max_rel(gp["g"], orc["g"]))
     if w.n_atoms:
         r["disp"] = rel_l2(gp["d"], orc["d"])
         r["v"] = rel_l2(gp["v"], orc["v"])
         r["x"] = rel_l2(gp["x"], orc["x"])
+        r["disp_max"] = max_rel(gp["d"], orc["d"])
+        r["v_max"] = max_rel(gp["v"], orc["v"])
     return r
