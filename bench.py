@@ -304,7 +304,7 @@ def run(args):
         "data": "synthetic",
         "config": {"workload": w.name, "lattice": list(w.L), "atoms": w.n_atoms,
                    "storage": args.storage, "tau": w.tau, "steps_per_call": args.steps,
-                   "streams": 1 if args.single_stream else 2, "graphs": bool(args.graphs)},
+                   "streams": streams_used(w, args.single_stream), "graphs": bool(args.graphs)},
         "hbm_gbs_step": round(step_gbs, 1),
         "hbm_frac_step": round(step_gbs / HBM_PEAK_GBS, 4),
         # summed durations of the atom-side kernel chains (binning, coupling, cell sort +
@@ -341,6 +341,15 @@ def calibrate_copy(args):
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_each_way": 4 * n, "launches": args.steps}), flush=True)
+
+
+def streams_used(w, single_stream):
+    """The library's schedule: the atom work gets a stream of its own unless asked not to, or
+    the lattice is small enough that fewer host calls win (LB_ONE_STREAM_MAX_SITES)."""
+    from paper_2305_05025_amd import _abi as A
+    sites = w.L[0] * w.L[1] * w.L[2]
+    small = sites <= A.LB_ONE_STREAM_MAX_SITES and "LBMD_OVERLAP_SMALL" not in os.environ
+    return 1 if single_stream or small or w.n_atoms == 0 else 2
 
 
 def main():

@@ -84,9 +84,13 @@ typedef enum {
                                       library runs the force field, the integration and the
                                       next step's binning on a stream of its own, where
                                       they overlap the lattice sweep.  Both give identical
-                                      bits.  For lattices of about 32^3 sites and below the
-                                      step is bound by the host's launch and event calls,
-                                      and this schedule (fewer calls) is the faster one */
+                                      bits.  Lattices of at most LB_ONE_STREAM_MAX_SITES
+                                      sites always run this schedule: their step is bound
+                                      by the host's launch and event calls, and it makes
+                                      fewer (32^3 with 500 atoms on MI355X: 0.050 ms per
+                                      step against 0.055-0.077 for two streams; from about
+                                      2^16 sites on, two streams are as fast or faster) */
+#define LB_ONE_STREAM_MAX_SITES 32768u
 #define LB_FLAG_FUSED_COUPLING 0x4u /* couple in the sweep itself: every 16 x 4 x 4 brick of sites
                                       that an atom stencil touches is updated by one workgroup
                                       that first computes the coupling velocity on the brick and

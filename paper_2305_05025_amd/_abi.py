@@ -17,6 +17,8 @@ LB_STORE_F32, LB_STORE_F16, LB_STORE_BF16 = 0, 1, 2
 LB_BF_NONE, LB_BF_KOLMOGOROV, LB_BF_SIGN_SHEAR, LB_BF_FIELD = 0, 1, 2, 3
 LB_FLAG_CHECK_FINITE = 0x1
 LB_FLAG_SINGLE_STREAM = 0x2
+# lattices of at most this many sites always run on the caller's stream alone
+LB_ONE_STREAM_MAX_SITES = 32768
 LB_FLAG_FUSED_COUPLING = 0x4
 LB_FLAG_STEP_GRAPHS = 0x8
 

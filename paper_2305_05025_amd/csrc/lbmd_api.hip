@@ -39,6 +39,8 @@ bool geometry(const lb_params* p, Geometry* g) {
   g->late_forces = std::getenv("LBMD_LATE_FORCES") != nullptr ||
                    (g->S >= (1L << 23) && sweep_bytes >= 7168.0 * (double)p->n_atoms);
   g->fused = (p->flags & LB_FLAG_FUSED_COUPLING) != 0 && p->n_atoms > 0;
+  g->overlap = p->n_atoms > 0 && !(p->flags & LB_FLAG_SINGLE_STREAM) &&
+               (g->S > (long)LB_ONE_STREAM_MAX_SITES || std::getenv("LBMD_OVERLAP_SMALL") != nullptr);
   g->ncell = 0;
   for (int k = 0; k < 3; ++k) {
     g->nc[k] = 0;
@@ -369,7 +371,7 @@ lb_status lb_init(const lb_params* p, void* workspace, size_t workspace_bytes, c
     return hip_fail(nullptr, e, "synchronising after set-up");
   }
   c->astream = st;
-  if (N > 0 && !(p->flags & LB_FLAG_SINGLE_STREAM)) {
+  if (g.overlap) {
     // atom work that overlaps the sweep runs on one more stream (default priority).  The
     // events inside a step are waited on only by this device's kernels, so they release at
     // device scope (no system-scope fence; about 4 us less per step); the fork and join with

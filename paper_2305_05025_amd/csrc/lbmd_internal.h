@@ -159,6 +159,11 @@ struct Geometry {
   // cold sweep; otherwise the coupling velocity, friction and spread run as separate kernels
   // before one sweep over every site.  Both give the same bits.
   bool fused;
+  // The atom work runs on a stream of its own beside the lattice stream: atoms present, no
+  // LB_FLAG_SINGLE_STREAM, and more than LB_ONE_STREAM_MAX_SITES sites.  The environment
+  // variable LBMD_OVERLAP_SMALL (any value) at context creation lifts the size limit, so the
+  // two schedules can be compared on small lattices.
+  bool overlap;
 };
 
 bool geometry(const lb_params* p, Geometry* g);

@@ -28,6 +28,17 @@ def test_library_exports_every_declared_symbol():
     assert set(names) <= bound, set(names) - bound
 
 
+def test_binding_constants_match_the_header():
+    """Every constant the header defines (status codes, storage formats, body-force kinds,
+    flags, the one-stream lattice limit) has the same value in the Python binding."""
+    src = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "lbmd.h")).read(), flags=re.S)
+    consts = {n: int(v, 0) for n, v in re.findall(r"#define\s+(LB_[A-Z0-9_]+)\s+(0x[0-9a-fA-F]+|\d+)u?\b", src)}
+    consts.update({n: int(v) for n, v in re.findall(r"\b(LB_[A-Z0-9_]+)\s*=\s*(\d+)", src)})
+    assert {"LB_OK", "LB_EOVERFLOW", "LB_BF_FIELD", "LB_FLAG_STEP_GRAPHS", "LB_ONE_STREAM_MAX_SITES"} <= set(consts)
+    for n, v in consts.items():
+        assert getattr(A, n) == v, (n, getattr(A, n, None), v)
+
+
 def test_velocity_set_matches_oracle_ordering(O):
     c, w = A.lb_velocity_set()
     co, wo = O.velocity_set()

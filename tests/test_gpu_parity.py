@@ -258,6 +258,35 @@ def test_single_stream_schedule_is_bitwise_identical(O):
             assert (a == b).all()
 
 
+def test_small_lattice_one_stream_default_is_bitwise_identical(O):
+    """A lattice of at most LB_ONE_STREAM_MAX_SITES sites (the 32^3 ball) runs on one stream by
+    default; with LBMD_OVERLAP_SMALL it takes the two-stream schedule.  Both give identical
+    bits, and the default matches the oracle."""
+    import os
+    from paper_2305_05025_amd import _abi as A
+    from paper_2305_05025_amd.coupled import CoupledLB
+    w = _c0()
+    assert int(np.prod(w.L)) <= A.LB_ONE_STREAM_MAX_SITES
+    outs = []
+    for overlap in (False, True):
+        if overlap:
+            os.environ["LBMD_OVERLAP_SMALL"] = "1"
+        try:
+            sim = CoupledLB.from_workload(w)
+        finally:
+            os.environ.pop("LBMD_OVERLAP_SMALL", None)
+        sim.step(12)
+        g = sim.populations()
+        _, _, x, v = sim.read_fields()
+        outs.append((g, x, v))
+        sim.close()
+    for a, b in zip(outs[0], outs[1]):
+        assert (a == b).all()
+    r = compare(gpu_run(w, 12), oracle_run(O, w, 12), w)
+    say("c0 12 steps, one stream", r)
+    assert max(r.values()) < 1e-5, r
+
+
 def test_error_paths_on_device():
     import torch
     from paper_2305_05025_amd import _abi as A
