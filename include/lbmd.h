@@ -98,12 +98,12 @@ typedef enum {
                                       force (staged in LDS), on a stream of its own beside the
                                       sweep of the other sites.  Same bits as the default, which
                                       runs the coupling as separate kernels before one sweep.  On
-                                      MI355X the default is faster from 96^3 sites up (256^3 with
-                                      200,000 atoms: 0.568 against 0.567 ms in FP32, 0.364 against
-                                      0.408 in FP16; 384^3 with 10^6 atoms 2.13 against 2.44);
-                                      this one for small lattices bound by the host's launch
-                                      rate (32^3 with 500 atoms: 0.080 against 0.088 ms).  Needs
-                                      lb_workspace_bytes() for these flags */
+                                      MI355X the default is as fast or faster at every size
+                                      measured (256^3 with 200,000 atoms: 0.568 against 0.567 ms
+                                      in FP32, 0.364 against 0.408 in FP16; 384^3 with 10^6 atoms
+                                      2.13 against 2.44; 32^3 with 500 atoms, both on one stream:
+                                      0.050 against 0.067-0.073).  Needs lb_workspace_bytes() for
+                                      these flags */
 #define LB_FLAG_STEP_GRAPHS 0x8u    /* replay the step from a HIP graph: the first call that starts
                                       at an even (odd) step captures the launches and events of
                                       two steps, and every call of two or more steps replays it,
@@ -117,7 +117,8 @@ typedef enum {
                                       lb_destroy.  Measured on MI355X it is not faster than the
                                       best eager schedule at any size (ms per step, graphs
                                       against eager two-stream: 32^3 with 500 atoms 0.054
-                                      against 0.065, and 0.051 eager on one stream; 96^3 0.082
+                                      against 0.065, and 0.051 eager on one stream, the default
+                                      there; 96^3 0.082
                                       against 0.075; 128^3 0.119 against 0.108; 256^3 0.591
                                       against 0.548): small lattices are bound by the dependent kernels'
                                       dispatch latency on the GPU, which a graph keeps, and the
