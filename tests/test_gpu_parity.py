@@ -139,6 +139,20 @@ def test_config0_100_steps(O):
     assert r["v"] < 6.0 * spread["v"], (r["v"], spread["v"])
 
 
+def test_paper_coupling_rate_tethered_ball(O):
+    """The friction at the paper's own rate, gamma dt / m = 0.2 per step (unit mass; the
+    benchmark workloads use m = 32 for their Lennard-Jones packings): 200 tethered atoms without
+    Lennard-Jones, stable at m = 1, dragged by a Kolmogorov flow over 50 steps.  The atoms'
+    initial velocities relax towards the fluid's within a few steps, so every atom velocity is
+    set by the interpolated fluid velocity and the two-way coupling."""
+    from workloads import small_workload
+    w = small_workload((24, 22, 20), 200, seed=13, tau=0.7, gamma=0.2, k_tether=0.05, lj=False, mass=1.0,
+                       bf_kind=1, bf_amp=1e-4)
+    r = compare(gpu_run(w, 50), oracle_run(O, w, 50), w)
+    say("gamma/m = 0.2, tethered ball, 50 steps", r)
+    assert max(r.values()) < 1e-5, r
+
+
 # ------------------------------------------------------------------ coupled: globules
 
 def _globule(L=(40, 36, 30), n=1500, bf=1, seed=6):
