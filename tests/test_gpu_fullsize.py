@@ -1,11 +1,13 @@
 """Parity at the full sizes of all five workloads (32^3 tethered ball, 128^3 globule with
 Kolmogorov forcing, 256^3 with ten globules, 96^3 globule with a body-force field, 384^3 with
-fifty globules and sign-shear forcing), in the launch configuration bench.py times (three
-streams, FP32 storage): one coupled step from a seeded random lattice state and the
+fifty globules and sign-shear forcing), in the launch configuration bench.py times (two
+streams, one for the 32^3 ball, whose lattice is small enough to run on one; FP32 storage): one coupled step from a seeded random lattice state and the
 workload's atoms, compared with the oracle on sampled outputs it computes one by one
 (populations at sampled sites, half of them on atom stencils; positions and velocities of
 sampled atoms).  Rel. L2 over the samples <= 1e-5, and element by element
-max |GPU - oracle| / max |oracle| <= 1e-5."""
+max |GPU - oracle| / max |oracle| <= 1e-5.  The 256^3 workload is also checked with thermal
+noise at the benchmark's kT = 1e-4, so that the noise generator's counter, keyed by site and
+step, is compared at 16.7M sites."""
 import numpy as np
 import pytest
 
@@ -28,12 +30,23 @@ def _sample_sites(rng, w, n_random, n_near):
 
 @pytest.mark.parametrize("config", [0, 1, 2, 3, 4])
 def test_one_step_full_size_sampled(O, config):
-    import torch
-    from paper_2305_05025_amd.coupled import CoupledLB
     from workloads import make_workload
     say("full-size sampled parity: building workload", config)
-    w = make_workload(config)
-    rng = np.random.default_rng(100 + config)
+    _one_step_sampled(O, make_workload(config), 100 + config)
+
+
+def test_one_step_full_size_sampled_thermal(O):
+    """The 256^3 workload with the fluctuating lattice of the benchmark's thermal leg."""
+    import dataclasses
+    from workloads import make_workload
+    say("full-size sampled parity, thermal: building workload 2")
+    _one_step_sampled(O, dataclasses.replace(make_workload(2), kT=1e-4, noise_seed=7), 205)
+
+
+def _one_step_sampled(O, w, seed):
+    import torch
+    from paper_2305_05025_amd.coupled import CoupledLB
+    rng = np.random.default_rng(seed)
     shape = (19, w.L[2], w.L[1], w.L[0])
     say("  random lattice state", shape)
     g0 = rng.standard_normal(size=shape, dtype=np.float32)
