@@ -301,6 +301,40 @@ def test_small_lattice_one_stream_default_is_bitwise_identical(O):
     assert max(r.values()) < 1e-5, r
 
 
+def test_contexts_interleaved_on_their_own_streams():
+    """Three contexts at once, each on a caller stream of its own, their calls interleaved with no
+    synchronisation between them: two of the 48 x 44 x 40 globule (two-stream schedule, each
+    with its own atom stream and events) and the 32^3 ball (one stream).  Each ends with the
+    bits of the same steps run alone on the default stream."""
+    import torch
+    from paper_2305_05025_amd.coupled import CoupledLB
+    wa, wb = _globule(n=4000, L=(48, 44, 40)), _c0()
+
+    def state(sim):
+        g = sim.populations()
+        _, _, x, v = sim.read_fields()
+        return g, x, v
+
+    def alone(w, n):
+        sim = CoupledLB.from_workload(w)
+        sim.step(n)
+        out = state(sim)
+        sim.close()
+        return out
+
+    sims = [CoupledLB.from_workload(w, stream=torch.cuda.Stream()) for w in (wa, wa, wb)]
+    for calls in ((3, 2, 4), (5, 6, 2), (4, 4, 0)):
+        for sim, n in zip(sims, calls):
+            sim.step(n)
+    outs = [state(sim) for sim in sims]
+    for sim in sims:
+        sim.close()
+    ref_a, ref_b = alone(wa, 12), alone(wb, 6)
+    for out, ref in zip(outs, (ref_a, ref_a, ref_b)):
+        for a, b in zip(out, ref):
+            assert (a == b).all()
+
+
 def test_error_paths_on_device():
     import torch
     from paper_2305_05025_amd import _abi as A
