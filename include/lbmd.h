@@ -291,7 +291,8 @@ size_t lb_adjoint_workspace_bytes(const lb_ctx* c, int32_t k);
  * dL_db     device [3][nz][ny][nx] out (FP32): dL/dF_ext summed over the steps, or NULL
  * dL_dX0, dL_dv0  device [N][3] out, or NULL: dL/dX and dL/dv at the first checkpoint's step
  *           (positions taken with the tether anchors held fixed)
- * Everything runs on the context's stream; the call synchronises before returning.  The
+ * The work is queued on the context's stream (and, for a two-stream context, on its atom
+ * stream, forked from and joined with it); the call synchronises before returning.  The
  * context's state is restored to the one before the call.  Rounding of FP16/BF16 storage is
  * treated as the identity. */
 lb_status lb_backward(lb_ctx* c, const void* ckpts, int32_t n_steps, int32_t k, void* adj_ws,

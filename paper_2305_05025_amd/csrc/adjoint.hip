@@ -283,7 +283,7 @@ struct AdjAtomArgs {
   const float* phi;
   const float* lx_in;
   const float* lv_in;
-  float* lx_out;      // holds lx_in + H v'/m on entry
+  float* lxa;         // out: the coupling's part of dL/dX^n (added to lx_out by k_adj_addx)
   float* lv_out;
   float* lU;
   float4* lf;         // k_adj_dir: v'/m per atom
@@ -353,12 +353,19 @@ __global__ __launch_bounds__(256) void k_adj_atoms(AdjAtomArgs a) {
       a.lU[3 * i + c] = lu[c];
       a.lv_out[3 * i + c] = vp[c] - lu[c];
     }
-    a.lx_out[3 * i] += gx + M[0][0] * lu[0] + M[0][1] * lu[1] + M[0][2] * lu[2];
-    a.lx_out[3 * i + 1] += gy + M[1][0] * lu[0] + M[1][1] * lu[1] + M[1][2] * lu[2];
-    a.lx_out[3 * i + 2] += gz + M[2][0] * lu[0] + M[2][1] * lu[1] + M[2][2] * lu[2];
+    a.lxa[3 * i] = gx + M[0][0] * lu[0] + M[0][1] * lu[1] + M[0][2] * lu[2];
+    a.lxa[3 * i + 1] = gy + M[1][0] * lu[0] + M[1][1] * lu[1] + M[1][2] * lu[2];
+    a.lxa[3 * i + 2] = gz + M[2][0] * lu[0] + M[2][1] * lu[1] + M[2][2] * lu[2];
   }
   const double b = block_sum(dg);
   if (threadIdx.x == 0) a.dg_part[blockIdx.x] = b;
+}
+
+// dL/dX^n = (dL/dX^{n+1} + H v'/m, the force field's Hessian-vector product) + the coupling's
+// part (k_adj_atoms), one value per thread
+__global__ __launch_bounds__(256) void k_adj_addx(float* lx_out, const float* lxa, int n3) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j < n3) lx_out[j] += lxa[j];
 }
 
 // dL/du_c at every site of the flagged tiles: the transpose of the interpolation applied to
@@ -575,7 +582,7 @@ static AdjAtomArgs atom_args(lb_ctx* c, const AdjointBuffers& b) {
   a.phi = b.phi;
   a.lx_in = b.lx_in;
   a.lv_in = b.lv_in;
-  a.lx_out = b.lx_out;
+  a.lxa = b.lxa;
   a.lv_out = b.lv_out;
   a.lU = b.lU;
   a.lf = b.lf;
@@ -590,11 +597,18 @@ hipError_t launch_adjoint_step(lb_ctx* c, const AdjointBuffers& b) {
   const hipStream_t st = c->stream;
   const AdjAtomArgs aa = atom_args(c, b);
   const unsigned nab = adjoint_atom_blocks(c);
-  // 1. direction v'/m and the force-field Hessian-vector product: lx_out = lx_in + H v'/m
+  // 1. direction v'/m and the force-field Hessian-vector product: lx_out = lx_in + H v'/m.  The
+  // product needs only v'/m, the positions and the step's cell lists, and nothing after it
+  // reads lx_out until k_adj_addx: with a side stream it runs there beside steps 2-6.
   hipLaunchKernelGGL(k_adj_dir, dim3(nab), dim3(256), 0, st, aa);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if ((e = launch_force_hvp(c, b.lf, b.lx_in, b.lx_out)) != hipSuccess) return e;
+  const bool side = b.side != nullptr && b.side != st;
+  if (side && ((e = hipEventRecord(b.ev_fork, st)) != hipSuccess ||
+               (e = hipStreamWaitEvent(b.side, b.ev_fork, 0)) != hipSuccess))
+    return e;
+  if ((e = launch_force_hvp(c, b.lf, b.lx_in, b.lx_out, side ? b.side : st)) != hipSuccess) return e;
+  if (side && (e = hipEventRecord(b.ev_join, b.side)) != hipSuccess) return e;
   // 2. dL/dF on the flagged tiles
   const AdjLatticeArgs la = lattice_args(c, b);
   const dim3 tgrid(persistent_grid(g.ntiles)), blk(256);
@@ -654,6 +668,11 @@ hipError_t launch_adjoint_step(lb_ctx* c, const AdjointBuffers& b) {
   // 6. FP64 accumulators
   hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(kAdjRed), 0, st, (const double*)b.dg_part, (int)nab,
                      (const double*)b.dom_part, g.nblocks, b.acc);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // 7. dL/dX^n: the product (joined from the side stream) plus the coupling's part
+  if (side && (e = hipStreamWaitEvent(st, b.ev_join, 0)) != hipSuccess) return e;
+  const int n3 = 3 * c->p.n_atoms;
+  hipLaunchKernelGGL(k_adj_addx, dim3(blocks(n3, 256)), dim3(256), 0, st, b.lx_out, (const float*)b.lxa, n3);
   return hipGetLastError();
 }
 

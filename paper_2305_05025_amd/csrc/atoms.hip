@@ -1200,18 +1200,18 @@ hipError_t launch_forces(lb_ctx* c) {
   return hipGetLastError();
 }
 
-hipError_t launch_force_hvp(lb_ctx* c, const float4* lf, const float* lx_in, float* lx_out) {
+hipError_t launch_force_hvp(lb_ctx* c, const float4* lf, const float* lx_in, float* lx_out, hipStream_t st) {
   ForceArgs a = force_args(c);
   a.lf = lf;
   a.lx_in = lx_in;
   a.lx_out = lx_out;
   const dim3 grid(persistent_grid(std::min(a.ncell, (long)a.N)));
   if (a.ncell > 0 && a.coul2 != 0.f)
-    hipLaunchKernelGGL((k_forces_cells<true, true>), grid, dim3(256), 0, c->stream, a);
+    hipLaunchKernelGGL((k_forces_cells<true, true>), grid, dim3(256), 0, st, a);
   else if (a.ncell > 0)
-    hipLaunchKernelGGL((k_forces_cells<true, false>), grid, dim3(256), 0, c->stream, a);
+    hipLaunchKernelGGL((k_forces_cells<true, false>), grid, dim3(256), 0, st, a);
   else
-    hipLaunchKernelGGL(k_bonded_forces<true>, dim3(blocks(a.N, 256)), dim3(256), 0, c->stream, a);
+    hipLaunchKernelGGL(k_bonded_forces<true>, dim3(blocks(a.N, 256)), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

@@ -860,7 +860,7 @@ namespace {
 // final state, k state slots, k binning regions (one per step of a segment: the recomputed
 // forward step q bins into region q and its backward step reads it there), adjoint fields
 struct AdjLayout {
-  size_t final_state, slots, sets, set_bytes, lam[2], phi, luc, lU, lf, lx[2], lv[2], dg_part,
+  size_t final_state, slots, sets, set_bytes, lam[2], phi, luc, lU, lf, lx[2], lv[2], lxa, dg_part,
       dom_part, acc, total;
   Layout set;  // the context's layout with the binning offsets of one step's region
 };
@@ -889,6 +889,7 @@ AdjLayout plan_adjoint(const lb_ctx* c, int k) {
     l.lx[q] = take(12 * N);
     l.lv[q] = take(12 * N);
   }
+  l.lxa = take(12 * N);
   l.dg_part = take(8 * (size_t)adjoint_atom_blocks(c));
   l.dom_part = take(16 * (size_t)c->geo.nblocks);
   l.acc = take(24);
@@ -955,9 +956,11 @@ lb_status lb_backward(lb_ctx* c, const void* ckpts, int32_t n_steps, int32_t k, 
     c->bin = bin0;
   };
   lb_status st = LB_OK;
-  // every kernel of the backward pass runs in order on the caller's stream, and the forward
-  // steps are recomputed by the unfused kernels (the same bits), which leave the binning,
-  // coupling velocity, friction and spread force of each step in its region
+  // the forward steps are recomputed by the unfused kernels (the same bits), each a one-step
+  // call on the context's schedule, leaving the binning, coupling velocity, friction and
+  // spread force of each step in its region; the other kernels of the backward pass run on the
+  // caller's stream, except the force field's Hessian-vector product of each adjoint step,
+  // which a two-stream context runs on its atom stream beside the lattice part
   c->astream = c->stream;
   c->geo.fused = false;
   if ((st = lb_state_save(c, A + L.final_state)) != LB_OK) goto restore;
@@ -1002,7 +1005,9 @@ lb_status lb_backward(lb_ctx* c, const void* ckpts, int32_t n_steps, int32_t k, 
         use_set(q);
         c->couple_u = (float*)(set(q) + L.set.U);
         c->keep_coupling = true;
+        c->astream = as;
         st = lb_couple_step(c, 1);
+        c->astream = c->stream;
         c->keep_coupling = false;
         c->couple_u = nullptr;
         use_own();
@@ -1056,6 +1061,15 @@ lb_status lb_backward(lb_ctx* c, const void* ckpts, int32_t n_steps, int32_t k, 
         b.lv_in = (const float*)(A + L.lv[li]);
         b.lx_out = (float*)(A + L.lx[li ^ 1]);
         b.lv_out = (float*)(A + L.lv[li ^ 1]);
+        b.lxa = (float*)(A + L.lxa);
+        // the force field's Hessian-vector product beside the lattice part, on the atom
+        // stream of a two-stream context (whose per-step events the recompute, run on one
+        // stream here, leaves free)
+        if (as != c->stream) {
+          b.side = as;
+          b.ev_fork = c->ev_couple;
+          b.ev_join = c->ev_spread;
+        }
         e = launch_adjoint_step(c, b);
         use_own();
         if (e != hipSuccess) {

@@ -247,7 +247,7 @@ hipError_t launch_couple(lb_ctx* c);
 hipError_t launch_spread(lb_ctx* c);
 hipError_t launch_forces(lb_ctx* c);
 // adjoint: lx_out = lx_in + (d F_ff / d X)^T lf at the context's current positions
-hipError_t launch_force_hvp(lb_ctx* c, const float4* lf, const float* lx_in, float* lx_out);
+hipError_t launch_force_hvp(lb_ctx* c, const float4* lf, const float* lx_in, float* lx_out, hipStream_t st);
 hipError_t launch_integrate(lb_ctx* c);
 hipError_t launch_read_atoms(lb_ctx* c, float* x, float* v);
 
@@ -270,6 +270,11 @@ struct AdjointBuffers {
   const float* lv_in;    // [N][3] dL/dv^{n+1}
   float* lx_out;
   float* lv_out;
+  float* lxa;            // [N][3] the coupling's part of dL/dX^n (scratch of the step)
+  // the force field's Hessian-vector product runs on `side` beside the lattice part when it
+  // is set and differs from the context's stream, forked and joined with the two events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 unsigned adjoint_atom_blocks(const lb_ctx* c);
 // the adjoint of step c->step, with the context's forward buffers holding that step's

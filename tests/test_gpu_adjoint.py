@@ -67,6 +67,34 @@ def _dfields(rng, shape, n=2):
     return [rng.normal(0, 1.0, size=shape) for _ in range(n)]
 
 
+def test_adjoint_side_stream_is_bitwise_identical():
+    """In a two-stream context each adjoint step runs the force field's Hessian-vector product on
+    the atom stream beside its lattice part; on one stream it runs in order.  Both give the same
+    bits for every gradient (a 16^3 globule, whose default is one stream; LBMD_OVERLAP_SMALL
+    gives it two)."""
+    import os
+    from workloads import globule_workload
+    L = 16
+    w = globule_workload(L, 1, 200, seed=8, tau=0.7, gamma=0.15)
+    rng = np.random.default_rng(3)
+    field = rng.normal(0, 1e-6, size=(3, L, L, L))
+    D = rng.normal(size=3)
+    D /= np.linalg.norm(D)
+    outs = []
+    for overlap in (False, True):
+        if overlap:
+            os.environ["LBMD_OVERLAP_SMALL"] = "1"
+        try:
+            o, _ = _gpu_grads(w, field, D, 12, 5)
+        finally:
+            os.environ.pop("LBMD_OVERLAP_SMALL", None)
+        outs.append(o[0])
+    a, b = outs
+    assert a["gamma"] == b["gamma"] and a["tau"] == b["tau"], (a["gamma"], b["gamma"], a["tau"], b["tau"])
+    for key in ("body_force", "x0", "v0"):
+        assert bool((a[key] == b[key]).all()), key
+
+
 def test_adjoint_globule_with_lj_and_bonds(O):
     """One 60-atom globule (bonds + LJ) in a 10^3 box with a random body-force field;
     12 steps in segments of 5 (three segments, the last one shorter)."""
